@@ -1,0 +1,111 @@
+"""One Galilean PIC step in order, the stable tile sort and FP64 diagnostics
+(oracle side).
+
+Step k -> k+1 (tau^k = k dtau):
+  1. gather the level-k node fields, Higuera-Cary push u^{k-1/2} -> u^{k+1/2},
+     move r^k -> r^{k+1} along d zeta / d tau = v_z - 1      (push.py)
+  2. deposit J^{k+1/2} (Esirkepov frame current + rhobar)    (deposit.py)
+  3. drop particles that left at zeta < 0; append window batch k + 1
+  4. stable sort by tile key
+  5. binomial filter of J, transverse FFT, right-to-left march of the node
+     system with slow step Delta = dtau, inverse FFT         (fields.py)
+
+Tile key (reading; the paper keeps no particle order): tiles of
+T_x x T_y x T_zeta cells, key = (t_zeta * nT_y + t_y) * nT_x + t_x, sorted
+stably so particles of one tile keep their previous relative order; removed
+particles are dropped, new ones enter after all existing ones.
+"""
+import numpy as np
+
+from . import params as _params
+from .plasma import Particles, load_full_cells, inject_batch
+from .push import push_and_move
+from .deposit import deposit, deposit_rho, continuity_residual
+from .fields import (laser_state, real_fields, march, half_node_currents,
+                     binomial_filter)
+
+
+def tile_key(p, P):
+    nTx, nTy, _ = p.ntiles
+    tx = P.ix // p.tile[0]
+    ty = P.iy // p.tile[1]
+    tz = P.iz // p.tile[2]
+    return (tz * nTy + ty) * nTx + tx
+
+
+def stable_sort(p, P):
+    order = np.argsort(tile_key(p, P), kind="stable")
+    return P.take(order)
+
+
+class Simulation:
+    def __init__(self, cfg):
+        p = _params.from_config(cfg)
+        self.p = p
+        self.k = 0
+        P = Particles.concat(load_full_cells(p), inject_batch(p, 0))
+        P.pid = np.arange(len(P), dtype=np.int64)
+        self.next_pid = len(P)
+        self.P = stable_sort(p, P)
+        self.state = laser_state(p)
+        self.F = real_fields(p, self.state)
+        self.J = None
+        self.diag = None
+
+    @property
+    def tau(self):
+        return self.k * self.p.dtau
+
+    def step(self, diag=False):
+        p = self.p
+        P = self.P
+        if diag:
+            rho0 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
+        old, steps, vy = push_and_move(p, P, self.F)
+        new = (P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
+        Jx, Jy, Jz = deposit(p, old, new, steps, vy)
+        if diag:
+            rho1 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
+        P = P.take(P.iz >= 0)
+        B = inject_batch(p, self.k + 1)
+        B.pid = self.next_pid + np.arange(len(B), dtype=np.int64)
+        self.next_pid += len(B)
+        P = Particles.concat(P, B)
+        self.P = stable_sort(p, P)
+        self.J = (Jx, Jy, Jz)
+        fJ = [Jx, Jy, Jz]
+        for _ in range(p.filter_passes):
+            fJ = [binomial_filter(p, a) for a in fJ]
+        self.Jf = tuple(fJ)
+        jh = half_node_currents(p, *fJ)
+        self.state = march(p, self.state, jh, p.dtau)
+        self.F = real_fields(p, self.state)
+        self.k += 1
+        if diag:
+            self.diag = self.diagnostics(rho0, rho1)
+        return self
+
+    def run(self, n, diag=False):
+        for _ in range(n):
+            self.step(diag=diag)
+        return self
+
+    def diagnostics(self, rho0=None, rho1=None):
+        """FP64 diagnostics at the current level."""
+        p = self.p
+        V = p.hx * p.hy_eff * p.h
+        P = self.P
+        rho = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
+        F = self.F[:, :p.Nz]
+        d = dict(tau=self.tau, step=self.k, n_particles=len(P),
+                 charge_particles=p.q * p.w * len(P),
+                 charge_grid=float(np.sum(rho) * V),
+                 field_energy=float(0.5 * np.sum(F * F) * V),
+                 ez_axis=self.F[2, :p.Nz, p.Ny // 2, p.Nx // 2].copy())
+        if rho0 is not None:
+            r = continuity_residual(p, rho0, rho1, *self.J)
+            s = (rho1 - rho0) / p.dtau
+            ns = float(np.sqrt(np.sum(s * s)))
+            d["continuity_abs"] = float(np.sqrt(np.sum(r * r)))
+            d["continuity_rel"] = d["continuity_abs"] / ns if ns > 0 else 0.0
+        return d

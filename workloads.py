@@ -1,0 +1,89 @@
+"""Seeded synthetic workloads shared by the oracle tests, the GPU tests and bench.py.
+
+This module only holds parameter sets (plain numbers in the units the workload
+is stated in).  It contains none of the method's arithmetic: unit conversion,
+particle loading, random offsets and every other derived quantity are computed
+independently by the oracle (``oracle/``) and by the HIP library.
+
+Lengths and times are in laser wavelengths (lambda_L = 1, c = 1) unless
+``length_unit`` says otherwise; ``length_unit`` is the factor that turns them
+into the paper's normalised units c/omega_0 (2*pi for lambda_L units, 1 when
+the workload is already in c/omega_0).  Densities are in units of the critical
+density of omega_0 (so omega_p^2 = n_e).
+"""
+import math
+
+TWO_PI = 2.0 * math.pi
+
+
+def _base(**kw):
+    cfg = dict(
+        dims=3, n=[64, 64, 64], d=[0.4, 0.4, 0.05], length_unit=TWO_PI,
+        dtau=0.0,             # 0 -> half the zeta step
+        precision="fp32",     # "fp64" | "fp32" (cell+offset) | "fp32abs"
+        tile=[8, 8, 8],
+        n_e=0.0, ppc=[1, 1, 2], load=0,   # load 0 = stratified random, 1 = quiet lattice
+        a0=0.0, waist=0.0, fwhm=0.0, zeta_c=None, pol=0,
+        seed=0, filter_passes=1, steps=1,
+        beam=None,
+    )
+    cfg.update(kw)
+    return cfg
+
+
+def lwfa2d_fp64():
+    """2-D (x, zeta) LWFA, 64 x 256, dx = 0.25, dzeta = 0.05, n_e = 0.01, 2 ppc,
+    a0 = 1, FWHM 5, waist 4, laser centred at zeta = 200 dzeta; 100 steps, FP64."""
+    return _base(dims=2, n=[64, 1, 256], d=[0.25, 1.0, 0.05], precision="fp64",
+                 tile=[8, 1, 8], n_e=0.01, ppc=[1, 1, 2], a0=1.0, waist=4.0,
+                 fwhm=5.0, zeta_c=200 * 0.05, steps=100)
+
+
+def lwfa3d_fp32(ppc=(1, 1, 2), steps=1000):
+    """3-D LWFA, 256 x 256 x 512, dx = dy = 0.4, dzeta = 0.05, n_e = 0.001, 2 ppc
+    (67,108,864 electrons), a0 = 2, waist 8, FWHM 8; FP32 cell + offset."""
+    return _base(dims=3, n=[256, 256, 512], d=[0.4, 0.4, 0.05], precision="fp32",
+                 tile=[8, 8, 8], n_e=0.001, ppc=list(ppc), a0=2.0, waist=8.0,
+                 fwhm=8.0, zeta_c=None, steps=steps)
+
+
+def precision_study(mode):
+    """As lwfa3d_fp32 at 8 ppc (268,435,456 electrons), 200 steps, in one of the
+    three precision modes."""
+    c = lwfa3d_fp32(ppc=(2, 2, 2), steps=200)
+    c["precision"] = mode
+    return c
+
+
+def pwfa3d_fp32():
+    """3-D PWFA in plasma units: 512 x 512 x 1024, dx = dy = 0.1, dzeta = 0.05,
+    n_e = 1, 4 ppc, Gaussian driver sigma_r = 0.5, sigma_zeta = 1, peak 10 n_e,
+    gamma = 2000 with 0.1 % spread, 1e7 macro-particles; 500 steps."""
+    return _base(dims=3, n=[512, 512, 1024], d=[0.1, 0.1, 0.05], length_unit=1.0,
+                 precision="fp32", tile=[8, 8, 8], n_e=1.0, ppc=[1, 2, 2],
+                 steps=500,
+                 beam=dict(n_peak=10.0, sigma_r=0.5, sigma_z=1.0, gamma=2000.0,
+                           dgamma=2.0, np=10_000_000))
+
+
+def denoiser_lwfa(ppc=(1, 1, 1)):
+    """lwfa3d_fp32 at 1 ppc (the network's input) or 16 ppc (its reference)."""
+    return lwfa3d_fp32(ppc=ppc, steps=1000)
+
+
+def small3d(precision="fp64", n=(32, 32, 64), tile=(8, 8, 8), ppc=(1, 1, 2),
+            steps=4, a0=1.0, seed=3, n_e=0.01):
+    """Small 3-D LWFA-like case: several tiles in every direction, a laser strong
+    enough to move particles across cells, finishes in seconds on a CPU."""
+    return _base(dims=3, n=list(n), d=[0.4, 0.4, 0.05], precision=precision,
+                 tile=list(tile), n_e=n_e, ppc=list(ppc), a0=a0, waist=3.0,
+                 fwhm=1.5, zeta_c=None, steps=steps, seed=seed)
+
+
+CONFIGS = {
+    "lwfa2d_fp64": lwfa2d_fp64,
+    "lwfa3d_fp32": lwfa3d_fp32,
+    "precision_study": precision_study,
+    "pwfa3d_fp32": pwfa3d_fp32,
+    "denoiser_lwfa": denoiser_lwfa,
+}
