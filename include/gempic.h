@@ -1,0 +1,183 @@
+/* gempic.h -- C ABI of the MI355X (gfx950) Galilean PIC step.
+ *
+ * One step advances a plasma and its electromagnetic field by one slow step
+ * dtau in the Galilean coordinates (x, y, zeta = z - c t, tau = t) of
+ * Pukhov, Elkina & Wilson, "Galilean Electromagnetic Particle-in-Cell Code"
+ * (arXiv 2509.16793):
+ *   - field gather and relativistic push along the characteristics of the
+ *     transformed Vlasov equation, d zeta / d tau = v_z - c (Sec. 5, eq:Vlasov1
+ *     and its characteristics);
+ *   - charge-conserving deposition of the beam-particle current j = q n v with
+ *     macro-particle charge Q_b = q n h_x h_y h (Sec. 5.1);
+ *   - the semi-implicit FD-spectral field update: transverse Fourier transform
+ *     (Sec. 3.1), universal reduced system (eq:RxGu .. eq:EzGu), node scheme
+ *     RxN .. eqall marched from the right boundary (Sec. 4.1) with the analytic
+ *     node solution of App. B;
+ *   - moving-window injection of the fresh plasma the domain sweeps over
+ *     (Sec. 5.1; here every particle carries Q_b and is pushed in tau).
+ * Units are the paper's normalised ones (Sec. 3): c = 1, lengths in c/omega_0,
+ * fields in m c omega_0 / e, densities in units of the critical density.
+ *
+ * Conventions
+ *   - Every function returns a gempic_status (0 = success, negative = error);
+ *     nothing throws or aborts across this boundary.  gempic_last_error()
+ *     returns a human-readable reason for the last failure on a handle.
+ *   - The handle owns every device allocation it makes (hipMalloc).  Getters
+ *     copy into caller-owned buffers; no internal pointer escapes.
+ *   - All device work is enqueued on cfg.stream (a hipStream_t; NULL = the
+ *     legacy default stream).  Getters and gempic_step synchronise that stream
+ *     before returning.
+ *   - Thread-compatible, not thread-safe: one handle per host thread.
+ *   - After GEMPIC_EDEVICE, GEMPIC_ECFL, GEMPIC_ENUMERIC or GEMPIC_ECAPACITY the
+ *     handle is "failed": the particle/field state is undefined (a step may
+ *     have been applied partially) and only getters, gempic_last_error and
+ *     gempic_destroy are accepted.
+ */
+#ifndef GEMPIC_H
+#define GEMPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEMPIC_ABI_VERSION 1
+
+typedef struct gempic gempic_t;
+
+typedef enum {
+  GEMPIC_OK = 0,
+  GEMPIC_EINVAL = -1,     /* bad argument or configuration                         */
+  GEMPIC_ENOMEM = -2,     /* device allocation failed                              */
+  GEMPIC_EDEVICE = -3,    /* a HIP call failed                                     */
+  GEMPIC_ECFL = -4,       /* slow step too large / a particle crossed > 1 cell     */
+  GEMPIC_ENUMERIC = -5,   /* NaN or Inf in the state                               */
+  GEMPIC_ESTATE = -6,     /* call not allowed in the handle's state                */
+  GEMPIC_EABI = -7,       /* abi_version mismatch                                  */
+  GEMPIC_ECAPACITY = -8   /* particle buffer capacity exceeded                     */
+} gempic_status;
+
+typedef enum {
+  GEMPIC_FP64 = 0,        /* every particle and field quantity in FP64             */
+  GEMPIC_FP32_CELL = 1    /* int32 cell + FP32 offsets/momenta/fields; FP64 tau,
+                             window thresholds and diagnostics                    */
+} gempic_precision;
+
+/* Configuration.  Lengths and times in "config units": multiplied by
+ * length_unit they become c/omega_0 (length_unit = 2 pi for lengths given in
+ * laser wavelengths, 1 when already normalised). */
+typedef struct {
+  int32_t abi_version;      /* must equal GEMPIC_ABI_VERSION                            */
+  int32_t dims;             /* 2 = (x, zeta), 3 = (x, y, zeta)                          */
+  int32_t n[3];             /* Nx, Ny (ignored in 2-D), Nzeta: powers of two, >= 2      */
+  double  d[3];             /* hx, hy (ignored in 2-D), h (zeta step), config units     */
+  double  length_unit;      /* > 0                                                      */
+  double  dtau;             /* slow step, config units; 0 selects h / 2.  2 dtau > h or
+                               dtau * h > 4 / n_e is rejected with GEMPIC_ECFL          */
+  int32_t precision;        /* gempic_precision                                         */
+  int32_t tile[3];          /* particle tile in cells; must divide n; 2-D: tile[1] = 1  */
+  double  n_e;              /* electron density (units of the critical density); 0 = vacuum */
+  int32_t ppc[3];           /* macro-particles per cell along x, y, zeta (2-D: ppc[1]=1) */
+  int32_t load;             /* 0 = stratified random (SplitMix64), 1 = quiet lattice    */
+  double  a0;               /* laser amplitude; 0 = no laser                            */
+  double  waist;            /* 1/e field radius R, config units; 0 = plane wave         */
+  double  fwhm;             /* intensity FWHM duration, config units                    */
+  double  zeta_c;           /* pulse centre, config units; NaN = (Nzeta-1) h - 2 T      */
+  int32_t pol;              /* 0 = E along x, 1 = E along y                             */
+  uint64_t seed;
+  int32_t filter_passes;    /* binomial 1-2-1 passes per axis: 0, 1 or 2                */
+  int32_t track_ids;        /* 1: keep a per-particle id array (tests, checkpoints)     */
+  int32_t deposit_rho;      /* 1: also deposit charge (diagnostics: continuity, charge) */
+  void*   stream;           /* hipStream_t or NULL                                      */
+} gempic_config;
+
+/* FP64 diagnostics of the last step (filled by gempic_step when requested). */
+typedef struct {
+  double  tau;              /* slow time after the step                                  */
+  int64_t step;             /* steps done since creation                                 */
+  int64_t n_particles;      /* plasma macro-particles in the box                         */
+  double  charge_particles; /* q w N                                                     */
+  double  charge_grid;      /* sum of rho V over the grid (needs deposit_rho)            */
+  double  field_energy;     /* 1/2 sum (E^2 + B^2) V over the field nodes                */
+  double  continuity_rel;   /* ||(rho1-rho0)/dtau - D rhobar + D.J|| / ||(rho1-rho0)/dtau||
+                               of the raw deposit (needs deposit_rho)                    */
+} gempic_diag;
+
+/* Field selector bits for gempic_fields. */
+#define GEMPIC_EX  (1u << 0)
+#define GEMPIC_EY  (1u << 1)
+#define GEMPIC_EZ  (1u << 2)
+#define GEMPIC_BX  (1u << 3)
+#define GEMPIC_BY  (1u << 4)
+#define GEMPIC_BZ  (1u << 5)
+#define GEMPIC_JX  (1u << 6)   /* raw deposited currents of the last step, lab frame    */
+#define GEMPIC_JY  (1u << 7)
+#define GEMPIC_JZ  (1u << 8)
+#define GEMPIC_RHO (1u << 9)   /* charge density after the last push (deposit_rho = 1)  */
+
+/* Create a simulation: validates the configuration, allocates device memory,
+ * loads the plasma at tau = 0 and initialises the laser (Sec. 6, E_laser) as a
+ * pure forward wave.  *out = NULL on error (the reason is returned by
+ * gempic_last_error(NULL) until the next call). */
+int gempic_create(const gempic_config* cfg, gempic_t** out);
+
+/* Advance nsteps slow steps.  diag (nullable) receives the FP64 diagnostics
+ * of the last step; computing them adds reductions to that step only. */
+int gempic_step(gempic_t* g, int32_t nsteps, gempic_diag* diag);
+
+/* Copy the selected real-space fields, in bit order, each as one array of the
+ * handle's precision (double for GEMPIC_FP64, float otherwise):
+ *   E, B:   [Nzeta][Ny][Nx]            node (i, j, n) at (i hx, j hy, n h)
+ *   J, rho: [Nzeta + filter_passes + 7][Ny][Nx]; plane p holds node n = p - 2
+ *           (J_x at x index i is J_x(i + 1/2); J_y at y index j is J_y(j + 1/2)
+ *           in 3-D; J_z at plane p is J_z(n + 1/2)).
+ * on_device = 1: dst is device memory, else host memory.  dst_bytes too small
+ * gives GEMPIC_EINVAL. */
+int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size_t dst_bytes);
+
+/* Number of bytes gempic_fields needs for mask. */
+size_t gempic_fields_bytes(const gempic_t* g, uint32_t mask);
+
+/* Copy the plasma particles (structure of arrays, in the handle's sorted
+ * order): cell[i] = (iz * Ny + iy) * Nx + ix (int32); off = 3 planes of
+ * capacity entries (offset in [0,1) along x, y, zeta); u = 3 planes of
+ * capacity entries (momentum gamma v); id (nullable) = capacity int64 ids
+ * (needs track_ids).  Offsets and momenta are double for GEMPIC_FP64, float
+ * otherwise.  *count receives the particle count; GEMPIC_EINVAL if capacity
+ * is smaller (then nothing is copied). */
+int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, void* u,
+                     int64_t* id, size_t capacity, size_t* count);
+
+/* Replace the state (checkpoint restore and tests).  particles: count entries
+ * in the layout of gempic_particles (must be sorted by tile, stable order
+ * within a tile as a step leaves it); spectral: six arrays R_x, R_y, L_x,
+ * L_y, E_z, B_z of [Nzeta][Ny][Nx/2] complex (interleaved re, im) in the
+ * handle's precision: the transverse modes k_x = 2 pi i / (Nx hx),
+ * i = 0 .. Nx/2 - 1, and k_y = 2 pi fftfreq(Ny, hy) of the forward transform
+ * sum f exp(-i k.r).  step sets the step counter (tau = step * dtau).  Host
+ * memory.  ids (nullable) as in gempic_particles. */
+int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void* off,
+                     const void* u, const int64_t* id, size_t count, const void* spectral,
+                     size_t spectral_bytes);
+
+/* Overwrite the six real-space node fields the next push gathers from
+ * (E_x, E_y, E_z, B_x, B_y, B_z, each [Nzeta][Ny][Nx] in the handle's
+ * precision, host memory).  For tests that feed identical fields to the GPU
+ * push and to a reference; the spectral state is left unchanged. */
+int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes);
+
+/* Read the spectral state (same layout as gempic_set_state) into host memory. */
+int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes);
+
+void gempic_destroy(gempic_t* g);
+
+const char* gempic_strerror(int code);
+const char* gempic_last_error(const gempic_t* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEMPIC_H */

@@ -36,12 +36,13 @@ def cic_weights(d):
 def gather(p, P, F):
     """Interpolate the six node fields F[c] (shape (Nz+1, Ny, Nx)) to every
     particle.  Returns an array (6, N).  Sum order: zeta node outermost, then
-    y, then x; weight = (wx * wy) * wz."""
+    y, then x; weight = (wx * wy) * wz.  The arithmetic runs in the precision
+    of the inputs (FP64 normally; FP32 inputs reproduce an FP32 push)."""
     wx = cic_weights(P.dx)
     wz = cic_weights(P.dz)
     ix1 = (P.ix + 1) % p.Nx
     xs = (P.ix, ix1)
-    out = np.zeros((6, len(P)))
+    out = np.zeros((6, len(P)), dtype=np.result_type(F.dtype, P.dx.dtype))
     if p.dims == 3:
         wy = cic_weights(P.dy)
         ys = (P.iy, (P.iy + 1) % p.Ny)

@@ -61,6 +61,7 @@ class Simulation:
         P = self.P
         if diag:
             rho0 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
+        n_pushed = len(P)
         old, steps, vy = push_and_move(p, P, self.F)
         new = (P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
         Jx, Jy, Jz = deposit(p, old, new, steps, vy)
@@ -82,7 +83,7 @@ class Simulation:
         self.F = real_fields(p, self.state)
         self.k += 1
         if diag:
-            self.diag = self.diagnostics(rho0, rho1)
+            self.diag = self.diagnostics(rho0, rho1, n_pushed)
         return self
 
     def run(self, n, diag=False):
@@ -90,18 +91,22 @@ class Simulation:
             self.step(diag=diag)
         return self
 
-    def diagnostics(self, rho0=None, rho1=None):
-        """FP64 diagnostics at the current level."""
+    def diagnostics(self, rho0=None, rho1=None, n_pushed=None):
+        """FP64 diagnostics of the last step: particle count after the step;
+        charge of the pushed particles (q w N) and on the grid after the move
+        (sum rho V, all particles before removal); field energy
+        1/2 sum (E^2 + B^2) V over the field nodes; continuity residual of
+        the raw deposit; on-axis E_z."""
         p = self.p
         V = p.hx * p.hy_eff * p.h
         P = self.P
-        rho = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
         F = self.F[:, :p.Nz]
         d = dict(tau=self.tau, step=self.k, n_particles=len(P),
-                 charge_particles=p.q * p.w * len(P),
-                 charge_grid=float(np.sum(rho) * V),
                  field_energy=float(0.5 * np.sum(F * F) * V),
                  ez_axis=self.F[2, :p.Nz, p.Ny // 2, p.Nx // 2].copy())
+        if rho1 is not None:
+            d["charge_particles"] = p.q * p.w * n_pushed
+            d["charge_grid"] = float(np.sum(rho1) * V)
         if rho0 is not None:
             r = continuity_residual(p, rho0, rho1, *self.J)
             s = (rho1 - rho0) / p.dtau

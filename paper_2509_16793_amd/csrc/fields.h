@@ -1,0 +1,323 @@
+// Field kernels: batched transverse 2-D FFT of real planes, the right-to-left
+// march of the node scheme (Sec. 4.1) with the analytic node solution (App. B),
+// and small helpers.
+//
+// Spectral layout: [plane][ky][kx] complex with kx = 0 .. Nx/2 - 1 (the kx
+// Nyquist column is dropped: the solver zeroes it), ky in FFT order; the
+// ky Nyquist row is stored and held at zero.  Forward transform
+// sum f exp(-i k.r), inverse with 1/(Nx Ny).
+#pragma once
+#include "common.h"
+
+// ---------------------------------------------------------------------------
+// Radix-2 Stockham FFT of nseq sequences of length N held in LDS (x -> result
+// pointer returned; y is the ping-pong buffer).  tw[t] = exp(-2 pi i t / N),
+// t < N/2; inverse uses the conjugate twiddles (no scaling here).
+template <typename T>
+GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, int N, int nseq, const cplx<T>* tw, bool inverse) {
+  int half = N >> 1;
+  int total = nseq * half;
+  for (int Ns = 1; Ns < N; Ns <<= 1) {
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      int sq = idx / half, j = idx - sq * half;
+      int k = j & (Ns - 1);
+      cplx<T> w = tw[k * (half / Ns)];
+      if (inverse) w.y = -w.y;
+      cplx<T>* xs = x + sq * N;
+      cplx<T> a = xs[j];
+      cplx<T> b = w * xs[j + half];
+      int d = ((j - k) << 1) + k;
+      cplx<T>* ys = y + sq * N;
+      ys[d] = a + b;
+      ys[d + Ns] = a - b;
+    }
+    __syncthreads();
+    cplx<T>* t = x; x = y; y = t;
+  }
+  return x;
+}
+
+// Forward transform along x of pairs of real rows (two-for-one): rows 2r and
+// 2r+1 of in[rows][Nx] -> out[rows][Nxh].  nseq pairs per work-group.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_r2c(const T* in, cplx<T>* out, int64_t rows, int Nx,
+                                                   int nseq, const cplx<T>* tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* y = x + nseq * Nx;
+  int64_t pair0 = (int64_t)blockIdx.x * nseq;
+  for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
+    int sq = idx / Nx, n = idx - sq * Nx;
+    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
+    T a = r0 < rows ? in[r0 * Nx + n] : (T)0;
+    T b = r1 < rows ? in[r1 * Nx + n] : (T)0;
+    x[idx] = mk(a, b);
+  }
+  __syncthreads();
+  cplx<T>* Z = lds_fft(x, y, Nx, nseq, tw, false);
+  int Nxh = Nx >> 1;
+  for (int idx = threadIdx.x; idx < nseq * Nxh; idx += blockDim.x) {
+    int sq = idx / Nxh, k = idx - sq * Nxh;
+    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
+    cplx<T> zk = Z[sq * Nx + k];
+    cplx<T> zc = conj(Z[sq * Nx + ((Nx - k) & (Nx - 1))]);
+    cplx<T> A = (T)0.5 * (zk + zc);
+    cplx<T> D = zk - zc;                  // B = D / (2 i) = -i D / 2
+    cplx<T> B = mk((T)0.5 * D.y, (T)-0.5 * D.x);
+    if (r0 < rows) out[r0 * Nxh + k] = A;
+    if (r1 < rows) out[r1 * Nxh + k] = B;
+  }
+}
+
+// Inverse of k_fft_x_r2c (scaled by 1/Nx): in[rows][Nxh] -> out[rows][Nx].
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_c2r(const cplx<T>* in, T* out, int64_t rows, int Nx,
+                                                   int nseq, const cplx<T>* tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* y = x + nseq * Nx;
+  int64_t pair0 = (int64_t)blockIdx.x * nseq;
+  int Nxh = Nx >> 1;
+  for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
+    int sq = idx / Nx, n = idx - sq * Nx;
+    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
+    cplx<T> z = mk((T)0, (T)0);
+    if (n < Nxh) {
+      cplx<T> A = r0 < rows ? in[r0 * Nxh + n] : mk((T)0, (T)0);
+      cplx<T> B = r1 < rows ? in[r1 * Nxh + n] : mk((T)0, (T)0);
+      z = A + mul_i(B);
+    } else if (n > Nxh) {
+      int k = Nx - n;
+      cplx<T> A = r0 < rows ? in[r0 * Nxh + k] : mk((T)0, (T)0);
+      cplx<T> B = r1 < rows ? in[r1 * Nxh + k] : mk((T)0, (T)0);
+      z = conj(A) + mul_i(conj(B));
+    }
+    x[idx] = z;
+  }
+  __syncthreads();
+  cplx<T>* Z = lds_fft(x, y, Nx, nseq, tw, true);
+  T sc = (T)1 / (T)Nx;
+  for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
+    int sq = idx / Nx, n = idx - sq * Nx;
+    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
+    cplx<T> z = Z[idx];
+    if (r0 < rows) out[r0 * Nx + n] = sc * z.x;
+    if (r1 < rows) out[r1 * Nx + n] = sc * z.y;
+  }
+}
+
+// Transform along y (columns), in place: data[planes][Ny][Nxh]; a work-group
+// takes ncol consecutive kx columns of one plane.  Inverse scales by 1/Ny.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_y(cplx<T>* data, int Ny, int Nxh, int ncol,
+                                               const cplx<T>* tw, int inverse) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* y = x + ncol * Ny;
+  int cpp = Nxh / ncol;                       // column groups per plane
+  int64_t plane = blockIdx.x / cpp;
+  int c0 = (blockIdx.x % cpp) * ncol;
+  cplx<T>* base = data + plane * Ny * Nxh + c0;
+  for (int idx = threadIdx.x; idx < ncol * Ny; idx += blockDim.x) {
+    int row = idx / ncol, c = idx - row * ncol;
+    x[c * Ny + row] = base[(int64_t)row * Nxh + c];
+  }
+  __syncthreads();
+  cplx<T>* Z = lds_fft(x, y, Ny, ncol, tw, inverse != 0);
+  T sc = inverse ? (T)1 / (T)Ny : (T)1;
+  for (int idx = threadIdx.x; idx < ncol * Ny; idx += blockDim.x) {
+    int row = idx / ncol, c = idx - row * ncol;
+    base[(int64_t)row * Nxh + c] = sc * Z[c * Ny + row];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The march.  One thread per transverse mode (ky, kx); zeta nodes n = Nz-1 .. 0.
+// Node "1" (n + 1, new level) is known; node 0 (n) is solved with App. B:
+//   K^2 = kx^2 + ky^2,  D = 16 + h (2 Delta + h) K^2,
+//   Jx = sum of the four j_x (both levels, both half-nodes), likewise Jy,
+//   Wx = -2 Lx1 + Rx0^0 + Rx1,  Ux = 2 Lx1 + Rx0^0 + Rx1 (and y),
+//   Ez0^1 = [Ez1 (16 - h^2 K^2) - 16 h jz+ - i h Delta (kx Jx + ky Jy)
+//            - 2 h Delta Ez0^0 K^2 + 2 i h^2 (kx jx+ + ky jy+)
+//            + 4 i h (kx Wx + ky Wy)] / D,
+//   Bz0^1 = [Bz1 (16 - h^2 K^2) + 2 i h^2 (kx jy+ - ky jx+)
+//            + i h Delta (kx Jy - ky Jx) - 2 h Delta Bz0^0 K^2
+//            + 4 i h (ky Ux - kx Uy)] / D,
+// then Rx, Ry from RxN/RyN and Lx, Ly from the L equations, with the readings
+// (Ly equation with (Bz0^1 + Bz1^1)/2; Ez equation with + i ky (Bx0 + Bx1)/2;
+// T4 with a minus sign) under which this closed form solves the node system.
+// Currents j^0 = j^1 = the step's deposit.  Solver current on half-node
+// n + 1/2 (plane n + 2 of the raw deposit):
+//   jx = filt[(Jx(n) + Jx(n+1)) / 2] exp(-i kx hx / 2), jy likewise with ky hy
+//   (3-D), jz = filt[Jz(n + 1/2)],
+// where filt is the binomial filter: (1,2,1)/4 per pass along zeta (zero
+// beyond the stored planes) and cos^2(k h / 2) per pass and transverse axis.
+template <typename T>
+struct MarchArgs {
+  Geom g;
+  const cplx<T>* J[3];     // raw current spectra [NPF][Ny][Nxh]; null = no current
+  cplx<T>* st[4];          // Rx, Ry, Ez, Bz [Nz][Ny][Nxh] (old level in, new level out)
+  cplx<T>* out[6];         // Ex, Ey, Ez, Bx, By, Bz spectra [Nz][Ny][Nxh]
+  cplx<T>* L[2];           // nullable: Lx, Ly of the new level
+  T Delta;
+};
+
+template <typename T>
+GP_DEV cplx<T> filt_plane(const cplx<T>* A, int p, int NPF, int P, int64_t stride, int64_t m) {
+  // binomial filter along the plane index, P passes
+  const T w1[3] = {(T)0.25, (T)0.5, (T)0.25};
+  const T w2[5] = {(T)0.0625, (T)0.25, (T)0.375, (T)0.25, (T)0.0625};
+  cplx<T> r = mk((T)0, (T)0);
+  if (P == 0) {
+    if (p >= 0 && p < NPF) r = A[(int64_t)p * stride + m];
+    return r;
+  }
+  for (int d = -P; d <= P; ++d) {
+    int q = p + d;
+    if (q < 0 || q >= NPF) continue;
+    T w = P == 1 ? w1[d + 1] : w2[d + 2];
+    cplx<T> v = A[(int64_t)q * stride + m];
+    r = r + w * v;
+  }
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_march(MarchArgs<T> a) {
+  const Geom& g = a.g;
+  int64_t M = (int64_t)g.Ny * g.Nxh;
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  int kyi = (int)(m / g.Nxh), kxi = (int)(m % g.Nxh);
+  const double PI = 3.14159265358979323846;
+  double kxd = 2.0 * PI * (double)kxi / ((double)g.Nx * g.hx);
+  int kys = kyi <= g.Ny / 2 ? kyi : kyi - g.Ny;
+  double kyd = g.Ny > 1 ? 2.0 * PI * (double)kys / ((double)g.Ny * g.hy) : 0.0;
+  bool nyq = g.Ny > 1 && kyi == g.Ny / 2;
+  int64_t stride = M;
+  if (nyq) {
+    cplx<T> z = mk((T)0, (T)0);
+    for (int n = 0; n < g.Nz; ++n) {
+      int64_t o = (int64_t)n * stride + m;
+      for (int q = 0; q < 4; ++q) a.st[q][o] = z;
+      for (int q = 0; q < 6; ++q) a.out[q][o] = z;
+      if (a.L[0]) { a.L[0][o] = z; a.L[1][o] = z; }
+    }
+    return;
+  }
+  T kx = (T)kxd, ky = (T)kyd;
+  T h = (T)g.h, D = a.Delta;
+  T K2 = kx * kx + ky * ky;
+  T Dd = (T)16 + h * ((T)2 * D + h) * K2;
+  T inv = (T)1 / Dd;
+  T c16 = (T)16 - h * h * K2;
+  // transverse filter and half-cell shifts
+  double fx = cos(0.5 * kxd * g.hx), fxy = fx * fx;
+  if (g.dims == 3) { double fy = cos(0.5 * kyd * g.hy); fxy *= fy * fy; }
+  double phi = g.P == 0 ? 1.0 : (g.P == 1 ? fxy : fxy * fxy);
+  cplx<T> sx = mk((T)(0.5 * phi * cos(0.5 * kxd * g.hx)), (T)(-0.5 * phi * sin(0.5 * kxd * g.hx)));
+  cplx<T> sy = g.dims == 3 ? mk((T)(0.5 * phi * cos(0.5 * kyd * g.hy)), (T)(-0.5 * phi * sin(0.5 * kyd * g.hy)))
+                           : mk((T)(0.5 * phi), (T)0);
+  T phz = (T)phi;
+  bool hasJ = a.J[0] != nullptr;
+  // filtered planes of Jx, Jy (nodal) carried between iterations
+  cplx<T> fxp = mk((T)0, (T)0), fyp = fxp;   // filtered plane n + 2 (node n + 1 of half-node n + 1/2)
+  cplx<T> jxp = fxp, jyp = fxp, jzp = fxp;   // solver currents on half-node n + 1/2
+  if (hasJ) {
+    // half-node q = Nz: planes Nz + 1, Nz + 2
+    cplx<T> f1 = filt_plane(a.J[0], g.Nz + 1, g.NPF, g.P, stride, m);
+    cplx<T> f2 = filt_plane(a.J[0], g.Nz + 2, g.NPF, g.P, stride, m);
+    jxp = sx * (f1 + f2);
+    fxp = f1;
+    cplx<T> e1 = filt_plane(a.J[1], g.Nz + 1, g.NPF, g.P, stride, m);
+    cplx<T> e2 = filt_plane(a.J[1], g.Nz + 2, g.NPF, g.P, stride, m);
+    jyp = sy * (e1 + e2);
+    fyp = e1;
+    jzp = phz * filt_plane(a.J[2], g.Nz + 1, g.NPF, g.P, stride, m);
+  }
+  cplx<T> Rx1 = mk((T)0, (T)0), Ry1 = Rx1, Lx1 = Rx1, Ly1 = Rx1, Ez1 = Rx1, Bz1 = Rx1;
+  for (int n = g.Nz - 1; n >= 0; --n) {
+    cplx<T> jxm = mk((T)0, (T)0), jym = jxm, jzm = jxm;
+    if (hasJ) {
+      // half-node n - 1/2: planes n + 1 (new) and n + 2 (carried)
+      cplx<T> f1 = filt_plane(a.J[0], n + 1, g.NPF, g.P, stride, m);
+      jxm = sx * (f1 + fxp);
+      fxp = f1;
+      cplx<T> e1 = filt_plane(a.J[1], n + 1, g.NPF, g.P, stride, m);
+      jym = sy * (e1 + fyp);
+      fyp = e1;
+      jzm = phz * filt_plane(a.J[2], n + 1, g.NPF, g.P, stride, m);
+    }
+    int64_t o = (int64_t)n * stride + m;
+    cplx<T> Rx0 = a.st[0][o], Ry0 = a.st[1][o], Ez0 = a.st[2][o], Bz0 = a.st[3][o];
+    cplx<T> Jx = (T)2 * (jxm + jxp);
+    cplx<T> Jy = (T)2 * (jym + jyp);
+    cplx<T> Wx = (Rx0 + Rx1) - (T)2 * Lx1;
+    cplx<T> Wy = (Ry0 + Ry1) - (T)2 * Ly1;
+    cplx<T> Ux = (Rx0 + Rx1) + (T)2 * Lx1;
+    cplx<T> Uy = (Ry0 + Ry1) + (T)2 * Ly1;
+    cplx<T> Ez = c16 * Ez1 - ((T)16 * h) * jzp
+                 - mul_i((h * D) * (kx * Jx + ky * Jy))
+                 - ((T)2 * h * D * K2) * Ez0
+                 + mul_i(((T)2 * h * h) * (kx * jxp + ky * jyp))
+                 + mul_i(((T)4 * h) * (kx * Wx + ky * Wy));
+    Ez = inv * Ez;
+    cplx<T> Bz = c16 * Bz1 + mul_i(((T)2 * h * h) * (kx * jyp - ky * jxp))
+                 + mul_i((h * D) * (kx * Jy - ky * Jx))
+                 - ((T)2 * h * D * K2) * Bz0
+                 + mul_i(((T)4 * h) * (ky * Ux - kx * Uy));
+    Bz = inv * Bz;
+    cplx<T> Ezs = Ez + Ez0, Bzs = Bz + Bz0;
+    cplx<T> Rx = Rx0 + mul_i(((T)0.5 * D) * (kx * Ezs + ky * Bzs)) - ((T)0.25 * D) * Jx;
+    cplx<T> Ry = Ry0 + mul_i(((T)0.5 * D) * (ky * Ezs - kx * Bzs)) - ((T)0.25 * D) * Jy;
+    cplx<T> Ezp = Ez1 + Ez, Bzp = Bz + Bz1;
+    cplx<T> Lx = Lx1 - ((T)0.5 * h) * (mul_i((T)0.5 * (kx * Ezp - ky * Bzp)) + jxp);
+    cplx<T> Ly = Ly1 - ((T)0.5 * h) * (mul_i((T)0.5 * (ky * Ezp + kx * Bzp)) + jyp);
+    a.st[0][o] = Rx;
+    a.st[1][o] = Ry;
+    a.st[2][o] = Ez;
+    a.st[3][o] = Bz;
+    a.out[0][o] = (T)0.5 * (Rx + Lx);
+    a.out[1][o] = (T)0.5 * (Ry + Ly);
+    a.out[2][o] = Ez;
+    a.out[3][o] = (T)0.5 * (Ly - Ry);
+    a.out[4][o] = (T)0.5 * (Rx - Lx);
+    a.out[5][o] = Bz;
+    if (a.L[0]) { a.L[0][o] = Lx; a.L[1][o] = Ly; }
+    Rx1 = Rx; Ry1 = Ry; Lx1 = Lx; Ly1 = Ly; Ez1 = Ez; Bz1 = Bz;
+    jxp = jxm; jyp = jym; jzp = jzm;
+  }
+}
+
+// E/B spectra from a given (R, L, Ez, Bz) state (state upload).
+template <typename T>
+__global__ void k_state_to_fields(const cplx<T>* Rx, const cplx<T>* Ry, const cplx<T>* Lx,
+                                  const cplx<T>* Ly, const cplx<T>* Ez, const cplx<T>* Bz,
+                                  cplx<T>* o0, cplx<T>* o1, cplx<T>* o2, cplx<T>* o3, cplx<T>* o4,
+                                  cplx<T>* o5, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  o0[i] = (T)0.5 * (Rx[i] + Lx[i]);
+  o1[i] = (T)0.5 * (Ry[i] + Ly[i]);
+  o2[i] = Ez[i];
+  o3[i] = (T)0.5 * (Ly[i] - Ry[i]);
+  o4[i] = (T)0.5 * (Rx[i] - Lx[i]);
+  o5[i] = Bz[i];
+}
+
+// Laser field E_pol(x, y, zeta) = lon[n] * tra[j][i] on the field nodes,
+// times 2 (R = 2 E for a pure forward wave).
+template <typename T>
+__global__ void k_laser(T* out, const double* lon, const double* tra, int Nz, int64_t nxy) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Nz * nxy) return;
+  int64_t n = i / nxy, r = i - n * nxy;
+  out[i] = (T)(2.0 * (lon[n] * tra[r]));
+}
+
+// zero a buffer of T
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}

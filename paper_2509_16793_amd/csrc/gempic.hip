@@ -1,0 +1,866 @@
+// Host driver and C ABI of the gfx950 Galilean PIC library (see include/gempic.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gempic.h"
+#include "common.h"
+#include "diag.h"
+#include "fields.h"
+#include "particles.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Dev {
+  std::vector<void*> ptrs;
+  hipError_t last = hipSuccess;
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) { last = e; return nullptr; }
+    ptrs.push_back(p);
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct gempic {
+  gempic_config cfg;
+  Geom g;
+  int prec;          // 0 fp64, 1 fp32
+  size_t esz;        // sizeof(T)
+  hipStream_t s;
+  int ppcx, ppcy, ppcz, quiet;
+  uint64_t key;
+  double L, hz, w, Tlas, zeta_c, waist;
+  int64_t step;
+  bool failed;
+  std::string err;
+  Dev dev;
+
+  // particles: two buffers of 7 arrays (cell, ox, oy, oz, ux, uy, uz) + ids
+  void* part[2][7];
+  int64_t* ids[2];
+  int cur;
+  void* stage[7];
+  int32_t* stage_g;
+  int64_t capacity, stage_per_tile, max_nm;
+  int max_chunks;
+  ChunkTab ct[2];
+  int ctc;
+  int32_t *code, *counts, *offs, *inj_count, *inj_off, *gflag, *grank;
+  int64_t *tile_count, *tile_base, *total, *next_id, *inj_total, *pushed;
+  int* err_dev;
+  // grids
+  void* F[6];
+  void* J[3];
+  void* rho[2];
+  void* Jhat[3];
+  void* st[4];
+  void* outs[6];
+  void* Lsp[2];
+  void* twx;
+  void* twy;
+  double* partial;
+  double* dres;
+};
+
+static int fail(gempic* g, int code, const std::string& msg) {
+  if (g) {
+    g->err = msg;
+    if (code == GEMPIC_EDEVICE || code == GEMPIC_ECFL || code == GEMPIC_ENUMERIC ||
+        code == GEMPIC_ECAPACITY)
+      g->failed = true;
+  } else {
+    g_create_error = msg;
+  }
+  return code;
+}
+
+#define HIPCHK(g, expr)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(g, GEMPIC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static bool pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Impl {
+  using C = cplx<T>;
+
+  static PartPtrs<T> parts(gempic* g, int b) {
+    PartPtrs<T> P;
+    P.cell = (int32_t*)g->part[b][0];
+    P.ox = (T*)g->part[b][1];
+    P.oy = (T*)g->part[b][2];
+    P.oz = (T*)g->part[b][3];
+    P.ux = (T*)g->part[b][4];
+    P.uy = (T*)g->part[b][5];
+    P.uz = (T*)g->part[b][6];
+    P.id = g->ids[b];
+    return P;
+  }
+  static PartPtrs<T> staging(gempic* g) {
+    PartPtrs<T> P;
+    P.cell = (int32_t*)g->stage[0];
+    P.ox = (T*)g->stage[1];
+    P.oy = (T*)g->stage[2];
+    P.oz = (T*)g->stage[3];
+    P.ux = (T*)g->stage[4];
+    P.uy = (T*)g->stage[5];
+    P.uz = (T*)g->stage[6];
+    P.id = nullptr;
+    return P;
+  }
+
+  static void fill(gempic* g, void* p, int64_t n) {
+    if (n <= 0) return;
+    k_fill<T><<<nblk(n, 256), 256, 0, g->s>>>((T*)p, n, (T)0);
+  }
+
+  // ---- FFT helpers --------------------------------------------------------
+  static void fft_fwd(gempic* g, const T* in, C* out, int64_t planes) {
+    const Geom& G = g->g;
+    int64_t rows = planes * G.Ny;
+    int64_t pairs = (rows + 1) / 2;
+    int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / G.Nx));
+    size_t sh = 2 * (size_t)nseq * G.Nx * sizeof(C);
+    k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
+    if (G.Ny > 1) {
+      int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
+      size_t sh2 = 2 * (size_t)ncol * G.Ny * sizeof(C);
+      k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 256, sh2, g->s>>>(out, G.Ny, G.Nxh, ncol,
+                                                                       (const C*)g->twy, 0);
+    }
+  }
+  static void fft_inv(gempic* g, C* in, T* out, int64_t planes) {
+    const Geom& G = g->g;
+    if (G.Ny > 1) {
+      int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
+      size_t sh2 = 2 * (size_t)ncol * G.Ny * sizeof(C);
+      k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 256, sh2, g->s>>>(in, G.Ny, G.Nxh, ncol,
+                                                                      (const C*)g->twy, 1);
+    }
+    int64_t rows = planes * G.Ny;
+    int64_t pairs = (rows + 1) / 2;
+    int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / G.Nx));
+    size_t sh = 2 * (size_t)nseq * G.Nx * sizeof(C);
+    k_fft_x_c2r<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
+  }
+
+  // ---- field update: FFT(J) -> march -> iFFT ------------------------------
+  static void field_update(gempic* g, bool with_current, T Delta) {
+    const Geom& G = g->g;
+    MarchArgs<T> a;
+    a.g = G;
+    for (int q = 0; q < 3; ++q) {
+      if (with_current) fft_fwd(g, (const T*)g->J[q], (C*)g->Jhat[q], G.NPF);
+      a.J[q] = with_current ? (const C*)g->Jhat[q] : nullptr;
+    }
+    for (int q = 0; q < 4; ++q) a.st[q] = (C*)g->st[q];
+    for (int q = 0; q < 6; ++q) a.out[q] = (C*)g->outs[q];
+    a.L[0] = (C*)g->Lsp[0];
+    a.L[1] = (C*)g->Lsp[1];
+    a.Delta = Delta;
+    int64_t M = (int64_t)G.Ny * G.Nxh;
+    k_march<T><<<nblk(M, 64), 64, 0, g->s>>>(a);
+    for (int q = 0; q < 6; ++q) fft_inv(g, (C*)g->outs[q], (T*)g->F[q], G.Nz);
+  }
+
+  // ---- sort + window injection of batch b --------------------------------
+  static int sort_and_inject(gempic* g, int64_t b) {
+    const Geom& G = g->g;
+    int A = g->cur, B = 1 - g->cur;
+    ChunkTab& oldt = g->ct[g->ctc];
+    ChunkTab& newt = g->ct[1 - g->ctc];
+    SortArgs sa;
+    sa.g = G;
+    sa.ct = oldt;
+    sa.cell = (const int32_t*)g->part[A][0];
+    sa.code = g->code;
+    sa.counts = g->counts;
+    sa.err = g->err_dev;
+    k_sort_rank<<<g->max_chunks, 256, 0, g->s>>>(sa);
+
+    k_fill<int32_t><<<nblk(G.NT, 256), 256, 0, g->s>>>(g->inj_count, G.NT, 0);
+    InjArgs ia;
+    int64_t nm = 0;
+    if (g->cfg.n_e > 0.0) {
+      double lo = g->L + (double)b * G.dtau;
+      double hi = g->L + (double)(b + 1) * G.dtau;
+      int64_t m0 = (int64_t)(G.Nzp - 1) * g->ppcz;
+      int64_t m_lo = b > 0 ? std::max<int64_t>(m0, (int64_t)std::floor(lo / g->hz) - 1) : m0;
+      int64_t m_hi = (int64_t)std::floor(hi / g->hz) + 1;
+      nm = m_hi - m_lo + 1;
+      if (nm > g->max_nm) return fail(g, GEMPIC_EDEVICE, "internal: window batch larger than staging");
+      ia.g = G;
+      ia.ppcx = g->ppcx; ia.ppcy = g->ppcy; ia.ppcz = g->ppcz;
+      ia.quiet = g->quiet;
+      ia.key = g->key;
+      ia.b = (int)b;
+      ia.m_lo = m_lo; ia.m_hi = m_hi;
+      ia.lo = lo; ia.hi = hi; ia.hz = g->hz;
+      ia.shift = (double)b * G.dtau;
+      ia.stage_per_tile = g->stage_per_tile;
+      ia.inj_count = g->inj_count;
+      ia.stage_g = g->stage_g;
+      ia.gflag = g->ids[0] ? g->gflag : nullptr;
+      k_inject<T><<<G.nTx * G.nTy, 256, 0, g->s>>>(ia, staging(g));
+      if (g->ids[0]) {
+        int64_t ng = nm * G.Ny * G.Nx * g->ppcx * g->ppcy;
+        k_scan_flags<<<1, 1024, 0, g->s>>>(ng, g->gflag, g->grank, nullptr);
+      }
+    }
+    OffArgs oa;
+    oa.g = G;
+    oa.ct = oldt;
+    oa.counts = g->counts;
+    oa.offs = g->offs;
+    oa.inj_count = g->inj_count;
+    oa.inj_off = g->inj_off;
+    oa.tile_count = g->tile_count;
+    k_tile_offsets<<<nblk(G.NT, 128), 128, 0, g->s>>>(oa);
+    k_scan_tiles<<<1, 1024, 0, g->s>>>(G.NT, g->tile_count, g->tile_base, g->total, newt.first,
+                                        newt.count, newt.n, g->capacity, g->err_dev);
+    k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, newt,
+                                                       g->max_chunks);
+    ScatArgs<T> sc;
+    sc.g = G;
+    sc.ct = oldt;
+    sc.code = g->code;
+    sc.offs = g->offs;
+    sc.tile_base = g->tile_base;
+    sc.capacity = g->capacity;
+    sc.err = g->err_dev;
+    if (G.dims == 3)
+      k_scatter<T, 3><<<g->max_chunks, 256, 0, g->s>>>(sc, parts(g, A), parts(g, B));
+    else
+      k_scatter<T, 2><<<g->max_chunks, 256, 0, g->s>>>(sc, parts(g, A), parts(g, B));
+    if (g->cfg.n_e > 0.0) {
+      InjCopyArgs ca;
+      ca.g = G;
+      ca.inj_count = g->inj_count;
+      ca.inj_off = g->inj_off;
+      ca.tile_base = g->tile_base;
+      ca.stage_per_tile = g->stage_per_tile;
+      ca.stage_g = g->stage_g;
+      ca.grank = g->grank;
+      ca.next_id = g->next_id;
+      ca.capacity = g->capacity;
+      ca.err = g->err_dev;
+      if (G.dims == 3)
+        k_inject_copy<T, 3><<<G.nTx * G.nTy, 256, 0, g->s>>>(ca, staging(g), parts(g, B));
+      else
+        k_inject_copy<T, 2><<<G.nTx * G.nTy, 256, 0, g->s>>>(ca, staging(g), parts(g, B));
+      if (g->ids[0]) {
+        int64_t ng = nm * G.Ny * G.Nx * g->ppcx * g->ppcy;
+        // next_id += number of selected candidates (a scan of the flags adds the total)
+        k_scan_flags<<<1, 1024, 0, g->s>>>(ng, g->gflag, g->grank, g->next_id);
+      }
+    }
+    g->cur = B;
+    g->ctc = 1 - g->ctc;
+    return GEMPIC_OK;
+  }
+
+  static PushArgs<T> push_args(gempic* g) {
+    const Geom& G = g->g;
+    PushArgs<T> a;
+    a.g = G;
+    for (int q = 0; q < 6; ++q) a.F[q] = (const T*)g->F[q];
+    for (int q = 0; q < 3; ++q) a.J[q] = (T*)g->J[q];
+    a.rho0 = g->cfg.deposit_rho ? (T*)g->rho[0] : nullptr;
+    a.rho1 = g->cfg.deposit_rho ? (T*)g->rho[1] : nullptr;
+    double q = -1.0;
+    double dtau = G.dtau;
+    a.eps = (T)(0.5 * q * dtau);
+    a.ax = (T)(dtau / G.hx);
+    a.ay = (T)(dtau / G.hy);
+    a.az = (T)(dtau / G.h);
+    double qw = G.qw;
+    if (G.dims == 3) {
+      a.cx = (T)(-qw / (dtau * G.hy * G.h));
+      a.cy = (T)(-qw / (dtau * G.hx * G.h));
+      a.cz = (T)(-qw / (dtau * G.hx * G.hy));
+      a.cjy = (T)0;
+    } else {
+      a.cx = (T)(-qw / (dtau * G.h));
+      a.cy = (T)0;
+      a.cz = (T)(-qw / (dtau * G.hx));
+      a.cjy = (T)(qw / (G.hx * G.h));
+    }
+    a.crho = (T)(qw / G.V);
+    a.ct = g->ct[g->ctc];
+    a.err = g->err_dev;
+    return a;
+  }
+
+  static size_t push_lds(const Geom& G, bool rho) {
+    int FY = G.dims == 3 ? G.Ty + 1 : 1, JY = G.dims == 3 ? G.Ty + 3 : 1;
+    size_t FN = (size_t)(G.Tx + 1) * FY * (G.Tz + 1);
+    size_t JN = (size_t)(G.Tx + 3) * JY * (G.Tz + 4);
+    size_t RN = (size_t)(G.Tx + 3) * JY * (G.Tz + 2);
+    return (6 * FN + 3 * JN + (rho ? 2 * RN : 0)) * sizeof(T);
+  }
+
+  static void set_lds_limits() {
+    int lim = 160 * 1024;
+    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 3, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 3, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_fft_x_r2c<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_fft_x_c2r<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_fft_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  }
+
+  static void launch_push(gempic* g) {
+    const Geom& G = g->g;
+    bool rho = g->cfg.deposit_rho != 0;
+    PushArgs<T> a = push_args(g);
+    size_t sh = push_lds(G, rho);
+    PartPtrs<T> P = parts(g, g->cur);
+    if (G.dims == 3) {
+      if (rho) k_push_deposit<T, 3, true><<<g->max_chunks, 256, sh, g->s>>>(a, P);
+      else k_push_deposit<T, 3, false><<<g->max_chunks, 256, sh, g->s>>>(a, P);
+    } else {
+      if (rho) k_push_deposit<T, 2, true><<<g->max_chunks, 256, sh, g->s>>>(a, P);
+      else k_push_deposit<T, 2, false><<<g->max_chunks, 256, sh, g->s>>>(a, P);
+    }
+  }
+
+  static int one_step(gempic* g) {
+    const Geom& G = g->g;
+    int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+    for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
+    if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
+    launch_push(g);
+    (void)hipMemcpyAsync(g->pushed, g->total, 8, hipMemcpyDeviceToDevice, g->s);
+    int rc = sort_and_inject(g, g->step + 1);
+    if (rc) return rc;
+    field_update(g, true, (T)G.dtau);
+    g->step += 1;
+    return GEMPIC_OK;
+  }
+
+  // ---- creation: load plasma, batch 0, laser -------------------------------
+  static int init_state(gempic* g) {
+    const Geom& G = g->g;
+    // chunk table of the loaded (full-cell) particles: closed-form tile counts
+    std::vector<int64_t> cnt(G.NT, 0), base(G.NT, 0);
+    int64_t tot = 0;
+    if (g->cfg.n_e > 0.0) {
+      for (int t = 0; t < G.NT; ++t) {
+        int tz = t / (G.nTx * G.nTy);
+        int z0 = tz * G.Tz, zend = std::min(z0 + G.Tz, G.Nzp - 1);
+        int64_t n = zend > z0 ? (int64_t)(zend - z0) * g->ppcz * G.Ty * G.Tx * g->ppcx * g->ppcy : 0;
+        cnt[t] = n;
+        base[t] = tot;
+        tot += n;
+      }
+    }
+    if (tot > g->capacity) return fail(g, GEMPIC_EINVAL, "capacity too small for the initial load");
+    HIPCHK(g, hipMemcpyAsync(g->tile_count, cnt.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->tile_base, base.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
+    if (tot > 0) {
+      LoadArgs la;
+      la.g = G;
+      la.ppcx = g->ppcx; la.ppcy = g->ppcy; la.ppcz = g->ppcz;
+      la.quiet = g->quiet;
+      la.key = g->key;
+      la.tile_base = g->tile_base;
+      k_load_full<T><<<G.NT, 256, 0, g->s>>>(la, parts(g, g->cur));
+    }
+    ChunkTab& t0 = g->ct[g->ctc];
+    k_scan_tiles<<<1, 1024, 0, g->s>>>(G.NT, g->tile_count, g->tile_base, g->total, t0.first, t0.count,
+                                        t0.n, g->capacity, g->err_dev);
+    k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, t0,
+                                                       g->max_chunks);
+    if (g->ids[0]) HIPCHK(g, hipMemcpyAsync(g->next_id, &tot, 8, hipMemcpyHostToDevice, g->s));
+    int rc = sort_and_inject(g, 0);
+    if (rc) return rc;
+
+    // laser: R_pol = 2 E_pol on the field nodes, then a march with Delta = 0
+    int64_t nxy = (int64_t)G.Ny * G.Nx;
+    int64_t nsp = (int64_t)G.Nz * G.Ny * G.Nxh;
+    for (int q = 0; q < 4; ++q) fill(g, g->st[q], 2 * nsp);
+    if (g->cfg.a0 != 0.0) {
+      std::vector<double> lon(G.Nz), tra(nxy);
+      for (int n = 0; n < G.Nz; ++n) {
+        double zeta = (double)n * G.h;
+        double phi = zeta - g->zeta_c;
+        lon[n] = g->cfg.a0 * std::cos(phi) * std::exp(-(phi * phi) / (g->Tlas * g->Tlas));
+      }
+      for (int j = 0; j < G.Ny; ++j)
+        for (int i = 0; i < G.Nx; ++i) {
+          double X = (double)i * G.hx - (double)(G.Nx / 2) * G.hx;
+          double Y = G.dims == 3 ? (double)j * G.hy - (double)(G.Ny / 2) * G.hy : 0.0;
+          tra[(int64_t)j * G.Nx + i] = g->waist > 0.0 ? std::exp(-(X * X + Y * Y) / (g->waist * g->waist)) : 1.0;
+        }
+      double* dl = (double*)g->dev.alloc(lon.size() * 8);
+      double* dt = (double*)g->dev.alloc(tra.size() * 8);
+      if (!dl || !dt) return fail(g, GEMPIC_ENOMEM, "laser buffers");
+      HIPCHK(g, hipMemcpyAsync(dl, lon.data(), lon.size() * 8, hipMemcpyHostToDevice, g->s));
+      HIPCHK(g, hipMemcpyAsync(dt, tra.data(), tra.size() * 8, hipMemcpyHostToDevice, g->s));
+      k_laser<T><<<nblk((int64_t)G.Nz * nxy, 256), 256, 0, g->s>>>((T*)g->J[0], dl, dt, G.Nz, nxy);
+      fft_fwd(g, (const T*)g->J[0], (C*)g->st[g->cfg.pol == 0 ? 0 : 1], G.Nz);
+    }
+    field_update(g, false, (T)0);
+    int64_t nJ = (int64_t)G.NPJ * nxy;
+    for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
+    if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
+    HIPCHK(g, hipStreamSynchronize(g->s));
+    return GEMPIC_OK;
+  }
+
+  static int diag(gempic* g, gempic_diag* d) {
+    const Geom& G = g->g;
+    int64_t n = 0, np = 0;
+    HIPCHK(g, hipMemcpyAsync(&n, g->total, 8, hipMemcpyDeviceToHost, g->s));
+    HIPCHK(g, hipMemcpyAsync(&np, g->pushed, 8, hipMemcpyDeviceToHost, g->s));
+    int64_t nf = (int64_t)G.Nz * G.Ny * G.Nx;
+    k_partial<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->F[0], (const T*)g->F[1], (const T*)g->F[2],
+                                                (const T*)g->F[3], (const T*)g->F[4], (const T*)g->F[5],
+                                                6, nf, 1, g->partial);
+    k_final<<<1, 256, 0, g->s>>>(g->partial, DIAG_BLOCKS, 1, g->dres);
+    double res[4] = {0, 0, 0, 0};
+    int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+    if (g->cfg.deposit_rho) {
+      k_partial<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->rho[1], nullptr, nullptr, nullptr, nullptr,
+                                                  nullptr, 1, nJ, 0, g->partial + 2 * DIAG_BLOCKS);
+      k_final<<<1, 256, 0, g->s>>>(g->partial + 2 * DIAG_BLOCKS, DIAG_BLOCKS, 1, g->dres + 1);
+      k_continuity<T><<<DIAG_BLOCKS, 256, 0, g->s>>>(G, (const T*)g->rho[0], (const T*)g->rho[1],
+                                                     (const T*)g->J[0], (const T*)g->J[1],
+                                                     (const T*)g->J[2], g->partial + 4 * DIAG_BLOCKS);
+      k_final<<<1, 256, 0, g->s>>>(g->partial + 4 * DIAG_BLOCKS, DIAG_BLOCKS, 2, g->dres + 2);
+    }
+    HIPCHK(g, hipMemcpyAsync(res, g->dres, 32, hipMemcpyDeviceToHost, g->s));
+    HIPCHK(g, hipStreamSynchronize(g->s));
+    d->tau = (double)g->step * G.dtau;
+    d->step = g->step;
+    d->n_particles = n;
+    d->field_energy = 0.5 * res[0] * G.V;
+    d->charge_grid = g->cfg.deposit_rho ? res[1] * G.V : 0.0;
+    d->continuity_rel = g->cfg.deposit_rho && res[3] > 0 ? std::sqrt(res[2]) / std::sqrt(res[3]) : 0.0;
+    d->charge_particles = G.qw * (double)np;
+    return GEMPIC_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+static int check_errors(gempic* g) {
+  int e = 0;
+  HIPCHK(g, hipMemcpyAsync(&e, g->err_dev, sizeof(int), hipMemcpyDeviceToHost, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  if (e & ERR_CFL) return fail(g, GEMPIC_ECFL, "a particle crossed more than one cell in a step");
+  if (e & ERR_NUMERIC) return fail(g, GEMPIC_ENUMERIC, "non-finite particle momentum");
+  if (e & ERR_CAPACITY) return fail(g, GEMPIC_ECAPACITY, "particle buffer capacity exceeded");
+  if (e & ERR_TILE) return fail(g, GEMPIC_EDEVICE, "internal: particle outside its tile");
+  return GEMPIC_OK;
+}
+
+static int validate(const gempic_config* c, Geom* G, std::string* why) {
+  if (c->abi_version != GEMPIC_ABI_VERSION) { *why = "abi_version mismatch"; return GEMPIC_EABI; }
+  if (c->dims != 2 && c->dims != 3) { *why = "dims must be 2 or 3"; return GEMPIC_EINVAL; }
+  if (!(c->length_unit > 0)) { *why = "length_unit must be > 0"; return GEMPIC_EINVAL; }
+  if (c->precision != GEMPIC_FP64 && c->precision != GEMPIC_FP32_CELL) { *why = "unknown precision"; return GEMPIC_EINVAL; }
+  if (c->filter_passes < 0 || c->filter_passes > 2) { *why = "filter_passes must be 0, 1 or 2"; return GEMPIC_EINVAL; }
+  double lu = c->length_unit;
+  G->dims = c->dims;
+  G->Nx = c->n[0];
+  G->Ny = c->dims == 3 ? c->n[1] : 1;
+  G->Nz = c->n[2];
+  if (!pow2(G->Nx) || !pow2(G->Nz) || !pow2(G->Ny) || G->Nx < 2 || G->Nz < 2 || (c->dims == 3 && G->Ny < 2)) {
+    *why = "grid sizes must be powers of two (>= 2)";
+    return GEMPIC_EINVAL;
+  }
+  G->Tx = c->tile[0];
+  G->Ty = c->dims == 3 ? c->tile[1] : 1;
+  G->Tz = c->tile[2];
+  if (G->Tx < 1 || G->Ty < 1 || G->Tz < 1 || G->Nx % G->Tx || G->Ny % G->Ty || G->Nz % G->Tz ||
+      G->Tx > 32 || G->Ty > 32 || G->Tz > 32) {
+    *why = "tile must divide the grid (1 .. 32 cells per axis)";
+    return GEMPIC_EINVAL;
+  }
+  G->hx = c->d[0] * lu;
+  G->hy = c->dims == 3 ? c->d[1] * lu : 1.0;
+  G->h = c->d[2] * lu;
+  if (!(G->hx > 0 && G->hy > 0 && G->h > 0)) { *why = "grid steps must be > 0"; return GEMPIC_EINVAL; }
+  G->dtau = c->dtau * lu;
+  if (G->dtau == 0.0) G->dtau = 0.5 * G->h;
+  if (!(G->dtau > 0)) { *why = "dtau must be >= 0"; return GEMPIC_EINVAL; }
+  if (2.0 * G->dtau > G->h * (1.0 + 1e-12)) { *why = "slow step too large: need 2 dtau <= h"; return GEMPIC_ECFL; }
+  if (c->n_e < 0) { *why = "n_e must be >= 0"; return GEMPIC_EINVAL; }
+  if (c->n_e > 0.0 && G->dtau * G->h > 4.0 / c->n_e) { *why = "slow step violates Delta*h <= 4/omega_p^2"; return GEMPIC_ECFL; }
+  if (c->ppc[0] < 1 || c->ppc[2] < 1 || (c->dims == 3 && c->ppc[1] < 1)) { *why = "ppc must be >= 1"; return GEMPIC_EINVAL; }
+  if (c->pol != 0 && c->pol != 1) { *why = "pol must be 0 or 1"; return GEMPIC_EINVAL; }
+  G->P = c->filter_passes;
+  G->ext = G->P + 3;
+  G->Nzp = G->Nz + G->ext;
+  G->NPJ = G->Nz + G->ext + 4;
+  G->NPF = G->Nz + 3 + G->P;
+  G->nTx = G->Nx / G->Tx;
+  G->nTy = G->Ny / G->Ty;
+  G->nTz = (G->Nzp + G->Tz - 1) / G->Tz;
+  G->NT = G->nTx * G->nTy * G->nTz;
+  G->Nxh = G->Nx / 2;
+  if ((int64_t)G->Nzp * G->Ny * G->Nx >= (1ll << 31)) { *why = "grid too large for int32 cells"; return GEMPIC_EINVAL; }
+  return GEMPIC_OK;
+}
+
+extern "C" {
+
+const char* gempic_strerror(int code) {
+  switch (code) {
+    case GEMPIC_OK: return "ok";
+    case GEMPIC_EINVAL: return "invalid argument";
+    case GEMPIC_ENOMEM: return "out of device memory";
+    case GEMPIC_EDEVICE: return "device error";
+    case GEMPIC_ECFL: return "slow step too large (more than one cell crossing)";
+    case GEMPIC_ENUMERIC: return "non-finite value";
+    case GEMPIC_ESTATE: return "call not allowed in this state";
+    case GEMPIC_EABI: return "ABI version mismatch";
+    case GEMPIC_ECAPACITY: return "particle capacity exceeded";
+    default: return "unknown error";
+  }
+}
+
+const char* gempic_last_error(const gempic_t* g) {
+  return g ? g->err.c_str() : g_create_error.c_str();
+}
+
+void gempic_destroy(gempic_t* g) {
+  if (!g) return;
+  if (g->s) (void)hipStreamSynchronize(g->s);
+  g->dev.release();
+  delete g;
+}
+
+int gempic_create(const gempic_config* cfg, gempic_t** out) {
+  if (!out) { g_create_error = "out is NULL"; return GEMPIC_EINVAL; }
+  *out = nullptr;
+  if (!cfg) { g_create_error = "cfg is NULL"; return GEMPIC_EINVAL; }
+  Geom G;
+  std::memset(&G, 0, sizeof(G));
+  std::string why;
+  int rc = validate(cfg, &G, &why);
+  if (rc) { g_create_error = why; return rc; }
+  gempic* g = new gempic();
+  g->cfg = *cfg;
+  g->s = (hipStream_t)cfg->stream;
+  g->prec = cfg->precision == GEMPIC_FP64 ? 0 : 1;
+  g->esz = g->prec == 0 ? 8 : 4;
+  g->ppcx = cfg->ppc[0];
+  g->ppcy = cfg->dims == 3 ? cfg->ppc[1] : 1;
+  g->ppcz = cfg->ppc[2];
+  g->quiet = cfg->load == 1;
+  g->key = sm_mix(cfg->seed ^ (0ull << 56));
+  double lu = cfg->length_unit;
+  int ppc = g->ppcx * g->ppcy * g->ppcz;
+  double hy_eff = G.dims == 3 ? G.hy : 1.0;
+  g->w = cfg->n_e * G.hx * hy_eff * G.h / (double)ppc;
+  G.qw = -1.0 * g->w;
+  G.V = G.hx * hy_eff * G.h;
+  g->L = (double)(G.Nz - 1 + G.ext) * G.h;
+  g->hz = G.h / (double)g->ppcz;
+  double fwhm = cfg->fwhm * lu;
+  g->Tlas = fwhm > 0 ? fwhm / std::sqrt(2.0 * std::log(2.0)) : 0.0;
+  g->zeta_c = std::isnan(cfg->zeta_c) ? (double)(G.Nz - 1) * G.h - 2.0 * g->Tlas : cfg->zeta_c * lu;
+  g->waist = cfg->waist * lu;
+  if (cfg->a0 != 0.0 && !(g->Tlas > 0)) { delete g; g_create_error = "laser needs fwhm > 0"; return GEMPIC_EINVAL; }
+  g->g = G;
+  g->step = 0;
+  g->failed = false;
+  g->cur = 0;
+  g->ctc = 0;
+
+  // capacities
+  int64_t ncell_p = (int64_t)G.Nzp * G.Ny * G.Nx;
+  int64_t n0 = cfg->n_e > 0 ? ncell_p * ppc : 0;
+  g->capacity = n0 + n0 / 4 + 4096;
+  g->max_nm = (int64_t)std::ceil(G.dtau * g->ppcz / G.h) + 5;
+  g->stage_per_tile = g->max_nm * G.Ty * G.Tx * g->ppcx * g->ppcy;
+  g->max_chunks = (int)(G.NT + g->capacity / GP_CHUNK + 1);
+
+  Dev& d = g->dev;
+  size_t es = g->esz;
+  bool ok = true;
+  auto A = [&](size_t bytes) { void* p = d.alloc(bytes); ok = ok && p; return p; };
+  for (int b = 0; b < 2; ++b) {
+    g->part[b][0] = A(g->capacity * 4);
+    for (int q = 1; q < 7; ++q) g->part[b][q] = (q == 2 && G.dims == 2) ? nullptr : A(g->capacity * es);
+    g->ids[b] = cfg->track_ids ? (int64_t*)A(g->capacity * 8) : nullptr;
+  }
+  int64_t nstage = (int64_t)G.nTx * G.nTy * g->stage_per_tile;
+  g->stage[0] = A(nstage * 4);
+  for (int q = 1; q < 7; ++q) g->stage[q] = (q == 2 && G.dims == 2) ? nullptr : A(nstage * es);
+  g->stage_g = (int32_t*)A(nstage * 4);
+  for (int b = 0; b < 2; ++b) {
+    g->ct[b].tile = (int32_t*)A((size_t)g->max_chunks * 4);
+    g->ct[b].start = (int32_t*)A((size_t)g->max_chunks * 4);
+    g->ct[b].end = (int32_t*)A((size_t)g->max_chunks * 4);
+    g->ct[b].first = (int32_t*)A((size_t)G.NT * 4);
+    g->ct[b].count = (int32_t*)A((size_t)G.NT * 4);
+    g->ct[b].n = (int32_t*)A(4);
+  }
+  g->code = (int32_t*)A(g->capacity * 4);
+  g->counts = (int32_t*)A((size_t)g->max_chunks * NCODE * 4);
+  g->offs = (int32_t*)A((size_t)g->max_chunks * NCODE * 4);
+  g->inj_count = (int32_t*)A((size_t)G.NT * 4);
+  g->inj_off = (int32_t*)A((size_t)G.NT * 4);
+  int64_t ng = g->max_nm * G.Ny * G.Nx * g->ppcx * g->ppcy;
+  g->gflag = cfg->track_ids ? (int32_t*)A(ng * 4) : nullptr;
+  g->grank = cfg->track_ids ? (int32_t*)A(ng * 4) : nullptr;
+  g->tile_count = (int64_t*)A((size_t)G.NT * 8);
+  g->tile_base = (int64_t*)A((size_t)G.NT * 8);
+  g->total = (int64_t*)A(8);
+  g->next_id = (int64_t*)A(8);
+  g->inj_total = (int64_t*)A(8);
+  g->pushed = (int64_t*)A(8);
+  g->err_dev = (int*)A(sizeof(int));
+  int64_t nf = (int64_t)G.Nz * G.Ny * G.Nx;
+  int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+  int64_t nsp = (int64_t)G.Nz * G.Ny * G.Nxh;
+  int64_t nJs = (int64_t)G.NPF * G.Ny * G.Nxh;
+  for (int q = 0; q < 6; ++q) g->F[q] = A(nf * es);
+  for (int q = 0; q < 3; ++q) g->J[q] = A(nJ * es);
+  for (int q = 0; q < 2; ++q) g->rho[q] = cfg->deposit_rho ? A(nJ * es) : nullptr;
+  for (int q = 0; q < 3; ++q) g->Jhat[q] = A(nJs * 2 * es);
+  for (int q = 0; q < 4; ++q) g->st[q] = A(nsp * 2 * es);
+  for (int q = 0; q < 6; ++q) g->outs[q] = A(nsp * 2 * es);
+  for (int q = 0; q < 2; ++q) g->Lsp[q] = A(nsp * 2 * es);
+  g->twx = A((size_t)std::max(1, G.Nx / 2) * 2 * es);
+  g->twy = A((size_t)std::max(1, G.Ny / 2) * 2 * es);
+  g->partial = (double*)A(6 * DIAG_BLOCKS * 8);
+  g->dres = (double*)A(4 * 8);
+  if (!ok) {
+    std::string m = std::string("device allocation failed: ") + hipGetErrorString(d.last);
+    gempic_destroy(g);
+    g_create_error = m;
+    return GEMPIC_ENOMEM;
+  }
+  // twiddles exp(-2 pi i t / N), computed in FP64 on the host
+  auto twiddles = [&](int N, void* dst) -> int {
+    int hN = std::max(1, N / 2);
+    std::vector<double> tw(2 * hN);
+    for (int t = 0; t < hN; ++t) {
+      double a = -2.0 * M_PI * (double)t / (double)N;
+      tw[2 * t] = std::cos(a);
+      tw[2 * t + 1] = std::sin(a);
+    }
+    if (g->prec == 0) return (int)hipMemcpy(dst, tw.data(), tw.size() * 8, hipMemcpyHostToDevice);
+    std::vector<float> f(tw.begin(), tw.end());
+    return (int)hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+  };
+  int e0 = 0;
+  if (twiddles(G.Nx, g->twx) || twiddles(std::max(G.Ny, 2), g->twy) ||
+      hipMemset(g->err_dev, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(g->next_id, 0, 8) != hipSuccess) {
+    gempic_destroy(g);
+    g_create_error = "initial device copies failed";
+    return GEMPIC_EDEVICE;
+  }
+  (void)e0;
+  if (g->prec == 0) Impl<double>::set_lds_limits(); else Impl<float>::set_lds_limits();
+  rc = g->prec == 0 ? Impl<double>::init_state(g) : Impl<float>::init_state(g);
+  if (rc == GEMPIC_OK) rc = check_errors(g);
+  if (rc) {
+    g_create_error = g->err;
+    gempic_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return GEMPIC_OK;
+}
+
+int gempic_step(gempic_t* g, int32_t nsteps, gempic_diag* diag) {
+  if (!g) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  if (nsteps < 0) return fail(g, GEMPIC_EINVAL, "nsteps < 0");
+  for (int k = 0; k < nsteps; ++k) {
+    int rc = g->prec == 0 ? Impl<double>::one_step(g) : Impl<float>::one_step(g);
+    if (rc) return rc;
+  }
+  int rc = check_errors(g);
+  if (rc) return rc;
+  if (diag) {
+    rc = g->prec == 0 ? Impl<double>::diag(g, diag) : Impl<float>::diag(g, diag);
+    if (rc) return rc;
+  }
+  return GEMPIC_OK;
+}
+
+size_t gempic_fields_bytes(const gempic_t* g, uint32_t mask) {
+  if (!g) return 0;
+  const Geom& G = g->g;
+  size_t nf = (size_t)G.Nz * G.Ny * G.Nx, nJ = (size_t)G.NPJ * G.Ny * G.Nx;
+  size_t b = 0;
+  for (int q = 0; q < 10; ++q)
+    if (mask & (1u << q)) b += (q < 6 ? nf : nJ) * g->esz;
+  return b;
+}
+
+int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size_t dst_bytes) {
+  if (!g || !dst) return GEMPIC_EINVAL;
+  if (mask >= (1u << 10)) return fail(g, GEMPIC_EINVAL, "unknown field bits");
+  if (dst_bytes < gempic_fields_bytes(g, mask)) return fail(g, GEMPIC_EINVAL, "dst_bytes too small");
+  if ((mask & GEMPIC_RHO) && !g->cfg.deposit_rho) return fail(g, GEMPIC_EINVAL, "rho needs deposit_rho = 1");
+  const Geom& G = g->g;
+  size_t nf = (size_t)G.Nz * G.Ny * G.Nx, nJ = (size_t)G.NPJ * G.Ny * G.Nx;
+  char* o = (char*)dst;
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int q = 0; q < 10; ++q) {
+    if (!(mask & (1u << q))) continue;
+    const void* src = q < 6 ? g->F[q] : (q < 9 ? g->J[q - 6] : g->rho[1]);
+    size_t bytes = (q < 6 ? nf : nJ) * g->esz;
+    HIPCHK(g, hipMemcpyAsync(o, src, bytes, kind, g->s));
+    o += bytes;
+  }
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
+int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, void* u, int64_t* id,
+                     size_t capacity, size_t* count) {
+  if (!g || !count) return GEMPIC_EINVAL;
+  int64_t n = 0;
+  HIPCHK(g, hipMemcpyAsync(&n, g->total, 8, hipMemcpyDeviceToHost, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  *count = (size_t)n;
+  if ((size_t)n > capacity) return fail(g, GEMPIC_EINVAL, "capacity smaller than the particle count");
+  if (id && !g->ids[0]) return fail(g, GEMPIC_EINVAL, "ids need track_ids = 1");
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  int b = g->cur;
+  size_t es = g->esz;
+  if (cell) HIPCHK(g, hipMemcpyAsync(cell, g->part[b][0], n * 4, kind, g->s));
+  for (int q = 0; q < 3; ++q) {
+    char* o = off ? (char*)off + q * capacity * es : nullptr;
+    char* v = u ? (char*)u + q * capacity * es : nullptr;
+    if (o) {
+      if (g->part[b][1 + q]) HIPCHK(g, hipMemcpyAsync(o, g->part[b][1 + q], n * es, kind, g->s));
+      else if (on_device) HIPCHK(g, hipMemsetAsync(o, 0, n * es, g->s));
+      else std::memset(o, 0, n * es);
+    }
+    if (v) HIPCHK(g, hipMemcpyAsync(v, g->part[b][4 + q], n * es, kind, g->s));
+  }
+  if (id) HIPCHK(g, hipMemcpyAsync(id, g->ids[b], n * 8, kind, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
+int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void* off, const void* u,
+                     const int64_t* id, size_t count, const void* spectral, size_t spectral_bytes) {
+  if (!g) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  const Geom& G = g->g;
+  size_t es = g->esz;
+  int64_t nsp = (int64_t)G.Nz * G.Ny * G.Nxh;
+  if ((int64_t)count > g->capacity) return fail(g, GEMPIC_EINVAL, "count exceeds capacity");
+  if (spectral && spectral_bytes < (size_t)(6 * nsp * 2) * es) return fail(g, GEMPIC_EINVAL, "spectral_bytes too small");
+  if (id && !g->ids[0]) return fail(g, GEMPIC_EINVAL, "ids need track_ids = 1");
+  if (count > 0 && (!cell || !off || !u)) return fail(g, GEMPIC_EINVAL, "particle arrays missing");
+  // tile counts from the cells; the order must already be sorted by tile
+  std::vector<int64_t> cnt(G.NT, 0);
+  int prev = -1;
+  int64_t maxid = -1;
+  for (size_t i = 0; i < count; ++i) {
+    int c = cell[i];
+    if (c < 0 || c >= G.Nzp * G.Ny * G.Nx) return fail(g, GEMPIC_EINVAL, "cell out of range");
+    int ix = c % G.Nx, r = c / G.Nx, iy = r % G.Ny, iz = r / G.Ny;
+    int t = ((iz / G.Tz) * G.nTy + iy / G.Ty) * G.nTx + ix / G.Tx;
+    if (t < prev) return fail(g, GEMPIC_EINVAL, "particles not sorted by tile");
+    prev = t;
+    cnt[t] += 1;
+    if (id) maxid = std::max<int64_t>(maxid, id[i]);
+  }
+  int b = g->cur;
+  HIPCHK(g, hipMemcpyAsync(g->part[b][0], cell, count * 4, hipMemcpyHostToDevice, g->s));
+  for (int q = 0; q < 3; ++q) {
+    if (g->part[b][1 + q])
+      HIPCHK(g, hipMemcpyAsync(g->part[b][1 + q], (const char*)off + q * count * es, count * es,
+                               hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->part[b][4 + q], (const char*)u + q * count * es, count * es,
+                             hipMemcpyHostToDevice, g->s));
+  }
+  if (id) {
+    HIPCHK(g, hipMemcpyAsync(g->ids[b], id, count * 8, hipMemcpyHostToDevice, g->s));
+    int64_t nid = maxid + 1;
+    HIPCHK(g, hipMemcpyAsync(g->next_id, &nid, 8, hipMemcpyHostToDevice, g->s));
+  }
+  HIPCHK(g, hipMemcpyAsync(g->tile_count, cnt.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
+  ChunkTab& t0 = g->ct[g->ctc];
+  k_scan_tiles<<<1, 1024, 0, g->s>>>(G.NT, g->tile_count, g->tile_base, g->total, t0.first, t0.count, t0.n,
+                                      g->capacity, g->err_dev);
+  k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, t0, g->max_chunks);
+  if (spectral) {
+    const char* sp = (const char*)spectral;
+    size_t bytes = (size_t)nsp * 2 * es;
+    // Rx, Ry, Lx, Ly, Ez, Bz -> state (Rx, Ry, Ez, Bz) and L
+    HIPCHK(g, hipMemcpyAsync(g->st[0], sp + 0 * bytes, bytes, hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->st[1], sp + 1 * bytes, bytes, hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->Lsp[0], sp + 2 * bytes, bytes, hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->Lsp[1], sp + 3 * bytes, bytes, hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->st[2], sp + 4 * bytes, bytes, hipMemcpyHostToDevice, g->s));
+    HIPCHK(g, hipMemcpyAsync(g->st[3], sp + 5 * bytes, bytes, hipMemcpyHostToDevice, g->s));
+    if (g->prec == 0) {
+      using C = cplx<double>;
+      k_state_to_fields<double><<<nblk(nsp, 256), 256, 0, g->s>>>(
+          (C*)g->st[0], (C*)g->st[1], (C*)g->Lsp[0], (C*)g->Lsp[1], (C*)g->st[2], (C*)g->st[3],
+          (C*)g->outs[0], (C*)g->outs[1], (C*)g->outs[2], (C*)g->outs[3], (C*)g->outs[4], (C*)g->outs[5], nsp);
+      for (int q = 0; q < 6; ++q) Impl<double>::fft_inv(g, (C*)g->outs[q], (double*)g->F[q], G.Nz);
+    } else {
+      using C = cplx<float>;
+      k_state_to_fields<float><<<nblk(nsp, 256), 256, 0, g->s>>>(
+          (C*)g->st[0], (C*)g->st[1], (C*)g->Lsp[0], (C*)g->Lsp[1], (C*)g->st[2], (C*)g->st[3],
+          (C*)g->outs[0], (C*)g->outs[1], (C*)g->outs[2], (C*)g->outs[3], (C*)g->outs[4], (C*)g->outs[5], nsp);
+      for (int q = 0; q < 6; ++q) Impl<float>::fft_inv(g, (C*)g->outs[q], (float*)g->F[q], G.Nz);
+    }
+  }
+  g->step = step;
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return check_errors(g);
+}
+
+int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes) {
+  if (!g || !fields) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  const Geom& G = g->g;
+  size_t nb = (size_t)G.Nz * G.Ny * G.Nx * g->esz;
+  if (bytes < 6 * nb) return fail(g, GEMPIC_EINVAL, "bytes too small");
+  for (int q = 0; q < 6; ++q)
+    HIPCHK(g, hipMemcpyAsync(g->F[q], (const char*)fields + q * nb, nb, hipMemcpyHostToDevice, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
+int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes) {
+  if (!g || !spectral) return GEMPIC_EINVAL;
+  const Geom& G = g->g;
+  size_t bytes = (size_t)G.Nz * G.Ny * G.Nxh * 2 * g->esz;
+  if (spectral_bytes < 6 * bytes) return fail(g, GEMPIC_EINVAL, "spectral_bytes too small");
+  char* o = (char*)spectral;
+  const void* src[6] = {g->st[0], g->st[1], g->Lsp[0], g->Lsp[1], g->st[2], g->st[3]};
+  for (int q = 0; q < 6; ++q)
+    HIPCHK(g, hipMemcpyAsync(o + q * bytes, src[q], bytes, hipMemcpyDeviceToHost, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,847 @@
+// Particle kernels: loading, window injection, fused gather + push + deposit,
+// and the stable tile sort.
+//
+// Particles are a structure of arrays: int32 linear cell (iz * Ny + iy) * Nx
+// + ix, offsets ox, oy, oz in [0,1) and momenta ux, uy, uz (u = gamma v) in
+// the precision T, optionally an int64 id.  They are kept sorted by tile
+// (tiles of Tx x Ty x Tz cells, tile index (tz * nTy + ty) * nTx + tx), stable
+// within a tile; each tile's range is cut into chunks of at most GP_CHUNK
+// particles, one work-group per chunk.
+#pragma once
+#include "common.h"
+
+template <typename T>
+struct PartPtrs {
+  int32_t* cell;
+  T* ox;
+  T* oy;
+  T* oz;
+  T* ux;
+  T* uy;
+  T* uz;
+  int64_t* id;   // nullable
+};
+
+struct ChunkTab {
+  int32_t* tile;    // [max_chunks] tile of each chunk
+  int32_t* start;   // [max_chunks]
+  int32_t* end;     // [max_chunks]
+  int32_t* first;   // [NT] first chunk of each tile
+  int32_t* count;   // [NT] chunks of each tile
+  int32_t* n;       // [1] number of chunks
+};
+
+template <typename T> GP_DEV T one_minus();
+template <> GP_DEV float one_minus<float>() { return 0x1.fffffep-1f; }
+template <> GP_DEV double one_minus<double>() { return 0x1.fffffffffffffp-1; }
+
+// Offset computed in FP64, stored in T; a value that rounds to 1 stays below.
+template <typename T> GP_DEV T store_offset(double d) {
+  T t = (T)d;
+  return t < (T)1 ? t : one_minus<T>();
+}
+
+// ---------------------------------------------------------------------------
+// Loading: every lattice particle of the full cells 0 .. Nzp - 2 of one tile,
+// written at tile_base[t] in (m, j, i, sy, sx) order.  Sub-row m of lab z has
+// particles at z offset (m % ppc_z + xi_z) / ppc_z in cell m / ppc_z.
+struct LoadArgs {
+  Geom g;
+  int ppcx, ppcy, ppcz;
+  int quiet;
+  uint64_t key;
+  const int64_t* tile_base;
+};
+
+template <typename T>
+__global__ void k_load_full(LoadArgs a, PartPtrs<T> P) {
+  const Geom& g = a.g;
+  int t = blockIdx.x;
+  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  int x0 = tx * g.Tx, y0 = ty * g.Ty, z0 = tz * g.Tz;
+  int zend = min(z0 + g.Tz, g.Nzp - 1);
+  if (zend <= z0) return;
+  int ppxy = a.ppcx * a.ppcy;
+  int64_t m_first = (int64_t)z0 * a.ppcz;
+  int64_t n_local = (int64_t)(zend - z0) * a.ppcz * g.Ty * g.Tx * ppxy;
+  int64_t base = a.tile_base[t];
+  for (int64_t l = threadIdx.x; l < n_local; l += blockDim.x) {
+    int s = (int)(l % ppxy);
+    int64_t r = l / ppxy;
+    int il = (int)(r % g.Tx); r /= g.Tx;
+    int jl = (int)(r % g.Ty); r /= g.Ty;
+    int64_t m = m_first + r;
+    int sx = s % a.ppcx, sy = s / a.ppcx;
+    int i = x0 + il, j = y0 + jl;
+    uint64_t gidx = ((((uint64_t)m * g.Ny + j) * g.Nx + i) * a.ppcy + sy) * a.ppcx + sx;
+    double xix = a.quiet ? 0.5 : sm_uniform(a.key, gidx * 3 + 0);
+    double xiz = a.quiet ? 0.5 : sm_uniform(a.key, gidx * 3 + 2);
+    double dx = fmin(((double)sx + xix) / (double)a.ppcx, 0x1.fffffffffffffp-1);
+    double dz = fmin(((double)(m % a.ppcz) + xiz) / (double)a.ppcz, 0x1.fffffffffffffp-1);
+    double dy = 0.0;
+    if (g.dims == 3) {
+      double xiy = a.quiet ? 0.5 : sm_uniform(a.key, gidx * 3 + 1);
+      dy = fmin(((double)sy + xiy) / (double)a.ppcy, 0x1.fffffffffffffp-1);
+    }
+    int iz = (int)(m / a.ppcz);
+    int64_t o = base + l;
+    P.cell[o] = (iz * g.Ny + j) * g.Nx + i;
+    P.ox[o] = store_offset<T>(dx);
+    if (g.dims == 3) P.oy[o] = store_offset<T>(dy);
+    P.oz[o] = store_offset<T>(dz);
+    P.ux[o] = (T)0;
+    P.uy[o] = (T)0;
+    P.uz[o] = (T)0;
+    if (P.id) P.id[o] = (int64_t)gidx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Window batch b: lattice particles with lo <= z_m < hi (no lower bound for
+// b = 0) among sub-rows m_lo .. m_hi, placed at zeta = z_m - b dtau in the
+// entry cell.  One work-group per transverse tile; candidates in
+// (m, j, i, sy, sx) order restricted to the tile, compacted with a block scan
+// into the staging area of the tile.
+struct InjArgs {
+  Geom g;
+  int ppcx, ppcy, ppcz;
+  int quiet;
+  uint64_t key;
+  int b;              // batch index
+  int64_t m_lo, m_hi;
+  double lo, hi, hz, shift;   // thresholds, sub-row length, b * dtau
+  int64_t stage_per_tile;
+  int32_t* inj_count;   // [NT], written for the entry-row tiles
+  int32_t* stage_g;     // [nTx * nTy * stage_per_tile] generation index
+  int32_t* gflag;       // nullable: [Ny * Nx * ppc * nm] selection flags (ids)
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject(InjArgs a, PartPtrs<T> S) {
+  const Geom& g = a.g;
+  __shared__ int wsum[8];
+  __shared__ int running;
+  int tt = blockIdx.x;                         // transverse tile index ty * nTx + tx
+  int tx = tt % g.nTx, ty = tt / g.nTx;
+  int x0 = tx * g.Tx, y0 = ty * g.Ty;
+  int ppxy = a.ppcx * a.ppcy;
+  int64_t nm = a.m_hi - a.m_lo + 1;
+  int64_t ncand = nm * g.Ty * g.Tx * ppxy;
+  int64_t sbase = (int64_t)tt * a.stage_per_tile;
+  if (threadIdx.x == 0) running = 0;
+  __syncthreads();
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t row = 0; row < ncand; row += blockDim.x) {
+    int64_t l = row + threadIdx.x;
+    bool sel = false;
+    double dx = 0, dy = 0, dz = 0;
+    int iz = 0, i = 0, j = 0;
+    int64_t gidx = 0;
+    if (l < ncand) {
+      int s = (int)(l % ppxy);
+      int64_t r = l / ppxy;
+      int il = (int)(r % g.Tx); r /= g.Tx;
+      int jl = (int)(r % g.Ty); r /= g.Ty;
+      int64_t m = a.m_lo + r;
+      int sx = s % a.ppcx, sy = s / a.ppcx;
+      i = x0 + il;
+      j = y0 + jl;
+      uint64_t lat = ((((uint64_t)m * g.Ny + j) * g.Nx + i) * a.ppcy + sy) * a.ppcx + sx;
+      double xiz = a.quiet ? 0.5 : sm_uniform(a.key, lat * 3 + 2);
+      double z = ((double)m + xiz) * a.hz;
+      sel = z < a.hi && (a.b == 0 || z >= a.lo);
+      gidx = ((r * g.Ny + j) * g.Nx + i) * ppxy + s;
+      if (a.gflag) a.gflag[gidx] = sel ? 1 : 0;
+      if (sel) {
+        double xix = a.quiet ? 0.5 : sm_uniform(a.key, lat * 3 + 0);
+        dx = fmin(((double)sx + xix) / (double)a.ppcx, 0x1.fffffffffffffp-1);
+        if (g.dims == 3) {
+          double xiy = a.quiet ? 0.5 : sm_uniform(a.key, lat * 3 + 1);
+          dy = fmin(((double)sy + xiy) / (double)a.ppcy, 0x1.fffffffffffffp-1);
+        }
+        double zeta = z - a.shift;
+        double sz = zeta / g.h;
+        double fz = floor(sz);
+        dz = sz - fz;
+        iz = (int)fz;
+        if (iz < g.Nzp - 1) { iz = g.Nzp - 1; dz = 0.0; }
+      }
+    }
+    // block-wide exclusive scan of sel, in candidate order
+    uint64_t bal = __ballot(sel);
+    int wrank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    int off = running;
+    for (int w = 0; w < wid; ++w) off += wsum[w];
+    if (sel) {
+      int64_t o = sbase + off + wrank;
+      S.cell[o] = (iz * g.Ny + j) * g.Nx + i;
+      S.ox[o] = store_offset<T>(dx);
+      if (g.dims == 3) S.oy[o] = store_offset<T>(dy);
+      S.oz[o] = store_offset<T>(dz);
+      S.ux[o] = (T)0;
+      S.uy[o] = (T)0;
+      S.uz[o] = (T)0;
+      a.stage_g[o] = (int32_t)gidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+      running += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int t = ((g.nTz - 1) * g.nTy + ty) * g.nTx + tx;
+    a.inj_count[t] = running;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused gather + push + move + deposit, one work-group per chunk.
+//
+// Gather: linear weights on the 8 (3-D) / 4 (2-D) nodes around the particle,
+// staged in LDS for the tile's (T+1)^3 nodes; zeta nodes >= Nz carry zero.
+// Push: Higuera-Cary, eps = (q/m) dtau / 2.  Move: offsets advance by
+// v dtau / h_axis, zeta by (v_z - 1) dtau / h with the cancellation-free
+// v_z - 1; cell steps beyond one raise ERR_CFL.
+// Deposit: Esirkepov frame current W on the staggered grid plus the time- and
+// zeta-centred charge for the lab J_z, accumulated in an LDS tile of
+// (Tx+3) x (Ty+3) x (Tz+4) nodes per component (origin x0-1, y0-1, node
+// z0-2) and added to the global arrays with one atomic per non-zero node.
+// The arithmetic of gather, push and move follows a fixed operation order
+// (FP64 results are reproducible bit for bit).
+template <typename T>
+struct PushArgs {
+  Geom g;
+  const T* F[6];       // Ex Ey Ez Bx By Bz, [Nz][Ny][Nx]
+  T* J[3];             // [NPJ][Ny][Nx]
+  T* rho0;             // nullable: charge before the move
+  T* rho1;             // nullable: charge after the move
+  T eps;               // (q/m) dtau / 2
+  T ax, ay, az;        // dtau / hx, dtau / hy, dtau / h
+  T cx, cy, cz;        // -q w / (dtau hy h), -q w / (dtau hx h), -q w / (dtau hx hy) (2-D: hy = 1)
+  T cjy;               // 2-D out-of-plane: q w / (hx h)
+  T crho;              // q w / V
+  ChunkTab ct;
+  int* err;
+};
+
+template <typename T> GP_DEV void lds_add(T* p, T v) {
+  if (v != (T)0) atomicAdd(p, v);
+}
+
+template <typename T>
+GP_DEV void window3(int k, T d0, T d1, T* S0, T* S1) {
+  // 3-node window starting at min(c0, c0 + k)
+  int off0 = k < 0 ? 1 : 0;
+  int off1 = k > 0 ? 1 : 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S0[a] = (a == off0 ? (T)1 - d0 : (T)0) + (a == off0 + 1 ? d0 : (T)0);
+    S1[a] = (a == off1 ? (T)1 - d1 : (T)0) + (a == off1 + 1 ? d1 : (T)0);
+  }
+}
+
+template <typename T, int DIM, bool RHO>
+__global__ __launch_bounds__(256) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
+  const Geom& g = a.g;
+  int c = blockIdx.x;
+  if (c >= *a.ct.n) return;
+  int t = a.ct.tile[c];
+  int p0 = a.ct.start[c], p1 = a.ct.end[c];
+  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  int x0 = tx * g.Tx, y0 = ty * g.Ty, z0 = tz * g.Tz;
+  const int FX = g.Tx + 1, FY = DIM == 3 ? g.Ty + 1 : 1, FZ = g.Tz + 1;
+  const int FN = FX * FY * FZ;
+  const int JX = g.Tx + 3, JY = DIM == 3 ? g.Ty + 3 : 1, JZ = g.Tz + 4;
+  const int JN = JX * JY * JZ;
+  const int RX = g.Tx + 3, RY = DIM == 3 ? g.Ty + 3 : 1, RZ = g.Tz + 2;   // rho: origin (x0-1, y0-1, node z0-1)
+  const int RN = RX * RY * RZ;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sF = reinterpret_cast<T*>(smem_raw);
+  T* sJ = sF + 6 * FN;
+  T* sR = sJ + 3 * JN;
+
+  for (int idx = threadIdx.x; idx < FN; idx += blockDim.x) {
+    int lx = idx % FX, r = idx / FX;
+    int ly = r % FY, lz = r / FY;
+    int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
+    int gy = y0 + ly; if (gy >= g.Ny) gy -= g.Ny;
+    int gz = z0 + lz;
+    size_t gi = ((size_t)gz * g.Ny + gy) * g.Nx + gx;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sF[q * FN + idx] = gz < g.Nz ? a.F[q][gi] : (T)0;
+  }
+  for (int idx = threadIdx.x; idx < 3 * JN + (RHO ? 2 * RN : 0); idx += blockDim.x) sJ[idx] = (T)0;
+  __syncthreads();
+
+  const T third = (T)1 / (T)3;
+  for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+    int cell = P.cell[p];
+    int ix = cell % g.Nx;
+    int r = cell / g.Nx;
+    int iy = r % g.Ny;
+    int iz = r / g.Ny;
+    int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+    if (lx < 0 || lx >= g.Tx || ly < 0 || ly >= (DIM == 3 ? g.Ty : 1) || lz < 0 || lz >= g.Tz) {
+      atomicOr(a.err, ERR_TILE);
+      continue;
+    }
+    T dx0 = P.ox[p], dz0 = P.oz[p];
+    T dy0 = DIM == 3 ? P.oy[p] : (T)0;
+    T ux = P.ux[p], uy = P.uy[p], uz = P.uz[p];
+
+    // gather
+    T wx[2] = {(T)1 - dx0, dx0};
+    T wz[2] = {(T)1 - dz0, dz0};
+    T wy[2] = {(T)1 - dy0, dy0};
+    T f[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+      for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+          T w = DIM == 3 ? (wx[aa] * wy[b]) * wz[cc] : wx[aa] * wz[cc];
+          int li = ((lz + cc) * FY + (ly + b)) * FX + (lx + aa);
+#pragma unroll
+          for (int q = 0; q < 6; ++q) f[q] = f[q] + w * sF[q * FN + li];
+        }
+      }
+    }
+
+    // Higuera-Cary push
+    T eps = a.eps;
+    T umx = ux + eps * f[0];
+    T umy = uy + eps * f[1];
+    T umz = uz + eps * f[2];
+    T bx = eps * f[3], by = eps * f[4], bz = eps * f[5];
+    T um2 = (umx * umx + umy * umy) + umz * umz;
+    T b2 = (bx * bx + by * by) + bz * bz;
+    T sigma = ((T)1 + um2) - b2;
+    T bu = (bx * umx + by * umy) + bz * umz;
+    T gp = sqrt((sigma + sqrt(sigma * sigma + (T)4 * (b2 + bu * bu))) * (T)0.5);
+    T tx_ = bx / gp, ty_ = by / gp, tz_ = bz / gp;
+    T s = (T)1 / ((T)1 + ((tx_ * tx_ + ty_ * ty_) + tz_ * tz_));
+    T ut = (umx * tx_ + umy * ty_) + umz * tz_;
+    T upx = s * ((umx + ut * tx_) + (umy * tz_ - umz * ty_));
+    T upy = s * ((umy + ut * ty_) + (umz * tx_ - umx * tz_));
+    T upz = s * ((umz + ut * tz_) + (umx * ty_ - umy * tx_));
+    ux = (upx + eps * f[0]) + (upy * tz_ - upz * ty_);
+    uy = (upy + eps * f[1]) + (upz * tx_ - upx * tz_);
+    uz = (upz + eps * f[2]) + (upx * ty_ - upy * tx_);
+
+    // move
+    T uperp2 = ux * ux + uy * uy;
+    T gam = sqrt((T)1 + (uperp2 + uz * uz));
+    T vx = ux / gam, vy = uy / gam;
+    T vzm1 = uz >= (T)0 ? -((T)1 + uperp2) / (gam * (gam + uz)) : uz / gam - (T)1;
+    T tnx = dx0 + vx * a.ax;
+    T kxf = floor(tnx);
+    T dx1 = tnx - kxf;
+    int kx = (int)kxf;
+    if (dx1 >= (T)1) { dx1 = (T)0; kx += 1; }
+    T dy1 = (T)0;
+    int ky = 0;
+    if (DIM == 3) {
+      T tny = dy0 + vy * a.ay;
+      T kyf = floor(tny);
+      dy1 = tny - kyf;
+      ky = (int)kyf;
+      if (dy1 >= (T)1) { dy1 = (T)0; ky += 1; }
+    }
+    T tnz = dz0 + vzm1 * a.az;
+    T kzf = floor(tnz);
+    T dz1 = tnz - kzf;
+    int kz = (int)kzf;
+    if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
+    if (!(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
+    if (kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 1) {
+      atomicOr(a.err, ERR_CFL);
+      continue;
+    }
+    int nix = ix + kx; if (nix < 0) nix += g.Nx; if (nix >= g.Nx) nix -= g.Nx;
+    int niy = iy + ky; if (niy < 0) niy += g.Ny; if (niy >= g.Ny) niy -= g.Ny;
+    int niz = iz + kz;
+    P.cell[p] = (niz * g.Ny + niy) * g.Nx + nix;
+    P.ox[p] = dx1;
+    if (DIM == 3) P.oy[p] = dy1;
+    P.oz[p] = dz1;
+    P.ux[p] = ux;
+    P.uy[p] = uy;
+    P.uz[p] = uz;
+
+    // deposit
+    T S0x[3], S1x[3], S0z[3], S1z[3], S0y[3], S1y[3];
+    window3<T>(kx, dx0, dx1, S0x, S1x);
+    window3<T>(kz, dz0, dz1, S0z, S1z);
+    if (DIM == 3) window3<T>(ky, dy0, dy1, S0y, S1y);
+    T DSx[3], DSy[3], DSz[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      DSx[q] = S1x[q] - S0x[q];
+      DSz[q] = S1z[q] - S0z[q];
+      DSy[q] = DIM == 3 ? S1y[q] - S0y[q] : (T)0;
+    }
+    // local J-tile coordinates of the window origin
+    int jx0 = lx + min(kx, 0) + 1;
+    int jy0 = DIM == 3 ? ly + min(ky, 0) + 1 : 0;
+    int jz0 = lz + min(kz, 0) + 2;       // node base_z
+    T* sJx = sJ;
+    T* sJy = sJ + JN;
+    T* sJz = sJ + 2 * JN;
+    if (DIM == 3) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          T acc = (T)0;
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa) {
+            acc = acc + DSx[aa] * (S0y[b] * S0z[cc] + (T)0.5 * DSy[b] * S0z[cc] +
+                                   (T)0.5 * S0y[b] * DSz[cc] + third * DSy[b] * DSz[cc]);
+            lds_add(&sJx[((jz0 + cc) * JY + (jy0 + b)) * JX + (jx0 + aa)], a.cx * acc);
+          }
+        }
+      }
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          T acc = (T)0;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc = acc + DSy[b] * (S0x[aa] * S0z[cc] + (T)0.5 * DSx[aa] * S0z[cc] +
+                                  (T)0.5 * S0x[aa] * DSz[cc] + third * DSx[aa] * DSz[cc]);
+            lds_add(&sJy[((jz0 + cc) * JY + (jy0 + b)) * JX + (jx0 + aa)], a.cy * acc);
+          }
+        }
+      }
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          T w0 = (T)0, w1 = (T)0;   // W_zeta prefix on half-nodes base+1/2, base+3/2
+          T e0 = S0x[aa] * S0y[b] + (T)0.5 * DSx[aa] * S0y[b] + (T)0.5 * S0x[aa] * DSy[b] +
+                 third * DSx[aa] * DSy[b];
+          w0 = DSz[0] * e0;
+          w1 = w0 + DSz[1] * e0;
+          T t0 = S0x[aa] * S0y[b];
+          T t1 = S1x[aa] * S1y[b];
+          // half-nodes n + 1/2, n = base - 1 .. base + 2  (e = 0 .. 3)
+          T r0 = (T)0.25 * a.crho * (t0 * S0z[0] + t1 * S1z[0]);
+          T r1 = (T)0.25 * a.crho * (t0 * (S0z[0] + S0z[1]) + t1 * (S1z[0] + S1z[1]));
+          T r2 = (T)0.25 * a.crho * (t0 * (S0z[1] + S0z[2]) + t1 * (S1z[1] + S1z[2]));
+          T r3 = (T)0.25 * a.crho * (t0 * S0z[2] + t1 * S1z[2]);
+          int base = ((jz0 - 1) * JY + (jy0 + b)) * JX + (jx0 + aa);
+          lds_add(&sJz[base], r0);
+          lds_add(&sJz[base + JY * JX], r1 + a.cz * w0);
+          lds_add(&sJz[base + 2 * JY * JX], r2 + a.cz * w1);
+          lds_add(&sJz[base + 3 * JY * JX], r3);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        T acc = (T)0;
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa) {
+          acc = acc + DSx[aa] * (S0z[cc] + (T)0.5 * DSz[cc]);
+          lds_add(&sJx[(jz0 + cc) * JX + (jx0 + aa)], a.cx * acc);
+        }
+      }
+      T cyv = a.cjy * vy;
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          T wt = S0x[aa] * S0z[cc] + (T)0.5 * DSx[aa] * S0z[cc] + (T)0.5 * S0x[aa] * DSz[cc] +
+                 third * DSx[aa] * DSz[cc];
+          lds_add(&sJy[(jz0 + cc) * JX + (jx0 + aa)], cyv * wt);
+        }
+      }
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+        T e0 = S0x[aa] + (T)0.5 * DSx[aa];
+        T w0 = DSz[0] * e0;
+        T w1 = w0 + DSz[1] * e0;
+        T t0 = S0x[aa], t1 = S1x[aa];
+        T r0 = (T)0.25 * a.crho * (t0 * S0z[0] + t1 * S1z[0]);
+        T r1 = (T)0.25 * a.crho * (t0 * (S0z[0] + S0z[1]) + t1 * (S1z[0] + S1z[1]));
+        T r2 = (T)0.25 * a.crho * (t0 * (S0z[1] + S0z[2]) + t1 * (S1z[1] + S1z[2]));
+        T r3 = (T)0.25 * a.crho * (t0 * S0z[2] + t1 * S1z[2]);
+        int base = (jz0 - 1) * JX + (jx0 + aa);
+        lds_add(&sJz[base], r0);
+        lds_add(&sJz[base + JX], r1 + a.cz * w0);
+        lds_add(&sJz[base + 2 * JX], r2 + a.cz * w1);
+        lds_add(&sJz[base + 3 * JX], r3);
+      }
+    }
+    if (RHO) {
+      // charge before and after the move, rho tile origin (x0-1, y0-1, node z0-1)
+      T* sR0 = sR;
+      T* sR1 = sR + RN;
+      int oy = DIM == 3 ? 1 : 0;
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+        for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b)
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa) {
+            T w0 = DIM == 3 ? wx[aa] * (b ? dy0 : (T)1 - dy0) * wz[cc] : wx[aa] * wz[cc];
+            lds_add(&sR0[((lz + 1 + cc) * RY + (ly + oy + b)) * RX + (lx + 1 + aa)], a.crho * w0);
+            T vx1 = aa ? dx1 : (T)1 - dx1;
+            T vz1 = cc ? dz1 : (T)1 - dz1;
+            T w1 = DIM == 3 ? vx1 * (b ? dy1 : (T)1 - dy1) * vz1 : vx1 * vz1;
+            int lx1 = lx + kx, ly1 = ly + ky, lz1 = lz + kz;
+            lds_add(&sR1[((lz1 + 1 + cc) * RY + (ly1 + oy + b)) * RX + (lx1 + 1 + aa)], a.crho * w1);
+          }
+    }
+  }
+  __syncthreads();
+
+  // flush the J tile: global x = x0 - 1 + jx, y = y0 - 1 + jy, plane = z0 + jz
+  for (int idx = threadIdx.x; idx < 3 * JN; idx += blockDim.x) {
+    T v = sJ[idx];
+    if (v == (T)0) continue;
+    int q = idx / JN, l = idx % JN;
+    int jx = l % JX, rr = l / JX;
+    int jy = rr % JY, jz = rr / JY;
+    int plane = z0 + jz;
+    if (plane >= g.NPJ) continue;
+    int gx = x0 - 1 + jx; if (gx < 0) gx += g.Nx; if (gx >= g.Nx) gx -= g.Nx;
+    int gy = DIM == 3 ? y0 - 1 + jy : 0; if (gy < 0) gy += g.Ny; if (gy >= g.Ny) gy -= g.Ny;
+    atomicAdd(&a.J[q][((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
+  }
+  if (RHO) {
+    for (int idx = threadIdx.x; idx < 2 * RN; idx += blockDim.x) {
+      T v = sR[idx];
+      if (v == (T)0) continue;
+      int q = idx / RN, l = idx % RN;
+      int rx = l % RX, rr = l / RX;
+      int ry = rr % RY, rz = rr / RY;
+      int plane = z0 - 1 + rz + 2;
+      if (plane < 0 || plane >= g.NPJ) continue;
+      int gx = x0 - 1 + rx; if (gx < 0) gx += g.Nx; if (gx >= g.Nx) gx -= g.Nx;
+      int gy = DIM == 3 ? y0 - 1 + ry : 0; if (gy < 0) gy += g.Ny; if (gy >= g.Ny) gy -= g.Ny;
+      T* dst = q == 0 ? a.rho0 : a.rho1;
+      atomicAdd(&dst[((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable sort by tile, step 1: destination code and rank of every particle of
+// a chunk among the chunk's particles with the same code (array order).
+GP_DEV int tile_step(int src, int dst, int n) {
+  // step from source to destination tile index along a periodic axis of n tiles
+  int d = dst - src;
+  if (d < 0) d += n;
+  if (d == 0) return 0;
+  if (d == 1) return 1;
+  if (d == n - 1) return -1;
+  return 99;
+}
+
+struct SortArgs {
+  Geom g;
+  ChunkTab ct;
+  const int32_t* cell;
+  int32_t* code;        // [N] code << 24 | rank
+  int32_t* counts;      // [max_chunks * NCODE]
+  int* err;
+};
+
+__global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
+  const Geom& g = a.g;
+  __shared__ int wcnt[4][NCODE];
+  __shared__ int run[NCODE];
+  int c = blockIdx.x;
+  if (c >= *a.ct.n) return;
+  int t = a.ct.tile[c];
+  int p0 = a.ct.start[c], p1 = a.ct.end[c];
+  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x < NCODE) {
+    run[threadIdx.x] = 0;
+    for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0;
+  }
+  __syncthreads();
+  for (int row = p0; row < p1; row += blockDim.x) {
+    int p = row + threadIdx.x;
+    int code = -1;
+    if (p < p1) {
+      int cell = a.cell[p];
+      int ix = cell % g.Nx, r = cell / g.Nx;
+      int iy = r % g.Ny, iz = r / g.Ny;
+      if (cell < 0) {
+        code = CODE_REMOVED;
+      } else {
+        int sx = tile_step(tx, ix / g.Tx, g.nTx);
+        int sy = tile_step(ty, iy / g.Ty, g.nTy);
+        int sz = iz / g.Tz - tz;
+        if (sx == 99 || sy == 99 || sz < -1 || sz > 0) {
+          atomicOr(a.err, ERR_TILE);
+          code = CODE_REMOVED;
+        } else {
+          code = (sz + 1) * 9 + (sy + 1) * 3 + (sx + 1);
+        }
+      }
+    }
+    // rank among equal codes within the wave
+    int myrank = 0;
+    uint64_t active = __ballot(code >= 0);
+    uint64_t lt = (1ull << lane) - 1ull;
+    while (active) {
+      int leader = __ffsll((unsigned long long)active) - 1;
+      int lc = __shfl(code, leader);
+      uint64_t m = __ballot(code == lc);
+      if (code == lc) myrank = __popcll(m & lt);
+      if (lane == 0) wcnt[wid][lc] = __popcll(m);
+      active &= ~m;
+    }
+    __syncthreads();
+    if (code >= 0) {
+      int rk = run[code] + myrank;
+      for (int w = 0; w < wid; ++w) rk += wcnt[w][code];
+      a.code[p] = (code << 24) | rk;
+    }
+    __syncthreads();
+    if (threadIdx.x < NCODE) {
+      int s = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { s += wcnt[w][threadIdx.x]; wcnt[w][threadIdx.x] = 0; }
+      run[threadIdx.x] += s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NCODE) a.counts[c * NCODE + threadIdx.x] = run[threadIdx.x];
+}
+
+// Step 2: per destination tile, offsets of every (source chunk, code) group in
+// array order (source tiles ascending, chunks ascending), then the injected
+// particles; writes the new tile counts.
+struct OffArgs {
+  Geom g;
+  ChunkTab ct;              // old chunk table
+  const int32_t* counts;    // [chunks * NCODE]
+  int32_t* offs;            // [chunks * NCODE]
+  const int32_t* inj_count; // [NT]
+  int32_t* inj_off;         // [NT]
+  int64_t* tile_count;      // [NT]
+};
+
+__global__ void k_tile_offsets(OffArgs a) {
+  const Geom& g = a.g;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.NT) return;
+  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  int src[18], cod[18];
+  int ns = 0;
+  for (int sz = 0; sz >= -1; --sz) {          // source row tz - sz  (dest = source + sz)
+    int szr = tz - sz;
+    if (szr >= g.nTz) continue;
+    for (int sy = -1; sy <= 1; ++sy) {
+      for (int sx = -1; sx <= 1; ++sx) {
+        int sxt = tx - sx; sxt = ((sxt % g.nTx) + g.nTx) % g.nTx;
+        int syt = ty - sy; syt = ((syt % g.nTy) + g.nTy) % g.nTy;
+        // canonical step from this source to t
+        int cx = tile_step(sxt, tx, g.nTx), cy = tile_step(syt, ty, g.nTy);
+        if (cx != sx || cy != sy) continue;     // duplicate of another step
+        int s = (szr * g.nTy + syt) * g.nTx + sxt;
+        src[ns] = s;
+        cod[ns] = (sz + 1) * 9 + (sy + 1) * 3 + (sx + 1);
+        ++ns;
+      }
+    }
+  }
+  // sort sources by index (insertion sort)
+  for (int i = 1; i < ns; ++i) {
+    int s = src[i], c = cod[i], j = i - 1;
+    while (j >= 0 && src[j] > s) { src[j + 1] = src[j]; cod[j + 1] = cod[j]; --j; }
+    src[j + 1] = s; cod[j + 1] = c;
+  }
+  int64_t run = 0;
+  for (int i = 0; i < ns; ++i) {
+    int f = a.ct.first[src[i]], n = a.ct.count[src[i]];
+    for (int k = 0; k < n; ++k) {
+      int ci = (f + k) * NCODE + cod[i];
+      a.offs[ci] = (int32_t)run;
+      run += a.counts[ci];
+    }
+  }
+  a.inj_off[t] = (int32_t)run;
+  run += a.inj_count[t];
+  a.tile_count[t] = run;
+}
+
+// Step 3 (single work-group): exclusive scans of the tile counts (-> tile base,
+// total) and of the chunks per tile (-> chunk first, number of chunks).
+__global__ __launch_bounds__(1024) void k_scan_tiles(int NT, const int64_t* tile_count,
+                                                     int64_t* tile_base, int64_t* total,
+                                                     int32_t* ch_first, int32_t* ch_count,
+                                                     int32_t* nchunks, int64_t capacity,
+                                                     int* err) {
+  __shared__ int64_t sa[1024];
+  __shared__ int64_t sb[1024];
+  int tid = threadIdx.x;
+  int per = (NT + 1023) / 1024;
+  int i0 = tid * per, i1 = min(NT, i0 + per);
+  int64_t s1 = 0, s2 = 0;
+  for (int i = i0; i < i1; ++i) {
+    int64_t n = tile_count[i];
+    s1 += n;
+    s2 += (n + GP_CHUNK - 1) / GP_CHUNK;
+  }
+  sa[tid] = s1;
+  sb[tid] = s2;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t va = tid >= o ? sa[tid - o] : 0;
+    int64_t vb = tid >= o ? sb[tid - o] : 0;
+    __syncthreads();
+    sa[tid] += va;
+    sb[tid] += vb;
+    __syncthreads();
+  }
+  int64_t r1 = tid ? sa[tid - 1] : 0, r2 = tid ? sb[tid - 1] : 0;
+  for (int i = i0; i < i1; ++i) {
+    int64_t n = tile_count[i];
+    tile_base[i] = r1;
+    int nc = (int)((n + GP_CHUNK - 1) / GP_CHUNK);
+    ch_first[i] = (int32_t)r2;
+    ch_count[i] = nc;
+    r1 += n;
+    r2 += nc;
+  }
+  if (tid == 1023) {
+    *total = sa[1023];
+    *nchunks = (int32_t)sb[1023];
+    // over capacity: no chunk is processed any more (the error is reported)
+    if (sa[1023] > capacity) { atomicOr(err, ERR_CAPACITY); *nchunks = 0; *total = 0; }
+  }
+}
+
+// Step 4: chunk table of the sorted array.
+__global__ void k_build_chunks(int NT, const int64_t* tile_base, const int64_t* tile_count,
+                               ChunkTab ct, int max_chunks) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NT) return;
+  int f = ct.first[t], n = ct.count[t];
+  int64_t b = tile_base[t], e = b + tile_count[t];
+  for (int k = 0; k < n; ++k) {
+    int c = f + k;
+    if (c >= max_chunks) return;
+    ct.tile[c] = t;
+    ct.start[c] = (int32_t)(b + (int64_t)k * GP_CHUNK);
+    ct.end[c] = (int32_t)min(e, b + (int64_t)(k + 1) * GP_CHUNK);
+  }
+}
+
+// Step 5: scatter the chunk's particles to their sorted positions.
+template <typename T>
+struct ScatArgs {
+  Geom g;
+  ChunkTab ct;              // old chunk table
+  const int32_t* code;
+  const int32_t* offs;
+  const int64_t* tile_base; // new
+  int64_t capacity;
+  int* err;
+};
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_scatter(ScatArgs<T> a, PartPtrs<T> A, PartPtrs<T> B) {
+  const Geom& g = a.g;
+  int c = blockIdx.x;
+  if (c >= *a.ct.n) return;
+  int t = a.ct.tile[c];
+  int p0 = a.ct.start[c], p1 = a.ct.end[c];
+  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+    int cr = a.code[p];
+    int code = cr >> 24, rank = cr & 0xFFFFFF;
+    if (code == CODE_REMOVED) continue;
+    int sz = code / 9 - 1, sy = (code / 3) % 3 - 1, sx = code % 3 - 1;
+    int dx = tx + sx; if (dx < 0) dx += g.nTx; if (dx >= g.nTx) dx -= g.nTx;
+    int dy = ty + sy; if (dy < 0) dy += g.nTy; if (dy >= g.nTy) dy -= g.nTy;
+    int dz = tz + sz;
+    int dt = (dz * g.nTy + dy) * g.nTx + dx;
+    int64_t o = a.tile_base[dt] + a.offs[c * NCODE + code] + rank;
+    if (o >= a.capacity) { atomicOr(a.err, ERR_CAPACITY); continue; }
+    B.cell[o] = A.cell[p];
+    B.ox[o] = A.ox[p];
+    if (DIM == 3) B.oy[o] = A.oy[p];
+    B.oz[o] = A.oz[p];
+    B.ux[o] = A.ux[p];
+    B.uy[o] = A.uy[p];
+    B.uz[o] = A.uz[p];
+    if (B.id) B.id[o] = A.id[p];
+  }
+}
+
+// Step 6: staged window particles after every particle already in their tile.
+struct InjCopyArgs {
+  Geom g;
+  const int32_t* inj_count;  // [NT]
+  const int32_t* inj_off;    // [NT]
+  const int64_t* tile_base;
+  int64_t stage_per_tile;
+  const int32_t* stage_g;
+  const int32_t* grank;      // nullable: exclusive scan of the generation flags
+  const int64_t* next_id;    // nullable
+  int64_t capacity;
+  int* err;
+};
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_inject_copy(InjCopyArgs a, PartPtrs<T> S, PartPtrs<T> B) {
+  const Geom& g = a.g;
+  int tt = blockIdx.x;
+  int tx = tt % g.nTx, ty = tt / g.nTx;
+  int t = ((g.nTz - 1) * g.nTy + ty) * g.nTx + tx;
+  int n = a.inj_count[t];
+  int64_t sb = (int64_t)tt * a.stage_per_tile;
+  int64_t db = a.tile_base[t] + a.inj_off[t];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    int64_t s = sb + k, o = db + k;
+    if (o >= a.capacity) { atomicOr(a.err, ERR_CAPACITY); continue; }
+    B.cell[o] = S.cell[s];
+    B.ox[o] = S.ox[s];
+    if (DIM == 3) B.oy[o] = S.oy[s];
+    B.oz[o] = S.oz[s];
+    B.ux[o] = S.ux[s];
+    B.uy[o] = S.uy[s];
+    B.uz[o] = S.uz[s];
+    if (B.id) B.id[o] = *a.next_id + a.grank[a.stage_g[s]];
+  }
+}
+
+// Exclusive scan of int32 flags (single work-group), total added to *acc.
+__global__ __launch_bounds__(1024) void k_scan_flags(int64_t n, const int32_t* in, int32_t* out,
+                                                     int64_t* acc_total) {
+  __shared__ int64_t sa[1024];
+  int tid = threadIdx.x;
+  int64_t per = (n + 1023) / 1024;
+  int64_t i0 = tid * per, i1 = min(n, i0 + per);
+  int64_t s = 0;
+  for (int64_t i = i0; i < i1; ++i) s += in[i];
+  sa[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t v = tid >= o ? sa[tid - o] : 0;
+    __syncthreads();
+    sa[tid] += v;
+    __syncthreads();
+  }
+  int64_t r = tid ? sa[tid - 1] : 0;
+  for (int64_t i = i0; i < i1; ++i) {
+    int32_t v = in[i];
+    out[i] = (int32_t)r;
+    r += v;
+  }
+  __syncthreads();
+  if (tid == 1023 && acc_total) *acc_total += sa[1023];
+}

@@ -1,0 +1,249 @@
+"""Thin ctypes binding of the gfx950 Galilean PIC library (include/gempic.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+The functions keep the C names (gempic_create, gempic_step, gempic_fields,
+gempic_particles, gempic_set_state, gempic_get_spectral, gempic_destroy);
+``Sim`` wraps a handle for tests and the benchmark.  PyTorch is optional and
+only supplies device buffers and the current stream.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libgempic.so")
+
+ABI_VERSION = 1
+FP64, FP32_CELL = 0, 1
+EX, EY, EZ, BX, BY, BZ, JX, JY, JZ, RHO = (1 << i for i in range(10))
+FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
+
+STATUS = {0: "GEMPIC_OK", -1: "GEMPIC_EINVAL", -2: "GEMPIC_ENOMEM", -3: "GEMPIC_EDEVICE",
+          -4: "GEMPIC_ECFL", -5: "GEMPIC_ENUMERIC", -6: "GEMPIC_ESTATE", -7: "GEMPIC_EABI",
+          -8: "GEMPIC_ECAPACITY"}
+
+
+class GempicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gempic_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32), ("dims", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+        ("d", ctypes.c_double * 3), ("length_unit", ctypes.c_double), ("dtau", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("n_e", ctypes.c_double),
+        ("ppc", ctypes.c_int32 * 3), ("load", ctypes.c_int32), ("a0", ctypes.c_double),
+        ("waist", ctypes.c_double), ("fwhm", ctypes.c_double), ("zeta_c", ctypes.c_double),
+        ("pol", ctypes.c_int32), ("seed", ctypes.c_uint64), ("filter_passes", ctypes.c_int32),
+        ("track_ids", ctypes.c_int32), ("deposit_rho", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+class gempic_diag(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double), ("step", ctypes.c_int64), ("n_particles", ctypes.c_int64),
+        ("charge_particles", ctypes.c_double), ("charge_grid", ctypes.c_double),
+        ("field_energy", ctypes.c_double), ("continuity_rel", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+# exported symbols and their signatures (argument marshalling only)
+_SIGS = {
+    "gempic_create": (ctypes.c_int, [ctypes.POINTER(gempic_config), ctypes.POINTER(ctypes.c_void_p)]),
+    "gempic_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(gempic_diag)]),
+    "gempic_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_size_t]),
+    "gempic_fields_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32]),
+    "gempic_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "gempic_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.c_size_t]),
+    "gempic_get_spectral": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "gempic_set_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "gempic_destroy": (None, [ctypes.c_void_p]),
+    "gempic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "gempic_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load the in-tree HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, handle=None):
+    if rc != 0:
+        msg = lib().gempic_last_error(handle)
+        raise GempicError(rc, msg.decode() if msg else "")
+
+
+def make_config(cfg, stream=None, track_ids=False, deposit_rho=False):
+    """Workload dict (see workloads.py) -> gempic_config."""
+    c = gempic_config()
+    c.abi_version = ABI_VERSION
+    c.dims = int(cfg["dims"])
+    c.n[:] = [int(v) for v in cfg["n"]]
+    c.d[:] = [float(v) for v in cfg["d"]]
+    c.length_unit = float(cfg.get("length_unit", 1.0))
+    c.dtau = float(cfg.get("dtau", 0.0))
+    prec = cfg.get("precision", "fp32")
+    if prec not in ("fp64", "fp32"):
+        raise ValueError(f"precision {prec!r} not supported by the library")
+    c.precision = FP64 if prec == "fp64" else FP32_CELL
+    c.tile[:] = [int(v) for v in cfg.get("tile", (8, 8, 8))]
+    c.n_e = float(cfg.get("n_e", 0.0))
+    c.ppc[:] = [int(v) for v in cfg.get("ppc", (1, 1, 1))]
+    c.load = int(cfg.get("load", 0))
+    c.a0 = float(cfg.get("a0", 0.0))
+    c.waist = float(cfg.get("waist", 0.0))
+    c.fwhm = float(cfg.get("fwhm", 0.0))
+    zc = cfg.get("zeta_c", None)
+    c.zeta_c = math.nan if zc is None else float(zc)
+    c.pol = int(cfg.get("pol", 0))
+    c.seed = int(cfg.get("seed", 0))
+    c.filter_passes = int(cfg.get("filter_passes", 1))
+    c.track_ids = int(bool(track_ids))
+    c.deposit_rho = int(bool(deposit_rho))
+    c.stream = stream
+    return c
+
+
+def gempic_create(cfg):
+    h = ctypes.c_void_p()
+    _check(lib().gempic_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def gempic_step(h, n, want_diag=False):
+    d = gempic_diag() if want_diag else None
+    _check(lib().gempic_step(h, int(n), ctypes.byref(d) if d is not None else None), h)
+    return d
+
+
+def gempic_fields(h, mask, on_device, dst_ptr, nbytes):
+    _check(lib().gempic_fields(h, mask, int(on_device), dst_ptr, nbytes), h)
+
+
+def gempic_particles(h, on_device, cell, off, u, ids, capacity):
+    cnt = ctypes.c_size_t()
+    _check(lib().gempic_particles(h, int(on_device), cell, off, u, ids, capacity, ctypes.byref(cnt)), h)
+    return cnt.value
+
+
+def gempic_set_state(h, step, cell, off, u, ids, count, spectral, spectral_bytes):
+    _check(lib().gempic_set_state(h, int(step), cell, off, u, ids, count, spectral, spectral_bytes), h)
+
+
+def gempic_get_spectral(h, dst, nbytes):
+    _check(lib().gempic_get_spectral(h, dst, nbytes), h)
+
+
+def gempic_set_fields(h, src, nbytes):
+    _check(lib().gempic_set_fields(h, src, nbytes), h)
+
+
+def gempic_destroy(h):
+    lib().gempic_destroy(h)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Sim:
+    """One handle.  Host-side getters return numpy arrays."""
+
+    def __init__(self, cfg, stream=None, track_ids=False, deposit_rho=False):
+        self.cfg = dict(cfg)
+        self.c = make_config(cfg, stream, track_ids, deposit_rho)
+        self.h = gempic_create(self.c)
+        self.dtype = np.float64 if self.c.precision == FP64 else np.float32
+        self.dims = self.c.dims
+        self.Nx, self.Nz = self.c.n[0], self.c.n[2]
+        self.Ny = self.c.n[1] if self.dims == 3 else 1
+        self.P = self.c.filter_passes
+        self.NPJ = self.Nz + self.P + 7
+
+    def close(self):
+        if self.h:
+            gempic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1, diag=False):
+        d = gempic_step(self.h, n, diag)
+        if d is None:
+            return None
+        return {f: getattr(d, f) for f, _ in gempic_diag._fields_}
+
+    def fields(self, names=("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+        out = {}
+        for nm in names:
+            bit = 1 << FIELD_NAMES.index(nm)
+            planes = self.Nz if bit < JX else self.NPJ
+            a = np.empty((planes, self.Ny, self.Nx), self.dtype)
+            gempic_fields(self.h, bit, 0, _ptr(a), a.nbytes)
+            out[nm] = a
+        return out
+
+    def particles(self, ids=False):
+        cap = self._count()
+        cell = np.empty(cap, np.int32)
+        off = np.empty((3, cap), self.dtype)
+        u = np.empty((3, cap), self.dtype)
+        idv = np.empty(cap, np.int64) if ids else None
+        n = gempic_particles(self.h, 0, _ptr(cell), _ptr(off), _ptr(u), _ptr(idv), cap)
+        r = dict(cell=cell[:n], off=off[:, :n], u=u[:, :n])
+        if ids:
+            r["id"] = idv[:n]
+        return r
+
+    def _count(self):
+        cnt = ctypes.c_size_t()
+        rc = lib().gempic_particles(self.h, 0, None, None, None, None, 0, ctypes.byref(cnt))
+        if rc not in (0, -1):
+            _check(rc, self.h)
+        return cnt.value
+
+    def spectral(self):
+        nxh = self.Nx // 2
+        a = np.empty((6, self.Nz, self.Ny, nxh), np.complex128 if self.dtype == np.float64 else np.complex64)
+        gempic_get_spectral(self.h, _ptr(a), a.nbytes)
+        return a
+
+    def set_fields(self, F6):
+        a = np.ascontiguousarray(F6, self.dtype)
+        gempic_set_fields(self.h, _ptr(a), a.nbytes)
+
+    def set_state(self, step, cell, off, u, spectral, ids=None):
+        cell = np.ascontiguousarray(cell, np.int32)
+        off = np.ascontiguousarray(off, self.dtype)
+        u = np.ascontiguousarray(u, self.dtype)
+        ct = np.complex128 if self.dtype == np.float64 else np.complex64
+        sp = None if spectral is None else np.ascontiguousarray(spectral, ct)
+        idv = None if ids is None else np.ascontiguousarray(ids, np.int64)
+        gempic_set_state(self.h, step, _ptr(cell), _ptr(off), _ptr(u), _ptr(idv), len(cell),
+                         _ptr(sp), 0 if sp is None else sp.nbytes)

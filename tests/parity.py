@@ -1,0 +1,60 @@
+"""Helpers shared by the GPU parity tests (no tests here).  They convert the
+oracle's state to the library's layout and measure agreement; they do no
+arithmetic of the method."""
+import numpy as np
+
+from oracle.plasma import Particles
+
+SPEC_NAMES = ("Rx", "Ry", "Lx", "Ly", "Ez", "Bz")
+FIELDS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+
+
+def oracle_particles(o):
+    P, p = o.P, o.p
+    cell = ((P.iz * p.Ny + P.iy) * p.Nx + P.ix).astype(np.int64)
+    return cell, np.stack([P.dx, P.dy, P.dz]), np.stack([P.ux, P.uy, P.uz]), P.pid
+
+
+def oracle_half_spectrum(o):
+    nxh = o.p.Nx // 2
+    return np.stack([getattr(o.state, nm)[:, :, :nxh] for nm in SPEC_NAMES])
+
+
+def upload(gpu, o, with_fields=False):
+    """Give the GPU handle the oracle's particles and spectral state."""
+    cell, off, u, pid = oracle_particles(o)
+    gpu.set_state(o.k, cell, off, u, oracle_half_spectrum(o), ids=pid)
+    if with_fields:
+        gpu.set_fields(o.F[:, :o.p.Nz])
+
+
+def gpu_particles_to_oracle(p, d, dtype=np.float64):
+    cell = d["cell"].astype(np.int64)
+    ix = cell % p.Nx
+    iy = (cell // p.Nx) % p.Ny
+    iz = cell // (p.Nx * p.Ny)
+    off, u = d["off"].astype(dtype), d["u"].astype(dtype)
+    return Particles(ix=ix, iy=iy, iz=iz, dx=off[0], dy=off[1], dz=off[2], ux=u[0], uy=u[1],
+                     uz=u[2], pid=d.get("id", np.zeros(len(cell), np.int64)))
+
+
+def rel_errors(ref, got, floor=1e-6):
+    """Relative L2 error per component; a component whose reference norm is
+    below floor times the largest component norm is measured against the
+    largest norm instead."""
+    norms = {k: np.linalg.norm(np.asarray(ref[k], np.float64)) for k in ref}
+    big = max(norms.values()) if norms else 0.0
+    out = {}
+    for k in ref:
+        n = norms[k] if norms[k] >= floor * big else big
+        d = np.linalg.norm(np.asarray(got[k], np.float64) - np.asarray(ref[k], np.float64))
+        out[k] = d / n if n > 0 else d
+    return out
+
+
+def oracle_fields(o):
+    return {nm: o.F[c, :o.p.Nz] for c, nm in enumerate(FIELDS)}
+
+
+def oracle_currents(o, nplanes):
+    return {"Jx": o.J[0][:nplanes], "Jy": o.J[1][:nplanes], "Jz": o.J[2][:nplanes]}

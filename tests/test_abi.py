@@ -1,0 +1,83 @@
+"""The C-ABI library builds for gfx950, loads, exports every function that
+include/gempic.h declares, and rejects invalid configurations before touching
+a device (so these run on the CPU)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import workloads
+from paper_2509_16793_amd import gempic as gp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gempic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gempic_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "gempic_create" in names and "gempic_step" in names
+    L = gp.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding marshals each of them
+    assert set(names) <= set(gp._SIGS)
+
+
+def test_struct_layout_matches_header():
+    # offsets follow C alignment rules; the stream pointer is the last member
+    c = gp.gempic_config
+    assert c.stream.offset % 8 == 0
+    assert ctypes.sizeof(c) == c.stream.offset + 8
+    assert ctypes.sizeof(gp.gempic_diag) == 56
+
+
+def _create(cfg, **kw):
+    c = gp.make_config(cfg)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    h = ctypes.c_void_p()
+    rc = gp.lib().gempic_create(ctypes.byref(c), ctypes.byref(h))
+    return rc, h
+
+
+def test_rejects_too_large_slow_step():
+    cfg = workloads.lwfa2d_fp64()
+    cfg["dtau"] = 0.04          # > h / 2 = 0.025 (config units)
+    rc, h = _create(cfg)
+    assert rc == -4 and not h.value
+    assert b"2 dtau" in gp.lib().gempic_last_error(None)
+
+
+def test_rejects_stability_bound():
+    cfg = workloads.lwfa2d_fp64()
+    cfg["n_e"] = 1e6            # Delta * h > 4 / omega_p^2
+    rc, _ = _create(cfg)
+    assert rc == -4
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("abi_version", 99, -7), ("dims", 4, -1), ("precision", 7, -1), ("filter_passes", 3, -1)])
+def test_rejects_bad_fields(field, value, code):
+    rc, _ = _create(workloads.lwfa2d_fp64(), **{field: value})
+    assert rc == code
+
+
+def test_rejects_non_power_of_two_and_bad_tile():
+    cfg = workloads.lwfa2d_fp64()
+    cfg["n"] = [60, 1, 256]
+    assert _create(cfg)[0] == -1
+    cfg = workloads.lwfa2d_fp64()
+    cfg["tile"] = [6, 1, 8]
+    assert _create(cfg)[0] == -1
+
+
+def test_strerror():
+    for code in range(0, -9, -1):
+        assert gp.lib().gempic_strerror(code)
