@@ -1,0 +1,146 @@
+"""Benchmark of the Galilean PIC step on one MI355X.
+
+Workload: the 3-D LWFA setup -- 256 x 256 x 512 cells, dx = dy = 0.4,
+dzeta = 0.05 (laser wavelengths), n_e = 0.001 n_c, 2 particles per cell
+(67,108,864 electrons plus window inflow), a0 = 2 laser, FP32 cell + offset
+particles -- synthetic and seeded.  One step = gather + push + deposit, stable
+sort + window injection, and the field update (FFT, march, inverse FFT).
+
+Prints one JSON line.  value = particle updates per second of the
+gather + push + deposit kernel (HIP events around its launches, on the stream
+the library runs on); ms_per_step = wall time per whole step over the timed
+region.  roofline = that kernel's algorithmic bytes (2 x 28 B particle state,
+24 B of fields and 12 B of current per cell) per launch over its average
+duration, against 8 TB/s.  cpu_baseline = the FP64 CPU oracle's gather + push
++ deposit on a bounded crop of the same workload, timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle updates/s (gather+push+deposit), % HBM roofline; 1ppc+CNN vs 16ppc"
+HBM_PEAK_GBS = 8000.0
+STATE_BYTES = 28          # int32 cell + 3 x FP32 offset + 3 x FP32 momentum
+
+
+def algorithmic_bytes_per_update(ppc):
+    """Particle state read + written once, 6 FP32 fields read once per cell,
+    3 FP32 currents written once per cell."""
+    return 2 * STATE_BYTES + (24.0 + 12.0) / ppc
+
+
+def cpu_baseline(seconds_budget=30.0):
+    """FP64 oracle gather + push + deposit on a 32 x 32 x 512 transverse crop of
+    the workload (same steps, density, ppc; laser waist scaled to the crop)."""
+    import numpy as np
+    import workloads
+    from oracle.sim import Simulation
+    from oracle.push import push_and_move
+    from oracle.deposit import deposit
+
+    cfg = workloads.lwfa3d_fp32()
+    cfg["n"] = [32, 32, 512]
+    cfg["precision"] = "fp64"
+    cfg["waist"] = 2.0
+    s = Simulation(cfg)
+    p = s.p
+    done = 0
+    t_used = 0.0
+    steps = 0
+    P = s.P
+    while steps < 3 and t_used < seconds_budget:
+        t0 = time.perf_counter()
+        old, st, vy = push_and_move(p, P, s.F)
+        deposit(p, old, (P.ix, P.iy, P.iz, P.dx, P.dy, P.dz), st, vy)
+        t_used += time.perf_counter() - t0
+        done += len(P)
+        steps += 1
+        P = P.take(P.iz >= 0)          # particles that left the box (untimed)
+    return {"value": done / t_used, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy oracle, gather+push+deposit, {steps} steps of a "
+                      f"32x32x512 crop of the workload ({len(s.P)} particles), single thread",
+            "seconds": t_used}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2509_16793_amd.gempic import Sim
+
+    torch.cuda.init()
+    dev = torch.cuda.current_device()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    cfg = workloads.lwfa3d_fp32()
+    ppc = cfg["ppc"][0] * cfg["ppc"][1] * cfg["ppc"][2]
+    sim = Sim(cfg, stream=stream)
+    print(f"[bench] created {cfg['n']} ppc={ppc}", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    n0 = sim._count()
+    print(f"[bench] warmup {args.warmup} steps done, {n0} particles", file=sys.stderr, flush=True)
+
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph, nt = sim.get_timing()
+    n1 = sim._count()
+    print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+
+    n_avg = 0.5 * (n0 + n1)
+    push_s = ph["push_deposit"] / 1e3
+    value = n_avg * args.steps / push_s
+    launch_s = push_s / args.steps
+    bpu = algorithmic_bytes_per_update(ppc)
+    achieved = n_avg * bpu / launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": (t1 - t0) * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "lwfa3d_fp32: 3-D LWFA 256x256x512, dx=dy=0.4, dzeta=0.05 "
+                               "(lambda_L), n_e=0.001 n_c, 2 ppc, a0=2, waist 8, FWHM 8, "
+                               "FP32 cell+offset particles",
+                   "grid": cfg["n"], "ppc": ppc, "particles": int(n_avg)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push_deposit", "bytes_per_update": bpu,
+                     "avg_launch_ms": launch_s * 1e3},
+        "phase_ms_per_step": {k: v / args.steps for k, v in ph.items()},
+        "step_updates_per_s": n_avg * args.steps / (t1 - t0),
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a crop", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

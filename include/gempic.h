@@ -171,6 +171,16 @@ int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes);
 /* Read the spectral state (same layout as gempic_set_state) into host memory. */
 int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes);
 
+/* Per-phase GPU time measured with HIP events on the handle's stream,
+ * accumulated over the steps taken while enabled (for benchmarks; timing adds
+ * five event records per step).  enable = 1 starts (and resets) the
+ * accumulation, 0 stops it.  Phases of ms[5]: 0 = clearing the current
+ * arrays, 1 = gather + push + deposit kernel, 2 = sort + window injection,
+ * 3 = field update (FFT, march, inverse FFT), 4 = whole step.  *steps = steps
+ * accumulated.  gempic_get_timing synchronises the stream. */
+int gempic_timing(gempic_t* g, int32_t enable);
+int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps);
+
 void gempic_destroy(gempic_t* g);
 
 const char* gempic_strerror(int code);

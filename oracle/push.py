@@ -13,14 +13,15 @@ Higuera-Cary scheme (Phys. Plasmas 24, 052104, 2017), exact for uniform
 E x B drifts.  With eps = (q/m) dtau / 2:
     u-  = u + eps E,  beta = eps B,  sigma = 1 + |u-|^2 - |beta|^2,
     gamma+ = sqrt((sigma + sqrt(sigma^2 + 4 (|beta|^2 + (beta . u-)^2))) / 2),
-    t = beta / gamma+,  s = 1 / (1 + |t|^2),
+    t = beta / gamma+ (as beta times 1/gamma+),  s = 1 / (1 + |t|^2),
     u+ = s (u- + (u- . t) t + u- x t),  u_new = u+ + eps E + u+ x t.
 Position update in cell units:
     dx += (u_x / gamma) dtau / h_x,   dy += (u_y / gamma) dtau / h_y,
     dzeta += (v_z - 1) dtau / h,
-with v_z - 1 = -(1 + u_x^2 + u_y^2) / (gamma (gamma + u_z)) when u_z >= 0 and
-u_z / gamma - 1 otherwise (the same number, free of cancellation for
-u_z >> 1).
+with v = u (1/gamma) and v_z - 1 = -(1 + u_x^2 + u_y^2) (1/gamma) / (gamma + u_z)
+when u_z >= 0 and u_z (1/gamma) - 1 otherwise (the same number, free of
+cancellation for u_z >> 1).  Divisions are written as one reciprocal each
+where several quotients share a denominator.
 
 Field shape (reading; the paper states none): linear (cloud-in-cell) on the
 nodes.  Fields sit at nodes at level k; the plane n = N_zeta is a ghost plane
@@ -76,9 +77,10 @@ def higuera_cary(ux, uy, uz, E, B, eps):
     sigma = 1.0 + um2 - b2
     bu = bx * umx + by * umy + bz * umz
     gp = np.sqrt((sigma + np.sqrt(sigma * sigma + 4.0 * (b2 + bu * bu))) * 0.5)
-    tx = bx / gp
-    ty = by / gp
-    tz = bz / gp
+    rgp = 1.0 / gp
+    tx = bx * rgp
+    ty = by * rgp
+    tz = bz * rgp
     s = 1.0 / (1.0 + (tx * tx + ty * ty + tz * tz))
     ut = umx * tx + umy * ty + umz * tz
     upx = s * ((umx + ut * tx) + (umy * tz - umz * ty))
@@ -94,9 +96,10 @@ def velocities(ux, uy, uz):
     """Return (gamma, v_x, v_y, v_z - 1)."""
     uperp2 = ux * ux + uy * uy
     g = np.sqrt(1.0 + (uperp2 + uz * uz))
-    vx = ux / g
-    vy = uy / g
-    vzm1 = np.where(uz >= 0.0, -(1.0 + uperp2) / (g * (g + uz)), uz / g - 1.0)
+    rg = 1.0 / g
+    vx = ux * rg
+    vy = uy * rg
+    vzm1 = np.where(uz >= 0.0, (-(1.0 + uperp2) * rg) / (g + uz), uz * rg - 1.0)
     return g, vx, vy, vzm1
 
 

@@ -44,6 +44,7 @@ GP_HD double sm_uniform(uint64_t key, uint64_t counter) {
 struct Geom {
   int dims;
   int Nx, Ny, Nz;        // field grid; Ny = 1 in 2-D
+  int lnx, lny;          // log2 Nx, log2 Ny
   int Nzp;               // particle cells along zeta (Nz + ext)
   int ext;               // plasma cells beyond the last field node
   int P;                 // binomial filter passes

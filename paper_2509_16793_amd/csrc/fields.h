@@ -106,6 +106,60 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(const cplx<T>* in, T* out, in
   }
 }
 
+// Inverse of the x transform for the six field components at once, written
+// as interleaved node records out[row][Nx][6] (scaled by 1/Nx).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_c2r6(const cplx<T>* i0, const cplx<T>* i1, const cplx<T>* i2,
+                                                    const cplx<T>* i3, const cplx<T>* i4, const cplx<T>* i5,
+                                                    T* out, int64_t rows, int Nx, int nseq, const cplx<T>* tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const cplx<T>* in[6] = {i0, i1, i2, i3, i4, i5};
+  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* y = x + 6 * nseq * Nx;
+  int64_t pair0 = (int64_t)blockIdx.x * nseq;
+  int Nxh = Nx >> 1;
+  for (int idx = threadIdx.x; idx < 6 * nseq * Nx; idx += blockDim.x) {
+    int sq6 = idx / Nx, n = idx - sq6 * Nx;
+    int q = sq6 / nseq, sq = sq6 - q * nseq;
+    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
+    cplx<T> z = mk((T)0, (T)0);
+    if (n < Nxh) {
+      cplx<T> A = r0 < rows ? in[q][r0 * Nxh + n] : mk((T)0, (T)0);
+      cplx<T> B = r1 < rows ? in[q][r1 * Nxh + n] : mk((T)0, (T)0);
+      z = A + mul_i(B);
+    } else if (n > Nxh) {
+      int k = Nx - n;
+      cplx<T> A = r0 < rows ? in[q][r0 * Nxh + k] : mk((T)0, (T)0);
+      cplx<T> B = r1 < rows ? in[q][r1 * Nxh + k] : mk((T)0, (T)0);
+      z = conj(A) + mul_i(conj(B));
+    }
+    x[idx] = z;
+  }
+  __syncthreads();
+  cplx<T>* Z = lds_fft(x, y, Nx, 6 * nseq, tw, true);
+  T sc = (T)1 / (T)Nx;
+  for (int idx = threadIdx.x; idx < 6 * nseq * Nx; idx += blockDim.x) {
+    int q = idx % 6, r = idx / 6;
+    int sq = r / Nx, n = r - sq * Nx;
+    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
+    cplx<T> z = Z[(q * nseq + sq) * Nx + n];
+    if (r0 < rows) out[(r0 * Nx + n) * 6 + q] = sc * z.x;
+    if (r1 < rows) out[(r1 * Nx + n) * 6 + q] = sc * z.y;
+  }
+}
+
+// Component q of interleaved node records <-> a plain array.
+template <typename T>
+__global__ void k_deinterleave(const T* rec, T* out, int q, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = rec[6 * i + q];
+}
+template <typename T>
+__global__ void k_interleave(T* rec, const T* in, int q, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rec[6 * i + q] = in[i];
+}
+
 // Transform along y (columns), in place: data[planes][Ny][Nxh]; a work-group
 // takes ncol consecutive kx columns of one plane.  Inverse scales by 1/Ny.
 template <typename T>

@@ -65,7 +65,7 @@ struct gempic {
   int64_t *tile_count, *tile_base, *total, *next_id, *inj_total, *pushed;
   int* err_dev;
   // grids
-  void* F[6];
+  void* F6;          // gather fields: node records [Nz][Ny][Nx][6]
   void* J[3];
   void* rho[2];
   void* Jhat[3];
@@ -76,6 +76,10 @@ struct gempic {
   void* twy;
   double* partial;
   double* dres;
+  // timing: five events per step while enabled
+  bool timing;
+  std::vector<hipEvent_t> ev;
+  int64_t tsteps;
 };
 
 static int fail(gempic* g, int code, const std::string& msg) {
@@ -150,19 +154,23 @@ struct Impl {
                                                                        (const C*)g->twy, 0);
     }
   }
-  static void fft_inv(gempic* g, C* in, T* out, int64_t planes) {
+  // six field spectra (outs) -> interleaved real node records F6
+  static void fft_inv6(gempic* g) {
     const Geom& G = g->g;
     if (G.Ny > 1) {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
       size_t sh2 = 2 * (size_t)ncol * G.Ny * sizeof(C);
-      k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 256, sh2, g->s>>>(in, G.Ny, G.Nxh, ncol,
-                                                                      (const C*)g->twy, 1);
+      for (int q = 0; q < 6; ++q)
+        k_fft_y<T><<<(unsigned)((int64_t)G.Nz * (G.Nxh / ncol)), 256, sh2, g->s>>>(
+            (C*)g->outs[q], G.Ny, G.Nxh, ncol, (const C*)g->twy, 1);
     }
-    int64_t rows = planes * G.Ny;
+    int64_t rows = (int64_t)G.Nz * G.Ny;
     int64_t pairs = (rows + 1) / 2;
-    int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / G.Nx));
-    size_t sh = 2 * (size_t)nseq * G.Nx * sizeof(C);
-    k_fft_x_c2r<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
+    int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / (6 * G.Nx)));
+    size_t sh = 2 * (size_t)6 * nseq * G.Nx * sizeof(C);
+    k_fft_x_c2r6<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(
+        (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
+        (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, G.Nx, nseq, (const C*)g->twx);
   }
 
   // ---- field update: FFT(J) -> march -> iFFT ------------------------------
@@ -181,7 +189,7 @@ struct Impl {
     a.Delta = Delta;
     int64_t M = (int64_t)G.Ny * G.Nxh;
     k_march<T><<<nblk(M, 64), 64, 0, g->s>>>(a);
-    for (int q = 0; q < 6; ++q) fft_inv(g, (C*)g->outs[q], (T*)g->F[q], G.Nz);
+    fft_inv6(g);
   }
 
   // ---- sort + window injection of batch b --------------------------------
@@ -284,7 +292,7 @@ struct Impl {
     const Geom& G = g->g;
     PushArgs<T> a;
     a.g = G;
-    for (int q = 0; q < 6; ++q) a.F[q] = (const T*)g->F[q];
+    a.F6 = (const T*)g->F6;
     for (int q = 0; q < 3; ++q) a.J[q] = (T*)g->J[q];
     a.rho0 = g->cfg.deposit_rho ? (T*)g->rho[0] : nullptr;
     a.rho1 = g->cfg.deposit_rho ? (T*)g->rho[1] : nullptr;
@@ -307,55 +315,81 @@ struct Impl {
       a.cjy = (T)(qw / (G.hx * G.h));
     }
     a.crho = (T)(qw / G.V);
+    // fixed-point scale: every single contribution is bounded by
+    // max(|cx|, |cy|, |cz| + |crho|, |cjy|) and a node of the LDS tile receives
+    // at most one contribution per particle of the chunk.  FP32: a single
+    // contribution below 2^30 (converted through int32); FP64: the worst-case
+    // node sum below 2^61.
+    double cmax = std::max(std::max(std::fabs((double)a.cx), std::fabs((double)a.cy)),
+                           std::max(std::fabs((double)a.cz) + std::fabs((double)a.crho),
+                                    std::fabs((double)a.cjy)));
+    cmax = std::max(cmax, std::fabs((double)a.crho));
+    double lim = sizeof(T) == 4 ? std::ldexp(1.0, 30) : std::ldexp(1.0, 61) / (double)GP_CHUNK;
+    double sc = cmax > 0 ? lim / (cmax * 1.01) : 1.0;
+    int e2 = (int)std::floor(std::log2(sc));
+    a.fscale = (T)std::ldexp(1.0, e2);
+    a.finv = (T)std::ldexp(1.0, -e2);
     a.ct = g->ct[g->ctc];
     a.err = g->err_dev;
     return a;
   }
 
-  static size_t push_lds(const Geom& G, bool rho) {
-    int FY = G.dims == 3 ? G.Ty + 1 : 1, JY = G.dims == 3 ? G.Ty + 3 : 1;
-    size_t FN = (size_t)(G.Tx + 1) * FY * (G.Tz + 1);
-    size_t JN = (size_t)(G.Tx + 3) * JY * (G.Tz + 4);
-    size_t RN = (size_t)(G.Tx + 3) * JY * (G.Tz + 2);
-    return (6 * FN + 3 * JN + (rho ? 2 * RN : 0)) * sizeof(T);
-  }
-
   static void set_lds_limits() {
     int lim = 160 * 1024;
-    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 3, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 3, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_push_deposit<T, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_fft_x_r2c<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)k_fft_x_c2r<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)k_fft_x_c2r6<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_fft_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  }
+
+  template <int DIM, int TX, int TY, int TZ>
+  static void push_tile(gempic* g, const PushArgs<T>& a, PartPtrs<T> P, bool rho) {
+    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ><<<g->max_chunks, 512, 0, g->s>>>(a, P);
+    else k_push_deposit<T, DIM, false, TX, TY, TZ><<<g->max_chunks, 512, 0, g->s>>>(a, P);
   }
 
   static void launch_push(gempic* g) {
     const Geom& G = g->g;
     bool rho = g->cfg.deposit_rho != 0;
     PushArgs<T> a = push_args(g);
-    size_t sh = push_lds(G, rho);
     PartPtrs<T> P = parts(g, g->cur);
     if (G.dims == 3) {
-      if (rho) k_push_deposit<T, 3, true><<<g->max_chunks, 256, sh, g->s>>>(a, P);
-      else k_push_deposit<T, 3, false><<<g->max_chunks, 256, sh, g->s>>>(a, P);
+      if (G.Tx == 8) push_tile<3, 8, 8, 8>(g, a, P, rho);
+      else push_tile<3, 4, 4, 4>(g, a, P, rho);
     } else {
-      if (rho) k_push_deposit<T, 2, true><<<g->max_chunks, 256, sh, g->s>>>(a, P);
-      else k_push_deposit<T, 2, false><<<g->max_chunks, 256, sh, g->s>>>(a, P);
+      if (G.Tx == 8) push_tile<2, 8, 1, 8>(g, a, P, rho);
+      else push_tile<2, 4, 1, 4>(g, a, P, rho);
     }
+  }
+
+  static int mark(gempic* g, int k) {
+    if (!g->timing) return GEMPIC_OK;
+    size_t i = (size_t)g->tsteps * 5 + k;
+    while (g->ev.size() <= i) {
+      hipEvent_t e;
+      HIPCHK(g, hipEventCreate(&e));
+      g->ev.push_back(e);
+    }
+    HIPCHK(g, hipEventRecord(g->ev[i], g->s));
+    return GEMPIC_OK;
   }
 
   static int one_step(gempic* g) {
     const Geom& G = g->g;
     int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+    int rc = mark(g, 0);
+    if (rc) return rc;
     for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
     if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
+    if ((rc = mark(g, 1))) return rc;
     launch_push(g);
+    if ((rc = mark(g, 2))) return rc;
     (void)hipMemcpyAsync(g->pushed, g->total, 8, hipMemcpyDeviceToDevice, g->s);
-    int rc = sort_and_inject(g, g->step + 1);
+    rc = sort_and_inject(g, g->step + 1);
     if (rc) return rc;
+    if ((rc = mark(g, 3))) return rc;
     field_update(g, true, (T)G.dtau);
+    if ((rc = mark(g, 4))) return rc;
+    if (g->timing) g->tsteps += 1;
     g->step += 1;
     return GEMPIC_OK;
   }
@@ -436,9 +470,8 @@ struct Impl {
     HIPCHK(g, hipMemcpyAsync(&n, g->total, 8, hipMemcpyDeviceToHost, g->s));
     HIPCHK(g, hipMemcpyAsync(&np, g->pushed, 8, hipMemcpyDeviceToHost, g->s));
     int64_t nf = (int64_t)G.Nz * G.Ny * G.Nx;
-    k_partial<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->F[0], (const T*)g->F[1], (const T*)g->F[2],
-                                                (const T*)g->F[3], (const T*)g->F[4], (const T*)g->F[5],
-                                                6, nf, 1, g->partial);
+    k_partial<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->F6, nullptr, nullptr, nullptr, nullptr,
+                                                nullptr, 1, 6 * nf, 1, g->partial);
     k_final<<<1, 256, 0, g->s>>>(g->partial, DIAG_BLOCKS, 1, g->dres);
     double res[4] = {0, 0, 0, 0};
     int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
@@ -494,11 +527,13 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->Tx = c->tile[0];
   G->Ty = c->dims == 3 ? c->tile[1] : 1;
   G->Tz = c->tile[2];
-  if (G->Tx < 1 || G->Ty < 1 || G->Tz < 1 || G->Nx % G->Tx || G->Ny % G->Ty || G->Nz % G->Tz ||
-      G->Tx > 32 || G->Ty > 32 || G->Tz > 32) {
-    *why = "tile must divide the grid (1 .. 32 cells per axis)";
+  bool tile_ok = (G->Tx == 8 || G->Tx == 4) && G->Tz == G->Tx && (c->dims == 2 || G->Ty == G->Tx);
+  if (!tile_ok || G->Nx % G->Tx || G->Ny % G->Ty || G->Nz % G->Tz) {
+    *why = "tile must be 8x8x8 or 4x4x4 (2-D: 8x1x8 or 4x1x4) and divide the grid";
     return GEMPIC_EINVAL;
   }
+  G->lnx = 0; while ((1 << G->lnx) < G->Nx) ++G->lnx;
+  G->lny = 0; while ((1 << G->lny) < G->Ny) ++G->lny;
   G->hx = c->d[0] * lu;
   G->hy = c->dims == 3 ? c->d[1] * lu : 1.0;
   G->h = c->d[2] * lu;
@@ -549,6 +584,7 @@ const char* gempic_last_error(const gempic_t* g) {
 void gempic_destroy(gempic_t* g) {
   if (!g) return;
   if (g->s) (void)hipStreamSynchronize(g->s);
+  for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
   g->dev.release();
   delete g;
 }
@@ -588,6 +624,8 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   g->g = G;
   g->step = 0;
   g->failed = false;
+  g->timing = false;
+  g->tsteps = 0;
   g->cur = 0;
   g->ctc = 0;
 
@@ -639,7 +677,7 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
   int64_t nsp = (int64_t)G.Nz * G.Ny * G.Nxh;
   int64_t nJs = (int64_t)G.NPF * G.Ny * G.Nxh;
-  for (int q = 0; q < 6; ++q) g->F[q] = A(nf * es);
+  g->F6 = A(6 * nf * es);
   for (int q = 0; q < 3; ++q) g->J[q] = A(nJ * es);
   for (int q = 0; q < 2; ++q) g->rho[q] = cfg->deposit_rho ? A(nJ * es) : nullptr;
   for (int q = 0; q < 3; ++q) g->Jhat[q] = A(nJs * 2 * es);
@@ -728,7 +766,14 @@ int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size
   hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   for (int q = 0; q < 10; ++q) {
     if (!(mask & (1u << q))) continue;
-    const void* src = q < 6 ? g->F[q] : (q < 9 ? g->J[q - 6] : g->rho[1]);
+    const void* src = q < 6 ? g->outs[0] : (q < 9 ? g->J[q - 6] : g->rho[1]);
+    if (q < 6) {
+      // the fields live as interleaved node records; outs[0] is scratch here
+      if (g->prec == 0)
+        k_deinterleave<double><<<nblk(nf, 256), 256, 0, g->s>>>((const double*)g->F6, (double*)g->outs[0], q, nf);
+      else
+        k_deinterleave<float><<<nblk(nf, 256), 256, 0, g->s>>>((const float*)g->F6, (float*)g->outs[0], q, nf);
+    }
     size_t bytes = (q < 6 ? nf : nJ) * g->esz;
     HIPCHK(g, hipMemcpyAsync(o, src, bytes, kind, g->s));
     o += bytes;
@@ -824,18 +869,43 @@ int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void*
       k_state_to_fields<double><<<nblk(nsp, 256), 256, 0, g->s>>>(
           (C*)g->st[0], (C*)g->st[1], (C*)g->Lsp[0], (C*)g->Lsp[1], (C*)g->st[2], (C*)g->st[3],
           (C*)g->outs[0], (C*)g->outs[1], (C*)g->outs[2], (C*)g->outs[3], (C*)g->outs[4], (C*)g->outs[5], nsp);
-      for (int q = 0; q < 6; ++q) Impl<double>::fft_inv(g, (C*)g->outs[q], (double*)g->F[q], G.Nz);
+      Impl<double>::fft_inv6(g);
     } else {
       using C = cplx<float>;
       k_state_to_fields<float><<<nblk(nsp, 256), 256, 0, g->s>>>(
           (C*)g->st[0], (C*)g->st[1], (C*)g->Lsp[0], (C*)g->Lsp[1], (C*)g->st[2], (C*)g->st[3],
           (C*)g->outs[0], (C*)g->outs[1], (C*)g->outs[2], (C*)g->outs[3], (C*)g->outs[4], (C*)g->outs[5], nsp);
-      for (int q = 0; q < 6; ++q) Impl<float>::fft_inv(g, (C*)g->outs[q], (float*)g->F[q], G.Nz);
+      Impl<float>::fft_inv6(g);
     }
   }
   g->step = step;
   HIPCHK(g, hipStreamSynchronize(g->s));
   return check_errors(g);
+}
+
+int gempic_timing(gempic_t* g, int32_t enable) {
+  if (!g) return GEMPIC_EINVAL;
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  g->timing = enable != 0;
+  if (enable) g->tsteps = 0;
+  return GEMPIC_OK;
+}
+
+int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps) {
+  if (!g || !ms) return GEMPIC_EINVAL;
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  for (int k = 0; k < 5; ++k) ms[k] = 0.0;
+  for (int64_t s = 0; s < g->tsteps; ++s) {
+    float t;
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(g, hipEventElapsedTime(&t, g->ev[s * 5 + k], g->ev[s * 5 + k + 1]));
+      ms[k] += t;
+    }
+    HIPCHK(g, hipEventElapsedTime(&t, g->ev[s * 5], g->ev[s * 5 + 4]));
+    ms[4] += t;
+  }
+  if (steps) *steps = g->tsteps;
+  return GEMPIC_OK;
 }
 
 int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes) {
@@ -844,8 +914,14 @@ int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes) {
   const Geom& G = g->g;
   size_t nb = (size_t)G.Nz * G.Ny * G.Nx * g->esz;
   if (bytes < 6 * nb) return fail(g, GEMPIC_EINVAL, "bytes too small");
-  for (int q = 0; q < 6; ++q)
-    HIPCHK(g, hipMemcpyAsync(g->F[q], (const char*)fields + q * nb, nb, hipMemcpyHostToDevice, g->s));
+  int64_t nf = (int64_t)G.Nz * G.Ny * G.Nx;
+  for (int q = 0; q < 6; ++q) {
+    HIPCHK(g, hipMemcpyAsync(g->outs[0], (const char*)fields + q * nb, nb, hipMemcpyHostToDevice, g->s));
+    if (g->prec == 0)
+      k_interleave<double><<<nblk(nf, 256), 256, 0, g->s>>>((double*)g->F6, (const double*)g->outs[0], q, nf);
+    else
+      k_interleave<float><<<nblk(nf, 256), 256, 0, g->s>>>((float*)g->F6, (const float*)g->outs[0], q, nf);
+  }
   HIPCHK(g, hipStreamSynchronize(g->s));
   return GEMPIC_OK;
 }

@@ -199,339 +199,7 @@ __global__ __launch_bounds__(256) void k_inject(InjArgs a, PartPtrs<T> S) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Fused gather + push + move + deposit, one work-group per chunk.
-//
-// Gather: linear weights on the 8 (3-D) / 4 (2-D) nodes around the particle,
-// staged in LDS for the tile's (T+1)^3 nodes; zeta nodes >= Nz carry zero.
-// Push: Higuera-Cary, eps = (q/m) dtau / 2.  Move: offsets advance by
-// v dtau / h_axis, zeta by (v_z - 1) dtau / h with the cancellation-free
-// v_z - 1; cell steps beyond one raise ERR_CFL.
-// Deposit: Esirkepov frame current W on the staggered grid plus the time- and
-// zeta-centred charge for the lab J_z, accumulated in an LDS tile of
-// (Tx+3) x (Ty+3) x (Tz+4) nodes per component (origin x0-1, y0-1, node
-// z0-2) and added to the global arrays with one atomic per non-zero node.
-// The arithmetic of gather, push and move follows a fixed operation order
-// (FP64 results are reproducible bit for bit).
-template <typename T>
-struct PushArgs {
-  Geom g;
-  const T* F[6];       // Ex Ey Ez Bx By Bz, [Nz][Ny][Nx]
-  T* J[3];             // [NPJ][Ny][Nx]
-  T* rho0;             // nullable: charge before the move
-  T* rho1;             // nullable: charge after the move
-  T eps;               // (q/m) dtau / 2
-  T ax, ay, az;        // dtau / hx, dtau / hy, dtau / h
-  T cx, cy, cz;        // -q w / (dtau hy h), -q w / (dtau hx h), -q w / (dtau hx hy) (2-D: hy = 1)
-  T cjy;               // 2-D out-of-plane: q w / (hx h)
-  T crho;              // q w / V
-  ChunkTab ct;
-  int* err;
-};
-
-template <typename T> GP_DEV void lds_add(T* p, T v) {
-  if (v != (T)0) atomicAdd(p, v);
-}
-
-template <typename T>
-GP_DEV void window3(int k, T d0, T d1, T* S0, T* S1) {
-  // 3-node window starting at min(c0, c0 + k)
-  int off0 = k < 0 ? 1 : 0;
-  int off1 = k > 0 ? 1 : 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    S0[a] = (a == off0 ? (T)1 - d0 : (T)0) + (a == off0 + 1 ? d0 : (T)0);
-    S1[a] = (a == off1 ? (T)1 - d1 : (T)0) + (a == off1 + 1 ? d1 : (T)0);
-  }
-}
-
-template <typename T, int DIM, bool RHO>
-__global__ __launch_bounds__(256) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
-  const Geom& g = a.g;
-  int c = blockIdx.x;
-  if (c >= *a.ct.n) return;
-  int t = a.ct.tile[c];
-  int p0 = a.ct.start[c], p1 = a.ct.end[c];
-  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
-  int x0 = tx * g.Tx, y0 = ty * g.Ty, z0 = tz * g.Tz;
-  const int FX = g.Tx + 1, FY = DIM == 3 ? g.Ty + 1 : 1, FZ = g.Tz + 1;
-  const int FN = FX * FY * FZ;
-  const int JX = g.Tx + 3, JY = DIM == 3 ? g.Ty + 3 : 1, JZ = g.Tz + 4;
-  const int JN = JX * JY * JZ;
-  const int RX = g.Tx + 3, RY = DIM == 3 ? g.Ty + 3 : 1, RZ = g.Tz + 2;   // rho: origin (x0-1, y0-1, node z0-1)
-  const int RN = RX * RY * RZ;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sF = reinterpret_cast<T*>(smem_raw);
-  T* sJ = sF + 6 * FN;
-  T* sR = sJ + 3 * JN;
-
-  for (int idx = threadIdx.x; idx < FN; idx += blockDim.x) {
-    int lx = idx % FX, r = idx / FX;
-    int ly = r % FY, lz = r / FY;
-    int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
-    int gy = y0 + ly; if (gy >= g.Ny) gy -= g.Ny;
-    int gz = z0 + lz;
-    size_t gi = ((size_t)gz * g.Ny + gy) * g.Nx + gx;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) sF[q * FN + idx] = gz < g.Nz ? a.F[q][gi] : (T)0;
-  }
-  for (int idx = threadIdx.x; idx < 3 * JN + (RHO ? 2 * RN : 0); idx += blockDim.x) sJ[idx] = (T)0;
-  __syncthreads();
-
-  const T third = (T)1 / (T)3;
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-    int cell = P.cell[p];
-    int ix = cell % g.Nx;
-    int r = cell / g.Nx;
-    int iy = r % g.Ny;
-    int iz = r / g.Ny;
-    int lx = ix - x0, ly = iy - y0, lz = iz - z0;
-    if (lx < 0 || lx >= g.Tx || ly < 0 || ly >= (DIM == 3 ? g.Ty : 1) || lz < 0 || lz >= g.Tz) {
-      atomicOr(a.err, ERR_TILE);
-      continue;
-    }
-    T dx0 = P.ox[p], dz0 = P.oz[p];
-    T dy0 = DIM == 3 ? P.oy[p] : (T)0;
-    T ux = P.ux[p], uy = P.uy[p], uz = P.uz[p];
-
-    // gather
-    T wx[2] = {(T)1 - dx0, dx0};
-    T wz[2] = {(T)1 - dz0, dz0};
-    T wy[2] = {(T)1 - dy0, dy0};
-    T f[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-#pragma unroll
-      for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b) {
-#pragma unroll
-        for (int aa = 0; aa < 2; ++aa) {
-          T w = DIM == 3 ? (wx[aa] * wy[b]) * wz[cc] : wx[aa] * wz[cc];
-          int li = ((lz + cc) * FY + (ly + b)) * FX + (lx + aa);
-#pragma unroll
-          for (int q = 0; q < 6; ++q) f[q] = f[q] + w * sF[q * FN + li];
-        }
-      }
-    }
-
-    // Higuera-Cary push
-    T eps = a.eps;
-    T umx = ux + eps * f[0];
-    T umy = uy + eps * f[1];
-    T umz = uz + eps * f[2];
-    T bx = eps * f[3], by = eps * f[4], bz = eps * f[5];
-    T um2 = (umx * umx + umy * umy) + umz * umz;
-    T b2 = (bx * bx + by * by) + bz * bz;
-    T sigma = ((T)1 + um2) - b2;
-    T bu = (bx * umx + by * umy) + bz * umz;
-    T gp = sqrt((sigma + sqrt(sigma * sigma + (T)4 * (b2 + bu * bu))) * (T)0.5);
-    T tx_ = bx / gp, ty_ = by / gp, tz_ = bz / gp;
-    T s = (T)1 / ((T)1 + ((tx_ * tx_ + ty_ * ty_) + tz_ * tz_));
-    T ut = (umx * tx_ + umy * ty_) + umz * tz_;
-    T upx = s * ((umx + ut * tx_) + (umy * tz_ - umz * ty_));
-    T upy = s * ((umy + ut * ty_) + (umz * tx_ - umx * tz_));
-    T upz = s * ((umz + ut * tz_) + (umx * ty_ - umy * tx_));
-    ux = (upx + eps * f[0]) + (upy * tz_ - upz * ty_);
-    uy = (upy + eps * f[1]) + (upz * tx_ - upx * tz_);
-    uz = (upz + eps * f[2]) + (upx * ty_ - upy * tx_);
-
-    // move
-    T uperp2 = ux * ux + uy * uy;
-    T gam = sqrt((T)1 + (uperp2 + uz * uz));
-    T vx = ux / gam, vy = uy / gam;
-    T vzm1 = uz >= (T)0 ? -((T)1 + uperp2) / (gam * (gam + uz)) : uz / gam - (T)1;
-    T tnx = dx0 + vx * a.ax;
-    T kxf = floor(tnx);
-    T dx1 = tnx - kxf;
-    int kx = (int)kxf;
-    if (dx1 >= (T)1) { dx1 = (T)0; kx += 1; }
-    T dy1 = (T)0;
-    int ky = 0;
-    if (DIM == 3) {
-      T tny = dy0 + vy * a.ay;
-      T kyf = floor(tny);
-      dy1 = tny - kyf;
-      ky = (int)kyf;
-      if (dy1 >= (T)1) { dy1 = (T)0; ky += 1; }
-    }
-    T tnz = dz0 + vzm1 * a.az;
-    T kzf = floor(tnz);
-    T dz1 = tnz - kzf;
-    int kz = (int)kzf;
-    if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
-    if (!(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
-    if (kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 1) {
-      atomicOr(a.err, ERR_CFL);
-      continue;
-    }
-    int nix = ix + kx; if (nix < 0) nix += g.Nx; if (nix >= g.Nx) nix -= g.Nx;
-    int niy = iy + ky; if (niy < 0) niy += g.Ny; if (niy >= g.Ny) niy -= g.Ny;
-    int niz = iz + kz;
-    P.cell[p] = (niz * g.Ny + niy) * g.Nx + nix;
-    P.ox[p] = dx1;
-    if (DIM == 3) P.oy[p] = dy1;
-    P.oz[p] = dz1;
-    P.ux[p] = ux;
-    P.uy[p] = uy;
-    P.uz[p] = uz;
-
-    // deposit
-    T S0x[3], S1x[3], S0z[3], S1z[3], S0y[3], S1y[3];
-    window3<T>(kx, dx0, dx1, S0x, S1x);
-    window3<T>(kz, dz0, dz1, S0z, S1z);
-    if (DIM == 3) window3<T>(ky, dy0, dy1, S0y, S1y);
-    T DSx[3], DSy[3], DSz[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      DSx[q] = S1x[q] - S0x[q];
-      DSz[q] = S1z[q] - S0z[q];
-      DSy[q] = DIM == 3 ? S1y[q] - S0y[q] : (T)0;
-    }
-    // local J-tile coordinates of the window origin
-    int jx0 = lx + min(kx, 0) + 1;
-    int jy0 = DIM == 3 ? ly + min(ky, 0) + 1 : 0;
-    int jz0 = lz + min(kz, 0) + 2;       // node base_z
-    T* sJx = sJ;
-    T* sJy = sJ + JN;
-    T* sJz = sJ + 2 * JN;
-    if (DIM == 3) {
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          T acc = (T)0;
-#pragma unroll
-          for (int aa = 0; aa < 2; ++aa) {
-            acc = acc + DSx[aa] * (S0y[b] * S0z[cc] + (T)0.5 * DSy[b] * S0z[cc] +
-                                   (T)0.5 * S0y[b] * DSz[cc] + third * DSy[b] * DSz[cc]);
-            lds_add(&sJx[((jz0 + cc) * JY + (jy0 + b)) * JX + (jx0 + aa)], a.cx * acc);
-          }
-        }
-      }
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa) {
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          T acc = (T)0;
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            acc = acc + DSy[b] * (S0x[aa] * S0z[cc] + (T)0.5 * DSx[aa] * S0z[cc] +
-                                  (T)0.5 * S0x[aa] * DSz[cc] + third * DSx[aa] * DSz[cc]);
-            lds_add(&sJy[((jz0 + cc) * JY + (jy0 + b)) * JX + (jx0 + aa)], a.cy * acc);
-          }
-        }
-      }
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          T w0 = (T)0, w1 = (T)0;   // W_zeta prefix on half-nodes base+1/2, base+3/2
-          T e0 = S0x[aa] * S0y[b] + (T)0.5 * DSx[aa] * S0y[b] + (T)0.5 * S0x[aa] * DSy[b] +
-                 third * DSx[aa] * DSy[b];
-          w0 = DSz[0] * e0;
-          w1 = w0 + DSz[1] * e0;
-          T t0 = S0x[aa] * S0y[b];
-          T t1 = S1x[aa] * S1y[b];
-          // half-nodes n + 1/2, n = base - 1 .. base + 2  (e = 0 .. 3)
-          T r0 = (T)0.25 * a.crho * (t0 * S0z[0] + t1 * S1z[0]);
-          T r1 = (T)0.25 * a.crho * (t0 * (S0z[0] + S0z[1]) + t1 * (S1z[0] + S1z[1]));
-          T r2 = (T)0.25 * a.crho * (t0 * (S0z[1] + S0z[2]) + t1 * (S1z[1] + S1z[2]));
-          T r3 = (T)0.25 * a.crho * (t0 * S0z[2] + t1 * S1z[2]);
-          int base = ((jz0 - 1) * JY + (jy0 + b)) * JX + (jx0 + aa);
-          lds_add(&sJz[base], r0);
-          lds_add(&sJz[base + JY * JX], r1 + a.cz * w0);
-          lds_add(&sJz[base + 2 * JY * JX], r2 + a.cz * w1);
-          lds_add(&sJz[base + 3 * JY * JX], r3);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        T acc = (T)0;
-#pragma unroll
-        for (int aa = 0; aa < 2; ++aa) {
-          acc = acc + DSx[aa] * (S0z[cc] + (T)0.5 * DSz[cc]);
-          lds_add(&sJx[(jz0 + cc) * JX + (jx0 + aa)], a.cx * acc);
-        }
-      }
-      T cyv = a.cjy * vy;
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa) {
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          T wt = S0x[aa] * S0z[cc] + (T)0.5 * DSx[aa] * S0z[cc] + (T)0.5 * S0x[aa] * DSz[cc] +
-                 third * DSx[aa] * DSz[cc];
-          lds_add(&sJy[(jz0 + cc) * JX + (jx0 + aa)], cyv * wt);
-        }
-      }
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa) {
-        T e0 = S0x[aa] + (T)0.5 * DSx[aa];
-        T w0 = DSz[0] * e0;
-        T w1 = w0 + DSz[1] * e0;
-        T t0 = S0x[aa], t1 = S1x[aa];
-        T r0 = (T)0.25 * a.crho * (t0 * S0z[0] + t1 * S1z[0]);
-        T r1 = (T)0.25 * a.crho * (t0 * (S0z[0] + S0z[1]) + t1 * (S1z[0] + S1z[1]));
-        T r2 = (T)0.25 * a.crho * (t0 * (S0z[1] + S0z[2]) + t1 * (S1z[1] + S1z[2]));
-        T r3 = (T)0.25 * a.crho * (t0 * S0z[2] + t1 * S1z[2]);
-        int base = (jz0 - 1) * JX + (jx0 + aa);
-        lds_add(&sJz[base], r0);
-        lds_add(&sJz[base + JX], r1 + a.cz * w0);
-        lds_add(&sJz[base + 2 * JX], r2 + a.cz * w1);
-        lds_add(&sJz[base + 3 * JX], r3);
-      }
-    }
-    if (RHO) {
-      // charge before and after the move, rho tile origin (x0-1, y0-1, node z0-1)
-      T* sR0 = sR;
-      T* sR1 = sR + RN;
-      int oy = DIM == 3 ? 1 : 0;
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-        for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b)
-#pragma unroll
-          for (int aa = 0; aa < 2; ++aa) {
-            T w0 = DIM == 3 ? wx[aa] * (b ? dy0 : (T)1 - dy0) * wz[cc] : wx[aa] * wz[cc];
-            lds_add(&sR0[((lz + 1 + cc) * RY + (ly + oy + b)) * RX + (lx + 1 + aa)], a.crho * w0);
-            T vx1 = aa ? dx1 : (T)1 - dx1;
-            T vz1 = cc ? dz1 : (T)1 - dz1;
-            T w1 = DIM == 3 ? vx1 * (b ? dy1 : (T)1 - dy1) * vz1 : vx1 * vz1;
-            int lx1 = lx + kx, ly1 = ly + ky, lz1 = lz + kz;
-            lds_add(&sR1[((lz1 + 1 + cc) * RY + (ly1 + oy + b)) * RX + (lx1 + 1 + aa)], a.crho * w1);
-          }
-    }
-  }
-  __syncthreads();
-
-  // flush the J tile: global x = x0 - 1 + jx, y = y0 - 1 + jy, plane = z0 + jz
-  for (int idx = threadIdx.x; idx < 3 * JN; idx += blockDim.x) {
-    T v = sJ[idx];
-    if (v == (T)0) continue;
-    int q = idx / JN, l = idx % JN;
-    int jx = l % JX, rr = l / JX;
-    int jy = rr % JY, jz = rr / JY;
-    int plane = z0 + jz;
-    if (plane >= g.NPJ) continue;
-    int gx = x0 - 1 + jx; if (gx < 0) gx += g.Nx; if (gx >= g.Nx) gx -= g.Nx;
-    int gy = DIM == 3 ? y0 - 1 + jy : 0; if (gy < 0) gy += g.Ny; if (gy >= g.Ny) gy -= g.Ny;
-    atomicAdd(&a.J[q][((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
-  }
-  if (RHO) {
-    for (int idx = threadIdx.x; idx < 2 * RN; idx += blockDim.x) {
-      T v = sR[idx];
-      if (v == (T)0) continue;
-      int q = idx / RN, l = idx % RN;
-      int rx = l % RX, rr = l / RX;
-      int ry = rr % RY, rz = rr / RY;
-      int plane = z0 - 1 + rz + 2;
-      if (plane < 0 || plane >= g.NPJ) continue;
-      int gx = x0 - 1 + rx; if (gx < 0) gx += g.Nx; if (gx >= g.Nx) gx -= g.Nx;
-      int gy = DIM == 3 ? y0 - 1 + ry : 0; if (gy < 0) gy += g.Ny; if (gy >= g.Ny) gy -= g.Ny;
-      T* dst = q == 0 ? a.rho0 : a.rho1;
-      atomicAdd(&dst[((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
-    }
-  }
-}
+#include "push.h"
 
 // ---------------------------------------------------------------------------
 // Stable sort by tile, step 1: destination code and rank of every particle of

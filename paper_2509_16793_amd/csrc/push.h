@@ -1,0 +1,415 @@
+// Fused gather + push + move + deposit: one work-group per chunk of a tile.
+//
+// Gather: linear (CIC) weights on the 8 (3-D) / 4 (2-D) nodes around the
+// particle, from an LDS copy of the tile's (T+1)^3 node records (E, B
+// interleaved); zeta nodes >= Nz carry zero.
+// Push: Higuera-Cary with eps = (q/m) dtau / 2.  Move: offsets advance by
+// v dtau / h_axis, zeta by (v_z - 1) dtau / h with the cancellation-free
+// v_z - 1; a cell step beyond one raises ERR_CFL and the particle is left
+// unchanged.  Gather, push and move follow a fixed operation order without
+// contraction, so FP64 (and FP32) results reproduce a reference bit for bit.
+// Deposit: Esirkepov frame current W on the staggered grid plus the time- and
+// zeta-centred charge for the lab J_z, accumulated in an LDS tile of
+// (TX+3) x (TY+3) x (TZ+4) nodes per component (origin x0-1, y0-1, node z0-2),
+// then added to the global arrays with one atomic per non-zero node.  The LDS
+// tile holds 64-bit fixed-point integers: integer LDS atomics run tens of
+// times faster than floating-point ones on gfx950, and the tile sums become
+// exact and independent of the order of the atomics.  The scale is a power of
+// two chosen on the host: in FP32 a single contribution (bounded by the
+// largest coefficient) rounds to an int32 at 2^-30 of that bound; in FP64 a
+// chunk's worst-case node sum (chunk size x largest contribution) stays below
+// 2^61.  Neither can overflow the 64-bit sums.
+// A wave in which no particle crosses a transverse cell boundary takes a
+// reduced stencil (2 x 2 transverse nodes, 28 instead of 72 contributions);
+// the omitted terms are exactly zero.
+#pragma once
+
+template <typename T>
+struct PushArgs {
+  Geom g;
+  const T* F6;         // node records [Nz][Ny][Nx][6]: Ex Ey Ez Bx By Bz
+  T* J[3];             // [NPJ][Ny][Nx]
+  T* rho0;             // nullable: charge before the move
+  T* rho1;             // nullable: charge after the move
+  T eps;               // (q/m) dtau / 2
+  T ax, ay, az;        // dtau / hx, dtau / hy, dtau / h
+  T cx, cy, cz;        // -q w / (dtau hy h), -q w / (dtau hx h), -q w / (dtau hx hy) (2-D: hy = 1)
+  T cjy;               // 2-D out-of-plane: q w / (hx h)
+  T crho;              // q w / V
+  T fscale, finv;      // fixed-point scale of the LDS tile (power of two) and its inverse
+  ChunkTab ct;
+  int* err;
+};
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using t = float2; };
+template <> struct Vec2<double> { using t = double2; };
+
+// fixed-point accumulator of the LDS deposit tile
+template <typename T> struct Fix;
+template <> struct Fix<float> {
+  // a single contribution fits in int32 at the FP32 scale; sums in 64 bits
+  using t = unsigned long long;
+  static GP_DEV unsigned long long to(float v) { return (unsigned long long)(long long)__float2int_rn(v); }
+};
+template <> struct Fix<double> {
+  // two's complement sums in unsigned 64-bit atomics
+  using t = unsigned long long;
+  static GP_DEV unsigned long long to(double v) { return (unsigned long long)__double2ll_rn(v); }
+};
+GP_DEV double fix_value(unsigned long long v) { return (double)(long long)v; }
+
+// 3-node window starting at min(c0, c0 + k): old and new linear weights.
+template <typename T>
+GP_DEV void window3(int k, T d0, T d1, T* S0, T* S1) {
+  int off0 = k < 0 ? 1 : 0;
+  int off1 = k > 0 ? 1 : 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S0[a] = (a == off0 ? (T)1 - d0 : (T)0) + (a == off0 + 1 ? d0 : (T)0);
+    S1[a] = (a == off1 ? (T)1 - d1 : (T)0) + (a == off1 + 1 ? d1 : (T)0);
+  }
+}
+
+template <typename T, int DIM, bool RHO, int TX, int TY, int TZ>
+__global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
+  constexpr int FX = TX + 1, FY = DIM == 3 ? TY + 1 : 1, FZ = TZ + 1;
+  constexpr int FN = FX * FY * FZ;
+  constexpr int JX = TX + 3, JY = DIM == 3 ? TY + 3 : 1, JZ = TZ + 4;
+  constexpr int JN = JX * JY * JZ;
+  constexpr int RX = TX + 3, RY = DIM == 3 ? TY + 3 : 1, RZ = TZ + 2;
+  constexpr int RN = RX * RY * RZ;
+  constexpr int SJ = 3 * JN + (RHO ? 2 * RN : 0);
+  using A = typename Fix<T>::t;
+  __shared__ __align__(16) T sF[6 * FN];
+  __shared__ __align__(16) A sJ[SJ];
+  using V2 = typename Vec2<T>::t;
+
+  const Geom& g = a.g;
+  int c = blockIdx.x;
+  if (c >= *a.ct.n) return;
+  int t = a.ct.tile[c];
+  int p0 = a.ct.start[c], p1 = a.ct.end[c];
+  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+
+  // node records of the tile (3 pairs per node)
+  for (int idx = threadIdx.x; idx < 3 * FN; idx += blockDim.x) {
+    int node = idx / 3, part = idx - node * 3;
+    int lx = node % FX, r = node / FX;
+    int ly = r % FY, lz = r / FY;
+    int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
+    int gy = y0 + ly; if (gy >= g.Ny) gy -= g.Ny;
+    int gz = z0 + lz;
+    V2 v;
+    if (gz < g.Nz) {
+      size_t gi = ((size_t)gz * g.Ny + gy) * g.Nx + gx;
+      v = reinterpret_cast<const V2*>(a.F6 + 6 * gi)[part];
+    } else {
+      v.x = (T)0; v.y = (T)0;
+    }
+    reinterpret_cast<V2*>(sF + 6 * node)[part] = v;
+  }
+  for (int idx = threadIdx.x; idx < SJ; idx += blockDim.x) sJ[idx] = (A)0;
+  __syncthreads();
+
+  const int mx = g.Nx - 1, my = g.Ny - 1;
+  for (int row = p0; row < p1; row += blockDim.x) {
+    int p = row + (int)threadIdx.x;
+    bool valid = p < p1;
+    int lx = 0, ly = 0, lz = 0, kx = 0, ky = 0, kz = 0;
+    T dx0 = (T)0, dy0 = (T)0, dz0 = (T)0, dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
+    if (valid) {
+      int cell = P.cell[p];
+      int ix = cell & mx;
+      int iy = (cell >> g.lnx) & my;
+      int iz = cell >> (g.lnx + g.lny);
+      lx = ix - x0; ly = iy - y0; lz = iz - z0;
+      if (lx < 0 || lx >= TX || ly < 0 || ly >= (DIM == 3 ? TY : 1) || lz < 0 || lz >= TZ) {
+        atomicOr(a.err, ERR_TILE);
+        valid = false;
+        lx = ly = lz = 0;
+      } else {
+        dx0 = P.ox[p];
+        dz0 = P.oz[p];
+        if (DIM == 3) dy0 = P.oy[p];
+        T ux = P.ux[p], uy = P.uy[p], uz = P.uz[p];
+
+        // gather
+        T wx[2] = {(T)1 - dx0, dx0};
+        T wz[2] = {(T)1 - dz0, dz0};
+        T wy[2] = {(T)1 - dy0, dy0};
+        T f[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+        int nb = (lz * FY + ly) * FX + lx;
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+          for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b) {
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) {
+              T w = DIM == 3 ? (wx[aa] * wy[b]) * wz[cc] : wx[aa] * wz[cc];
+              const V2* rec = reinterpret_cast<const V2*>(sF + 6 * (nb + (cc * FY + b) * FX + aa));
+              V2 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+              f[0] = f[0] + w * r0.x;
+              f[1] = f[1] + w * r0.y;
+              f[2] = f[2] + w * r1.x;
+              f[3] = f[3] + w * r1.y;
+              f[4] = f[4] + w * r2.x;
+              f[5] = f[5] + w * r2.y;
+            }
+          }
+        }
+
+        // Higuera-Cary push
+        T eps = a.eps;
+        T umx = ux + eps * f[0];
+        T umy = uy + eps * f[1];
+        T umz = uz + eps * f[2];
+        T bx = eps * f[3], by = eps * f[4], bz = eps * f[5];
+        T um2 = (umx * umx + umy * umy) + umz * umz;
+        T b2 = (bx * bx + by * by) + bz * bz;
+        T sigma = ((T)1 + um2) - b2;
+        T bu = (bx * umx + by * umy) + bz * umz;
+        T gp = sqrt((sigma + sqrt(sigma * sigma + (T)4 * (b2 + bu * bu))) * (T)0.5);
+        T rgp = (T)1 / gp;
+        T tx_ = bx * rgp, ty_ = by * rgp, tz_ = bz * rgp;
+        T s = (T)1 / ((T)1 + ((tx_ * tx_ + ty_ * ty_) + tz_ * tz_));
+        T ut = (umx * tx_ + umy * ty_) + umz * tz_;
+        T upx = s * ((umx + ut * tx_) + (umy * tz_ - umz * ty_));
+        T upy = s * ((umy + ut * ty_) + (umz * tx_ - umx * tz_));
+        T upz = s * ((umz + ut * tz_) + (umx * ty_ - umy * tx_));
+        ux = (upx + eps * f[0]) + (upy * tz_ - upz * ty_);
+        uy = (upy + eps * f[1]) + (upz * tx_ - upx * tz_);
+        uz = (upz + eps * f[2]) + (upx * ty_ - upy * tx_);
+
+        // move
+        T uperp2 = ux * ux + uy * uy;
+        T gam = sqrt((T)1 + (uperp2 + uz * uz));
+        T rg = (T)1 / gam;
+        T vx = ux * rg;
+        vy = uy * rg;
+        T vzm1 = uz >= (T)0 ? (-((T)1 + uperp2) * rg) / (gam + uz) : uz * rg - (T)1;
+        T tnx = dx0 + vx * a.ax;
+        T kxf = floor(tnx);
+        dx1 = tnx - kxf;
+        kx = (int)kxf;
+        if (dx1 >= (T)1) { dx1 = (T)0; kx += 1; }
+        if (DIM == 3) {
+          T tny = dy0 + vy * a.ay;
+          T kyf = floor(tny);
+          dy1 = tny - kyf;
+          ky = (int)kyf;
+          if (dy1 >= (T)1) { dy1 = (T)0; ky += 1; }
+        }
+        T tnz = dz0 + vzm1 * a.az;
+        T kzf = floor(tnz);
+        dz1 = tnz - kzf;
+        kz = (int)kzf;
+        if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
+        if (!(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
+        if (kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 0) {
+          atomicOr(a.err, ERR_CFL);
+          valid = false;
+          kx = ky = kz = 0;
+        } else {
+          int nix = (ix + kx) & mx;
+          int niy = (iy + ky) & my;
+          int niz = iz + kz;
+          P.cell[p] = (niz * g.Ny + niy) * g.Nx + nix;
+          P.ox[p] = dx1;
+          if (DIM == 3) P.oy[p] = dy1;
+          P.oz[p] = dz1;
+          P.ux[p] = ux;
+          P.uy[p] = uy;
+          P.uz[p] = uz;
+        }
+      }
+    }
+
+    // ---- deposit (sums: FMA contraction allowed) ----
+    {
+#pragma clang fp contract(fast)
+      auto add = [](A* p, T v) { atomicAdd(p, Fix<T>::to(v)); };
+      const T fs = a.fscale;
+      // invalid lanes deposit zeros at a valid LDS address
+      T S0x[3], S1x[3], S0z[3], S1z[3], S0y[3], S1y[3];
+      window3<T>(kx, dx0, dx1, S0x, S1x);
+      window3<T>(kz, dz0, dz1, S0z, S1z);
+      if (DIM == 3) window3<T>(ky, dy0, dy1, S0y, S1y);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        S0x[i] = valid ? S0x[i] : (T)0;
+        S1x[i] = valid ? S1x[i] : (T)0;
+      }
+      T DSx[3], DSy[3], DSz[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        DSx[i] = S1x[i] - S0x[i];
+        DSz[i] = S1z[i] - S0z[i];
+        DSy[i] = DIM == 3 ? S1y[i] - S0y[i] : (T)0;
+      }
+      const T third = (T)(1.0 / 3.0);
+      // A, B along zeta: W factors S0*(A) + DS*(B)
+      T Az[3], Bz[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) { Az[i] = S0z[i] + (T)0.5 * DSz[i]; Bz[i] = (T)0.5 * S0z[i] + third * DSz[i]; }
+      int jx0 = lx + min(kx, 0) + 1;
+      int jy0 = DIM == 3 ? ly + min(ky, 0) + 1 : 0;
+      int jz0 = lz + kz + 2;            // node base_z (kz <= 0)
+      A* sJx = sJ + (jz0 * JY + jy0) * JX + jx0;
+      A* sJy = sJx + JN;
+      A* sJz = sJx + 2 * JN - JY * JX;  // half-node plane base_z - 1
+      T qr = (T)0.25 * a.crho * fs;
+      T cx = a.cx * fs, cy = a.cy * fs, cz = a.cz * fs;
+      if (DIM == 3) {
+        bool general = __any(kx != 0 || ky != 0);
+        T Cy[3], Dy[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { Cy[i] = S0y[i] + (T)0.5 * DSy[i]; Dy[i] = (T)0.5 * S0y[i] + third * DSy[i]; }
+        T s0e[4], s1e[4];
+        s0e[0] = S0z[0]; s0e[1] = S0z[0] + S0z[1]; s0e[2] = S0z[1] + S0z[2]; s0e[3] = S0z[2];
+        s1e[0] = S1z[0]; s1e[1] = S1z[0] + S1z[1]; s1e[2] = S1z[1] + S1z[2]; s1e[3] = S1z[2];
+        T pz0 = cz * DSz[0], pz1 = cz * (DSz[0] + DSz[1]);
+        if (general) {
+          T px[2] = {cx * DSx[0], cx * (DSx[0] + DSx[1])};
+          T py[2] = {cy * DSy[0], cy * (DSy[0] + DSy[1])};
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              T F = S0y[b] * Az[cc] + DSy[b] * Bz[cc];
+              add(&sJx[(cc * JY + b) * JX + 0], px[0] * F);
+              add(&sJx[(cc * JY + b) * JX + 1], px[1] * F);
+            }
+#pragma unroll
+          for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              T F = S0x[aa] * Az[cc] + DSx[aa] * Bz[cc];
+              add(&sJy[(cc * JY + 0) * JX + aa], py[0] * F);
+              add(&sJy[(cc * JY + 1) * JX + aa], py[1] * F);
+            }
+#pragma unroll
+          for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              T Fz = S0x[aa] * Cy[b] + DSx[aa] * Dy[b];
+              T t0 = qr * (S0x[aa] * S0y[b]), t1 = qr * (S1x[aa] * S1y[b]);
+              A* pz = &sJz[b * JX + aa];
+              add(pz + 0 * JY * JX, t0 * s0e[0] + t1 * s1e[0]);
+              add(pz + 1 * JY * JX, t0 * s0e[1] + t1 * s1e[1] + pz0 * Fz);
+              add(pz + 2 * JY * JX, t0 * s0e[2] + t1 * s1e[2] + pz1 * Fz);
+              add(pz + 3 * JY * JX, t0 * s0e[3] + t1 * s1e[3]);
+            }
+        } else {
+          // no transverse crossing in this wave: x and y windows start at the
+          // cell, the third window node and the second half-node carry zero
+          T px0 = cx * DSx[0], py0 = cy * DSy[0];
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+              add(&sJx[(cc * JY + b) * JX + 0], px0 * (S0y[b] * Az[cc] + DSy[b] * Bz[cc]));
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+              add(&sJy[(cc * JY + 0) * JX + aa], py0 * (S0x[aa] * Az[cc] + DSx[aa] * Bz[cc]));
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              T Fz = S0x[aa] * Cy[b] + DSx[aa] * Dy[b];
+              T t0 = qr * (S0x[aa] * S0y[b]), t1 = qr * (S1x[aa] * S1y[b]);
+              A* pz = &sJz[b * JX + aa];
+              add(pz + 0 * JY * JX, t0 * s0e[0] + t1 * s1e[0]);
+              add(pz + 1 * JY * JX, t0 * s0e[1] + t1 * s1e[1] + pz0 * Fz);
+              add(pz + 2 * JY * JX, t0 * s0e[2] + t1 * s1e[2] + pz1 * Fz);
+              add(pz + 3 * JY * JX, t0 * s0e[3] + t1 * s1e[3]);
+            }
+        }
+      } else {
+        // 2-D (x, zeta): W_x, out-of-plane J_y = q w v_y x time-averaged shape, J_z
+        T px[2] = {cx * DSx[0], cx * (DSx[0] + DSx[1])};
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          add(&sJx[cc * JX + 0], px[0] * Az[cc]);
+          add(&sJx[cc * JX + 1], px[1] * Az[cc]);
+        }
+        T cyv = a.cjy * fs * vy;
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            T wt = S0x[aa] * Az[cc] + DSx[aa] * Bz[cc];
+            add(&sJy[cc * JX + aa], cyv * wt);
+          }
+        T pz0 = cz * DSz[0], pz1 = cz * (DSz[0] + DSz[1]);
+        T s0e[4] = {S0z[0], S0z[0] + S0z[1], S0z[1] + S0z[2], S0z[2]};
+        T s1e[4] = {S1z[0], S1z[0] + S1z[1], S1z[1] + S1z[2], S1z[2]};
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa) {
+          T Fz = S0x[aa] + (T)0.5 * DSx[aa];
+          T t0 = qr * S0x[aa], t1 = qr * S1x[aa];
+          A* pz = &sJz[aa];
+          add(pz + 0 * JX, t0 * s0e[0] + t1 * s1e[0]);
+          add(pz + 1 * JX, t0 * s0e[1] + t1 * s1e[1] + pz0 * Fz);
+          add(pz + 2 * JX, t0 * s0e[2] + t1 * s1e[2] + pz1 * Fz);
+          add(pz + 3 * JX, t0 * s0e[3] + t1 * s1e[3]);
+        }
+      }
+      if (RHO && valid) {
+        // charge before and after the move; rho tile origin (x0-1, y0-1, node z0-1)
+        A* sR0 = sJ + 3 * JN;
+        A* sR1 = sR0 + RN;
+        T cr = a.crho * fs;
+        constexpr int oy = DIM == 3 ? 1 : 0;
+        T w0x[2] = {(T)1 - dx0, dx0}, w0y[2] = {(T)1 - dy0, dy0}, w0z[2] = {(T)1 - dz0, dz0};
+        T w1x[2] = {(T)1 - dx1, dx1}, w1y[2] = {(T)1 - dy1, dy1}, w1z[2] = {(T)1 - dz1, dz1};
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+          for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b)
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa) {
+              T v0 = DIM == 3 ? w0x[aa] * w0y[b] * w0z[cc] : w0x[aa] * w0z[cc];
+              T v1 = DIM == 3 ? w1x[aa] * w1y[b] * w1z[cc] : w1x[aa] * w1z[cc];
+              add(&sR0[((lz + 1 + cc) * RY + (ly + oy + b)) * RX + (lx + 1 + aa)], cr * v0);
+              add(&sR1[((lz + kz + 1 + cc) * RY + (ly + ky + oy + b)) * RX + (lx + kx + 1 + aa)], cr * v1);
+            }
+      }
+    }
+  }
+  __syncthreads();
+
+  // flush: global x = x0 - 1 + jx, y = y0 - 1 + jy, plane = z0 + jz
+  for (int idx = threadIdx.x; idx < 3 * JN; idx += blockDim.x) {
+    A iv = sJ[idx];
+    if (iv == (A)0) continue;
+    T v = (T)fix_value(iv) * a.finv;
+    int q = idx / JN, l = idx - q * JN;
+    int jx = l % JX, rr = l / JX;
+    int jy = rr % JY, jz = rr / JY;
+    int plane = z0 + jz;
+    if (plane >= g.NPJ) continue;
+    int gx = (x0 - 1 + jx) & mx;
+    int gy = DIM == 3 ? (y0 - 1 + jy) & my : 0;
+    atomicAdd(&a.J[q][((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
+  }
+  if (RHO) {
+    for (int idx = threadIdx.x; idx < 2 * RN; idx += blockDim.x) {
+      A iv = sJ[3 * JN + idx];
+      if (iv == (A)0) continue;
+      T v = (T)fix_value(iv) * a.finv;
+      int q = idx / RN, l = idx - q * RN;
+      int rx = l % RX, rr = l / RX;
+      int ry = rr % RY, rz = rr / RY;
+      int plane = z0 - 1 + rz + 2;
+      if (plane < 0 || plane >= g.NPJ) continue;
+      int gx = (x0 - 1 + rx) & mx;
+      int gy = DIM == 3 ? (y0 - 1 + ry) & my : 0;
+      T* dst = q == 0 ? a.rho0 : a.rho1;
+      atomicAdd(&dst[((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
+    }
+  }
+}

@@ -68,6 +68,9 @@ _SIGS = {
                                         ctypes.c_size_t]),
     "gempic_get_spectral": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "gempic_set_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "gempic_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "gempic_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]),
     "gempic_destroy": (None, [ctypes.c_void_p]),
     "gempic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gempic_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -160,6 +163,17 @@ def gempic_set_fields(h, src, nbytes):
     _check(lib().gempic_set_fields(h, src, nbytes), h)
 
 
+def gempic_timing(h, enable):
+    _check(lib().gempic_timing(h, int(enable)), h)
+
+
+def gempic_get_timing(h):
+    ms = (ctypes.c_double * 5)()
+    n = ctypes.c_int64()
+    _check(lib().gempic_get_timing(h, ms, ctypes.byref(n)), h)
+    return list(ms), n.value
+
+
 def gempic_destroy(h):
     lib().gempic_destroy(h)
 
@@ -233,6 +247,15 @@ class Sim:
         a = np.empty((6, self.Nz, self.Ny, nxh), np.complex128 if self.dtype == np.float64 else np.complex64)
         gempic_get_spectral(self.h, _ptr(a), a.nbytes)
         return a
+
+    def timing(self, enable=True):
+        gempic_timing(self.h, enable)
+
+    def get_timing(self):
+        """Accumulated ms per phase (clear, push+deposit, sort+window, fields,
+        step) and the number of timed steps."""
+        ms, n = gempic_get_timing(self.h)
+        return dict(zip(("clear", "push_deposit", "sort_window", "fields", "step"), ms)), n
 
     def set_fields(self, F6):
         a = np.ascontiguousarray(F6, self.dtype)

@@ -55,10 +55,11 @@ def test_push_bit_exact_from_shared_state(cfg):
         assert np.array_equal(d["off"][a], off[a]), f"offset axis {a}"
     for a in range(3):
         assert np.array_equal(d["u"][a], u[a]), f"momentum axis {a}"
-    # currents of this step agree to roundoff
+    # currents of this step: the GPU sums them in 64-bit fixed point (absolute
+    # resolution ~1e-15 of the largest single contribution); same bar as fields
     J = g.fields(("Jx", "Jy", "Jz"))
     err = rel_errors(oracle_currents(o, g.NPJ), J)
-    assert max(err.values()) < 1e-12, err
+    assert max(err.values()) < 1e-10, err
 
 
 def test_lwfa2d_fp64_100_steps():
