@@ -16,7 +16,7 @@
 // times faster than floating-point ones on gfx950, and the tile sums become
 // exact and independent of the order of the atomics.  The scale is a power of
 // two chosen on the host: in FP32 a single contribution (bounded by the
-// largest coefficient) rounds to an int32 at 2^-30 of that bound; in FP64 a
+// largest coefficient) truncates to an int32 at 2^-30 of that bound; in FP64 a
 // chunk's worst-case node sum (chunk size x largest contribution) stays below
 // 2^61.  Neither can overflow the 64-bit sums.
 // A wave in which no particle crosses a transverse cell boundary takes a
@@ -50,7 +50,8 @@ template <typename T> struct Fix;
 template <> struct Fix<float> {
   // a single contribution fits in int32 at the FP32 scale; sums in 64 bits
   using t = unsigned long long;
-  static GP_DEV unsigned long long to(float v) { return (unsigned long long)(long long)__float2int_rn(v); }
+  // truncation: the bias is below 2^-30 of the largest single contribution
+  static GP_DEV unsigned long long to(float v) { return (unsigned long long)(long long)(int)v; }
 };
 template <> struct Fix<double> {
   // two's complement sums in unsigned 64-bit atomics
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T>
     }
 
     // ---- deposit (sums: FMA contraction allowed) ----
-    {
+    if (__any(valid)) {
 #pragma clang fp contract(fast)
       auto add = [](A* p, T v) { atomicAdd(p, Fix<T>::to(v)); };
       const T fs = a.fscale;
