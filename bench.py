@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle updates/s (gather+push+deposit), % HBM roofline; 1ppc+CNN vs 16ppc"
+# HBM bytes per k_push_deposit launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this
+# workload, scaled by a plain-copy calibration (profiles/k_push_deposit_lwfa3d_*.md);
+# valid only for the kernel source it was measured on.
+MEASURED_TRAFFIC = {"push_h_sha256_prefix": "e1bb74c63113f18c", "bytes_per_launch": 6.214e9}
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 28          # int32 cell + 3 x FP32 offset + 3 x FP32 momentum
 
@@ -73,7 +77,19 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 28                      # 2^28 floats = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is a design only)", file=sys.stderr)
@@ -105,6 +121,10 @@ def main():
     n1 = sim._count()
     print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
 
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2509_16793_amd", "csrc", "push.h"), "rb").read()
+    same_kernel = hashlib.sha256(src).hexdigest()[:16] == MEASURED_TRAFFIC["push_h_sha256_prefix"]
+    traffic = MEASURED_TRAFFIC["bytes_per_launch"] if same_kernel else None
     n_avg = 0.5 * (n0 + n1)
     push_s = ph["push_deposit"] / 1e3
     value = n_avg * args.steps / push_s
@@ -129,7 +149,7 @@ def main():
                                "FP32 cell+offset particles",
                    "grid": cfg["n"], "ppc": ppc, "particles": int(n_avg)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_push_deposit", "bytes_per_update": bpu,
                      "avg_launch_ms": launch_s * 1e3},
         "phase_ms_per_step": {k: v / args.steps for k, v in ph.items()},
