@@ -71,6 +71,33 @@ def denoiser_lwfa(ppc=(1, 1, 1)):
     return lwfa3d_fp32(ppc=ppc, steps=1000)
 
 
+def denoiser_train(ppc=(1, 1, 1), seed=0, n=(64, 64, 512)):
+    """Training runs of the denoiser: the physics of denoiser_lwfa in a
+    64 x 64 cell transverse box (periodic), so that every 64^3 training crop
+    spans the full periodic cross-section and needs a halo only in zeta."""
+    cfg = lwfa3d_fp32(ppc=ppc, steps=1000)
+    cfg.update(n=list(n), seed=seed)
+    return cfg
+
+
+def denoiser_init(seed=0, last_scale=1.0, bias_scale=0.0):
+    """Initial FP32 weights of the 3 -> 16 -> 32 -> 16 -> 3 denoiser, flat,
+    layer by layer as (W[Cout][Cin][kz][ky][kx], b[Cout]): He-uniform bounds
+    sqrt(6 / (27 Cin)), the last layer scaled by ``last_scale`` (0 starts the
+    network as the plain filter), biases uniform in +-bias_scale."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    layers = ((3, 16), (16, 32), (32, 16), (16, 3))
+    for l, (ci, co) in enumerate(layers):
+        bound = math.sqrt(6.0 / (27 * ci))
+        W = rng.uniform(-bound, bound, size=co * ci * 27)
+        if l == len(layers) - 1:
+            W = W * last_scale
+        parts += [W, rng.uniform(-bias_scale, bias_scale, size=co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def small3d(precision="fp64", n=(32, 32, 64), tile=(8, 8, 8), ppc=(1, 1, 2),
             steps=4, a0=1.0, seed=3, n_e=0.01):
     """Small 3-D LWFA-like case: several tiles in every direction, a laser strong
