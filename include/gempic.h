@@ -103,6 +103,9 @@ typedef struct {
   double  field_energy;     /* 1/2 sum (E^2 + B^2) V over the field nodes                */
   double  continuity_rel;   /* ||(rho1-rho0)/dtau - D rhobar + D.J|| / ||(rho1-rho0)/dtau||
                                of the raw deposit (needs deposit_rho)                    */
+  int64_t fallbacks;        /* steps whose denoised current failed the continuity test
+                               (gempic_denoise.h); 0 without a denoiser                  */
+  double  denoise_rel;      /* that test's ratio in the last step                        */
 } gempic_diag;
 
 /* Field selector bits for gempic_fields. */

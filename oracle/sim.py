@@ -51,6 +51,9 @@ class Simulation:
         self.F = real_fields(p, self.state)
         self.J = None
         self.diag = None
+        # optional replacement of the binomial filter: f(sim, (Jx, Jy, Jz)) ->
+        # the three currents handed to the field solver
+        self.current_filter = None
 
     @property
     def tau(self):
@@ -74,9 +77,12 @@ class Simulation:
         P = Particles.concat(P, B)
         self.P = stable_sort(p, P)
         self.J = (Jx, Jy, Jz)
-        fJ = [Jx, Jy, Jz]
-        for _ in range(p.filter_passes):
-            fJ = [binomial_filter(p, a) for a in fJ]
+        if self.current_filter is not None:
+            fJ = list(self.current_filter(self, (Jx, Jy, Jz)))
+        else:
+            fJ = [Jx, Jy, Jz]
+            for _ in range(p.filter_passes):
+                fJ = [binomial_filter(p, a) for a in fJ]
         self.Jf = tuple(fJ)
         jh = half_node_currents(p, *fJ)
         self.state = march(p, self.state, jh, p.dtau)

@@ -4,12 +4,12 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "gempic.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("gempic.hip", "denoise.hip")]
 OUT_DIR = os.path.join(HERE, "_lib")
 OUT = os.path.join(OUT_DIR, "libgempic.so")
 
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # every FP64 result of the push/move must follow the written operation
     # order (no fused multiply-adds), so it reproduces bit for bit
     "-ffp-contract=off",
@@ -19,14 +19,28 @@ FLAGS = [
 
 
 def build(verbose=False):
+    """Compile every translation unit (in parallel) and link the library."""
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objs, procs = [], []
+    for src in SRCS:
+        obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
+        cmd = [hipcc] + FLAGS + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    for p, cmd in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = OUT + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-o", tmp, SRC]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
+    for o in objs:
+        os.remove(o)
     return OUT
 
 

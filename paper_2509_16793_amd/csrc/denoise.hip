@@ -1,0 +1,998 @@
+// Learned current denoiser on gfx950: BF16 MFMA 3x3x3 convolutions
+// (3 -> 16 -> 32 -> 16 -> 3, ReLU, FP32 accumulation), the staggered curl
+// correction of the binomially filtered current, the continuity test that
+// selects between them, and the training step (loss, backward, Adam).
+//
+// Layouts
+//   boxes are (Z, Y, X) voxels, x and y periodic, zero beyond the Z planes;
+//   currents, A and their gradients: FP32 planar [3][Z][Y][X];
+//   hidden activations and their gradients: bf16 channels-last [Z][Y][X][C];
+//   parameters: FP32, layer by layer W[Cout][Cin][kz][ky][kx] then b[Cout].
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 with the
+// output channels as the MFMA rows (operand A = weights, kept in VGPRs for
+// the whole work-group) and 16 consecutive x voxels as the columns (operand
+// B = activations, one 16-byte LDS read per lane from a halo tile).  The
+// reduction index k = (tap, input channel) is split in steps of 32; a lane
+// group g (lanes 16g .. 16g+15) supplies the 8 values k = 32 s + 8 g + e of
+// both operands, so operands A and B agree element by element.  The data
+// gradient is the same kernel with flipped taps and transposed channels;
+// weight gradients are MFMAs with the voxels as the reduction index.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gempic.h"
+#include "../../include/gempic_denoise.h"
+#include "common.h"
+#include "dn_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+namespace {
+
+constexpr int NLAYER = 4;
+constexpr int L_CIN[NLAYER] = {3, 16, 32, 16};
+constexpr int L_COUT[NLAYER] = {16, 32, 16, 3};
+constexpr int pad_in(int c) { return c <= 8 ? 8 : c; }          // MFMA k-chunks of 8
+constexpr int pad_out(int c) { return c <= 16 ? 16 : 32; }      // MFMA rows of 16
+
+int64_t layer_woff(int l) {
+  int64_t o = 0;
+  for (int i = 0; i < l; ++i) o += (int64_t)L_COUT[i] * L_CIN[i] * 27 + L_COUT[i];
+  return o;
+}
+int64_t n_params() { return layer_woff(NLAYER); }
+int64_t packed_units(int cinp, int coutp) {
+  int tpk = 32 / cinp;
+  int nks = (27 + tpk - 1) / tpk;
+  return (int64_t)nks * (coutp / 16) * 64;
+}
+
+constexpr int TZ = 4, TY = 8, TX = 16;        // output tile of one work-group
+constexpr int HZ = TZ + 2, HY = TY + 2, HX = TX + 2;
+constexpr int HALO = HZ * HY * HX;            // 1080 voxels
+constexpr int TILE = TZ * TY * TX;            // 512 voxels
+
+GP_DEV unsigned f2bf(float f) {               // round to nearest even
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+GP_DEV float bf2f(unsigned b) { return __uint_as_float(b << 16); }
+GP_DEV int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// weight packing: MFMA operand A for every (k-step s, row tile j, lane)
+struct PackArgs {
+  const float* W;     // layer weights [cout][cin][27]
+  int cin, cout;      // layer channels
+  int cinp, coutp;    // padded channels of the packed convolution
+  int transpose;      // 1: data-gradient convolution (cout -> cin, flipped taps)
+  u32x4* out;
+  int64_t units;
+};
+
+__global__ void k_pack(PackArgs a) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= a.units) return;
+  int lane = (int)(u % 64);
+  int64_t r = u / 64;
+  int nct = a.coutp / 16;
+  int j = (int)(r % nct);
+  int s = (int)(r / nct);
+  int g = lane >> 4, n = lane & 15;
+  int tpk = 32 / a.cinp;
+  int tp = s * tpk + (g * 8) / a.cinp;      // tap of the packed convolution
+  int c0 = (g * 8) % a.cinp;
+  int orow = 16 * j + n;                    // packed output channel
+  unsigned w[8];
+  for (int e = 0; e < 8; ++e) {
+    int cin_p = c0 + e;                     // packed input channel
+    int co, ci, t;
+    if (a.transpose) { co = cin_p; ci = orow; t = 26 - tp; }
+    else { co = orow; ci = cin_p; t = tp; }
+    float v = 0.0f;
+    if (tp <= 26 && co < a.cout && ci < a.cin) v = a.W[((int64_t)co * a.cin + ci) * 27 + t];
+    w[e] = f2bf(v);
+  }
+  u32x4 o;
+  o[0] = w[0] | (w[1] << 16);
+  o[1] = w[2] | (w[3] << 16);
+  o[2] = w[4] | (w[5] << 16);
+  o[3] = w[6] | (w[7] << 16);
+  a.out[u] = o;
+}
+
+// ---------------------------------------------------------------------------
+// convolution (forward, or data gradient with packed transposed weights)
+//   INMODE 0: bf16 channels-last input with CINP channels
+//   INMODE 1: FP32 planar 3-component input times in_scale (CINP = 8)
+//   OUTMODE 0: bf16 channels-last, + bias, ReLU
+//   OUTMODE 1: FP32 planar, first 3 channels, + bias
+//   OUTMODE 2: bf16 channels-last, zero where mask <= 0 (ReLU derivative)
+struct ConvArgs {
+  int Z, Y, X;
+  const u32x4* in;
+  const float* inf[3];
+  float in_scale;
+  const u32x4* wp;
+  const float* bias;
+  unsigned short* out;
+  float* outf[3];
+  const unsigned short* mask;
+};
+
+template <int CINP, int COUTP, int INMODE, int OUTMODE>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+  constexpr int U = CINP / 8;               // 16-byte units per voxel
+  constexpr int TPK = 32 / CINP;            // taps per k-step
+  constexpr int NKS = (27 + TPK - 1) / TPK;
+  constexpr int NCT = COUTP / 16;
+  constexpr int RPW = TZ * TY / 4;          // 16-voxel rows per wave
+  __shared__ u32x4 sX[HALO * U];
+
+  const int nbx = a.X / TX, nby = a.Y / TY;
+  int b = blockIdx.x;
+  const int bx = b % nbx;
+  b /= nbx;
+  const int by = b % nby, bz = b / nby;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+  const int tid = threadIdx.x;
+
+  if (INMODE == 0) {
+    for (int u = tid; u < HALO * U; u += 256) {
+      int hv = u / U, part = u - hv * U;
+      int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+      int gz = z0 + hz - 1;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (gz >= 0 && gz < a.Z) {
+        int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
+        v = a.in[(((int64_t)gz * a.Y + gy) * a.X + gx) * U + part];
+      }
+      sX[u] = v;
+    }
+  } else {
+    for (int hv = tid; hv < HALO; hv += 256) {
+      int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+      int gz = z0 + hz - 1;
+      float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+      if (gz >= 0 && gz < a.Z) {
+        int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
+        int64_t o = ((int64_t)gz * a.Y + gy) * a.X + gx;
+        c0 = a.inf[0][o] * a.in_scale;
+        c1 = a.inf[1][o] * a.in_scale;
+        c2 = a.inf[2][o] * a.in_scale;
+      }
+      u32x4 v = {f2bf(c0) | (f2bf(c1) << 16), f2bf(c2), 0u, 0u};
+      sX[hv] = v;
+    }
+  }
+
+  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  bf16x8 wr[NKS][NCT];
+#pragma unroll
+  for (int s = 0; s < NKS; ++s)
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) wr[s][j] = __builtin_bit_cast(bf16x8, a.wp[(s * NCT + j) * 64 + lane]);
+  __syncthreads();
+
+  for (int it = 0; it < RPW; it += 2) {
+    f32x4 acc[2][NCT];
+    int base[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int rg = wave * RPW + it + r;
+      int zz = rg / TY, yy = rg - zz * TY;
+      base[r] = ((zz + 1) * HY + (yy + 1)) * HX + (n + 1);
+#pragma unroll
+      for (int j = 0; j < NCT; ++j) acc[r][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+      int t = s * TPK + (g * 8) / CINP;
+      t = t > 26 ? 26 : t;                   // padding tap: zero weights
+      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      int off = ((dz * HY + dy) * HX + dx) * U + ((g * 8) % CINP) / 8;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        bf16x8 bv = __builtin_bit_cast(bf16x8, sX[base[r] * U + off]);
+#pragma unroll
+        for (int j = 0; j < NCT; ++j)
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[s][j], bv, acc[r][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int rg = wave * RPW + it + r;
+      int zz = rg / TY, yy = rg - zz * TY;
+      int z = z0 + zz;
+      if (z >= a.Z) continue;
+      int64_t vox = ((int64_t)z * a.Y + (y0 + yy)) * a.X + (x0 + n);
+      if (OUTMODE == 1) {
+        if (g == 0) {
+          a.outf[0][vox] = acc[r][0][0] + a.bias[0];
+          a.outf[1][vox] = acc[r][0][1] + a.bias[1];
+          a.outf[2][vox] = acc[r][0][2] + a.bias[2];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) {
+          int co0 = 16 * j + 4 * g;
+          float v[4];
+          if (OUTMODE == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[r][j][i] + a.bias[co0 + i], 0.0f);
+          } else {
+            u32x2 m = *(const u32x2*)(a.mask + vox * COUTP + co0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              unsigned mb = (i & 1) ? (m[i >> 1] >> 16) : (m[i >> 1] & 0xFFFFu);
+              v[i] = bf2f(mb) > 0.0f ? acc[r][j][i] : 0.0f;
+            }
+          }
+          u32x2 o;
+          o[0] = f2bf(v[0]) | (f2bf(v[1]) << 16);
+          o[1] = f2bf(v[2]) | (f2bf(v[3]) << 16);
+          *(u32x2*)(a.out + vox * COUTP + co0) = o;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight and bias gradients of one layer:
+//   gW[co][ci][t] += sum_v gy[v][co] x[v + off(t)][ci],  gb[co] += sum_v gy[v][co]
+//   XMODE 0: x bf16 channels-last with XS channels; 1: FP32 planar x in_scale (XS = 4)
+//   GMODE 0: gy bf16 channels-last with GS channels; 1: FP32 planar (GS = 4)
+struct WgradArgs {
+  int Z, Y, X;
+  const u32x4* x;
+  const float* xf[3];
+  float x_scale;
+  const u32x4* gy;
+  const float* gyf[3];
+  float* gW;
+  float* gb;
+};
+
+template <int CIN, int COUT, int XS, int GS, int XMODE, int GMODE>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  constexpr int MT = (COUT + 15) / 16, NT = (CIN + 15) / 16;
+  constexpr int NTILE = 27 * MT * NT;
+  constexpr int PERW = (NTILE + 3) / 4;
+  __shared__ u32x4 sXv[HALO * XS / 8 + 1];
+  __shared__ u32x4 sGv[TILE * GS / 8 + 1];
+  unsigned short* sX = (unsigned short*)sXv;
+  unsigned short* sG = (unsigned short*)sGv;
+
+  const int nbx = a.X / TX, nby = a.Y / TY;
+  int b = blockIdx.x;
+  const int bx = b % nbx;
+  b /= nbx;
+  const int by = b % nby, bz = b / nby;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+  const int tid = threadIdx.x;
+
+  if (XMODE == 0) {
+    constexpr int U = XS / 8;
+    for (int u = tid; u < HALO * U; u += 256) {
+      int hv = u / U, part = u - hv * U;
+      int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+      int gz = z0 + hz - 1;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (gz >= 0 && gz < a.Z) {
+        int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
+        v = a.x[(((int64_t)gz * a.Y + gy) * a.X + gx) * U + part];
+      }
+      sXv[u] = v;
+    }
+  } else {
+    for (int hv = tid; hv < HALO; hv += 256) {
+      int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+      int gz = z0 + hz - 1;
+      float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+      if (gz >= 0 && gz < a.Z) {
+        int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
+        int64_t o = ((int64_t)gz * a.Y + gy) * a.X + gx;
+        c0 = a.xf[0][o] * a.x_scale;
+        c1 = a.xf[1][o] * a.x_scale;
+        c2 = a.xf[2][o] * a.x_scale;
+      }
+      u32x2 v = {f2bf(c0) | (f2bf(c1) << 16), f2bf(c2)};
+      ((u32x2*)sX)[hv] = v;
+    }
+  }
+  if (GMODE == 0) {
+    constexpr int U = GS / 8;
+    for (int u = tid; u < TILE * U; u += 256) {
+      int tv = u / U, part = u - tv * U;
+      int zz = tv / (TY * TX), r = tv - zz * (TY * TX), yy = r / TX, xx = r - yy * TX;
+      int gz = z0 + zz;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (gz < a.Z) v = a.gy[(((int64_t)gz * a.Y + (y0 + yy)) * a.X + (x0 + xx)) * U + part];
+      sGv[u] = v;
+    }
+  } else {
+    for (int tv = tid; tv < TILE; tv += 256) {
+      int zz = tv / (TY * TX), r = tv - zz * (TY * TX), yy = r / TX, xx = r - yy * TX;
+      int gz = z0 + zz;
+      float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+      if (gz < a.Z) {
+        int64_t o = ((int64_t)gz * a.Y + (y0 + yy)) * a.X + (x0 + xx);
+        c0 = a.gyf[0][o];
+        c1 = a.gyf[1][o];
+        c2 = a.gyf[2][o];
+      }
+      u32x2 v = {f2bf(c0) | (f2bf(c1) << 16), f2bf(c2)};
+      ((u32x2*)sG)[tv] = v;
+    }
+  }
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  f32x4 acc[PERW];
+#pragma unroll
+  for (int i = 0; i < PERW; ++i) acc[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int q = 0; q < TILE / 32; ++q) {
+    // lane group g: 8 consecutive x voxels of tile row 2q + g/2
+    int row = 2 * q + (g >> 1);
+    int zz = row / TY, yy = row - zz * TY, xx0 = 8 * (g & 1);
+    int tv0 = (zz * TY + yy) * TX + xx0;
+    bf16x8 af[MT];
+#pragma unroll
+    for (int jc = 0; jc < MT; ++jc) {
+      int co = 16 * jc + n;
+      unsigned w[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = co < COUT ? sG[(tv0 + e) * GS + co] : 0u;
+      u32x4 p = {w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16), w[6] | (w[7] << 16)};
+      af[jc] = __builtin_bit_cast(bf16x8, p);
+    }
+#pragma unroll
+    for (int i = 0; i < PERW; ++i) {
+      int idx = wave + 4 * i;
+      if (idx < NTILE) {
+        int t = idx / (MT * NT), rem = idx - t * (MT * NT), jc = rem / NT, ji = rem - jc * NT;
+        int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        int ci = 16 * ji + n;
+        int hb = ((zz + 1 + dz) * HY + (yy + 1 + dy)) * HX + (xx0 + 1 + dx);
+        unsigned w[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = ci < CIN ? sX[(hb + e) * XS + ci] : 0u;
+        u32x4 p = {w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16), w[6] | (w[7] << 16)};
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[jc], __builtin_bit_cast(bf16x8, p), acc[i], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PERW; ++i) {
+    int idx = wave + 4 * i;
+    if (idx < NTILE) {
+      int t = idx / (MT * NT), rem = idx - t * (MT * NT), jc = rem / NT, ji = rem - jc * NT;
+      int ci = 16 * ji + n;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int co = 16 * jc + 4 * g + k;
+        if (co < COUT && ci < CIN) atomicAdd(&a.gW[((int64_t)co * CIN + ci) * 27 + t], acc[i][k]);
+      }
+    }
+  }
+  for (int co = tid; co < COUT; co += 256) {
+    float s = 0.0f;
+    for (int tv = 0; tv < TILE; ++tv) s += bf2f(sG[tv * GS + co]);
+    atomicAdd(&a.gb[co], s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise stencils on FP32 planar boxes
+struct Box {
+  int Z, Y, X;
+  GP_DEV int64_t at(int z, int y, int x) const { return ((int64_t)z * Y + y) * X + x; }
+};
+
+struct P3 { const float* p[3]; };
+struct W3 { float* p[3]; };
+
+// one 1-2-1 pass along x, y (periodic) and zeta (zero outside)
+__global__ void k_filter(Box B, P3 in, W3 out) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  if (v >= nv) return;
+  int x = (int)(v % B.X);
+  int64_t r = v / B.X;
+  int y = (int)(r % B.Y), z = (int)(r / B.Y);
+  const float w[3] = {0.25f, 0.5f, 0.25f};
+  for (int c = 0; c < 3; ++c) {
+    float acc = 0.0f;
+    for (int dz = -1; dz <= 1; ++dz) {
+      int zz = z + dz;
+      if (zz < 0 || zz >= B.Z) continue;
+      float sy = 0.0f;
+      for (int dy = -1; dy <= 1; ++dy) {
+        int yy = wrapi(y + dy, B.Y);
+        const float* row = in.p[c] + B.at(zz, yy, 0);
+        float sx = 0.25f * row[wrapi(x - 1, B.X)] + 0.5f * row[x] + 0.25f * row[wrapi(x + 1, B.X)];
+        sy += w[dy + 1] * sx;
+      }
+      acc += w[dz + 1] * sy;
+    }
+    out.p[c][v] = acc;
+  }
+}
+
+struct CurlArgs {
+  Box B;
+  float s, ihx, ihy, ih;
+};
+
+// s * curl(A) at (z, y, x), zero for planes outside the box
+GP_DEV void curl_at(const CurlArgs& a, P3 A, int z, int y, int x, float c[3]) {
+  if (z < 0 || z >= a.B.Z) { c[0] = c[1] = c[2] = 0.0f; return; }
+  const Box& B = a.B;
+  int64_t v = B.at(z, y, x);
+  int64_t vy = B.at(z, wrapi(y - 1, B.Y), x);
+  int64_t vx = B.at(z, y, wrapi(x - 1, B.X));
+  float axz = z > 0 ? A.p[0][B.at(z - 1, y, x)] : 0.0f;
+  float ayz = z > 0 ? A.p[1][B.at(z - 1, y, x)] : 0.0f;
+  float ax = A.p[0][v], ay = A.p[1][v], az = A.p[2][v];
+  c[0] = a.s * ((az - A.p[2][vy]) * a.ihy - (ay - ayz) * a.ih);
+  c[1] = a.s * ((ax - axz) * a.ih - (az - A.p[2][vx]) * a.ihx);
+  c[2] = a.s * ((ay - A.p[1][vx]) * a.ihx - (ax - A.p[0][vy]) * a.ihy);
+}
+
+GP_DEV double block_sum_d(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+// Jd = Jf + s curl(A); red[0] += |D.(s curl A)|^2, red[1] += |D.Jf|^2
+__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd, double* red) {
+  __shared__ double sh[4];
+  const Box& B = a.B;
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  double num = 0.0, den = 0.0;
+  if (v < nv) {
+    int x = (int)(v % B.X);
+    int64_t r = v / B.X;
+    int y = (int)(r % B.Y), z = (int)(r / B.Y);
+    float c[3], cx[3], cy[3], cz[3];
+    curl_at(a, A, z, y, x, c);
+    curl_at(a, A, z, y, wrapi(x - 1, B.X), cx);
+    curl_at(a, A, z, wrapi(y - 1, B.Y), x, cy);
+    curl_at(a, A, z - 1, y, x, cz);
+    for (int q = 0; q < 3; ++q) Jd.p[q][v] = Jf.p[q][v] + c[q];
+    double dc = (double)(c[0] - cx[0]) * a.ihx + (double)(c[1] - cy[1]) * a.ihy + (double)(c[2] - cz[2]) * a.ih;
+    int64_t vx = B.at(z, y, wrapi(x - 1, B.X)), vy = B.at(z, wrapi(y - 1, B.Y), x);
+    float fz = z > 0 ? Jf.p[2][B.at(z - 1, y, x)] : 0.0f;
+    double df = (double)(Jf.p[0][v] - Jf.p[0][vx]) * a.ihx + (double)(Jf.p[1][v] - Jf.p[1][vy]) * a.ihy +
+                (double)(Jf.p[2][v] - fz) * a.ih;
+    num = dc * dc;
+    den = df * df;
+  }
+  double tn = block_sum_d(num, sh);
+  __syncthreads();
+  double td = block_sum_d(den, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(&red[0], tn);
+    atomicAdd(&red[1], td);
+  }
+}
+
+// decide between the corrected and the filtered current; reset the sums
+__global__ void k_decide(double* red, double thr, int* use_net, double* rel, int64_t* fallbacks) {
+  double num = red[0], den = red[1];
+  double q = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
+  int ok = q <= thr;                         // false for NaN
+  *use_net = ok;
+  if (rel) *rel = q;
+  if (!ok && fallbacks) *fallbacks += 1;
+  red[0] = 0.0;
+  red[1] = 0.0;
+}
+
+__global__ void k_select(Box B, const int* use_net, P3 Jf, W3 Jd) {
+  if (*use_net) return;
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  if (v >= nv) return;
+  for (int q = 0; q < 3; ++q) Jd.p[q][v] = Jf.p[q][v];
+}
+
+// training loss on planes [lo, hi): r = (Jf + s curl A - Jt) / n_e,
+// loss += lscale sum r^2, gJ = gscale r (zero outside the planes)
+struct LossArgs {
+  CurlArgs c;
+  int lo, hi;
+  float inv_ne, gscale;
+  double lscale;
+};
+
+__global__ __launch_bounds__(256) void k_loss(LossArgs a, P3 Jf, P3 A, P3 Jt, W3 gJ, double* loss) {
+  __shared__ double sh[4];
+  const Box& B = a.c.B;
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  double l = 0.0;
+  if (v < nv) {
+    int x = (int)(v % B.X);
+    int64_t r = v / B.X;
+    int y = (int)(r % B.Y), z = (int)(r / B.Y);
+    bool in = z >= a.lo && z < a.hi;
+    float c[3];
+    curl_at(a.c, A, z, y, x, c);
+    for (int q = 0; q < 3; ++q) {
+      float rr = in ? (Jf.p[q][v] + c[q] - Jt.p[q][v]) * a.inv_ne : 0.0f;
+      l += (double)rr * rr;
+      gJ.p[q][v] = a.gscale * rr;
+    }
+  }
+  double t = block_sum_d(l, sh);
+  if (threadIdx.x == 0) atomicAdd(loss, t * a.lscale);
+}
+
+// gA = s curl^T(gJ)
+__global__ void k_curl_adj(CurlArgs a, P3 G, W3 gA) {
+  const Box& B = a.B;
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  if (v >= nv) return;
+  int x = (int)(v % B.X);
+  int64_t r = v / B.X;
+  int y = (int)(r % B.Y), z = (int)(r / B.Y);
+  int64_t vy = B.at(z, wrapi(y + 1, B.Y), x), vx = B.at(z, y, wrapi(x + 1, B.X));
+  bool up = z + 1 < B.Z;
+  int64_t vz = up ? B.at(z + 1, y, x) : 0;
+  float gx = G.p[0][v], gy = G.p[1][v], gz = G.p[2][v];
+  float gxz = up ? G.p[0][vz] : 0.0f, gyz = up ? G.p[1][vz] : 0.0f;
+  gA.p[0][v] = a.s * ((gy - gyz) * a.ih - (gz - G.p[2][vy]) * a.ihy);
+  gA.p[1][v] = a.s * (-(gx - gxz) * a.ih + (gz - G.p[2][vx]) * a.ihx);
+  gA.p[2][v] = a.s * ((gx - G.p[0][vy]) * a.ihy - (gy - G.p[1][vx]) * a.ihx);
+}
+
+// Adam with bias correction (c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t))
+__global__ void k_adam(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.0f - b1) * gi;
+  float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+template <typename T>
+__global__ void k_zero(T* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (T)0;
+}
+
+unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct gempic_dn {
+  hipStream_t s = nullptr;
+  std::string err;
+  std::vector<void*> ptrs;
+  float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  u32x4* fw[NLAYER] = {};
+  u32x4* bw[NLAYER] = {};    // data-gradient packs of layers 1 .. 3
+  int64_t cap = 0;           // voxels the inference buffers hold
+  int64_t cap_train = 0;     // voxels the training buffers hold
+  unsigned short *act[3] = {}, *gact[3] = {};
+  float* A = nullptr;        // [3][cap]
+  float *tJf = nullptr, *tJt = nullptr, *tgJ = nullptr, *tgA = nullptr, *tA = nullptr;
+  unsigned short* tact[3] = {};
+  double* red = nullptr;     // num, den, loss
+  int* use_net = nullptr;
+  double* rel = nullptr;
+  int64_t* fallbacks = nullptr;
+  int64_t t = 0;             // Adam steps taken
+  bool packed = false;
+
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) ptrs.erase(it);
+    (void)hipFree(p);
+  }
+};
+
+static int dn_fail(gempic_dn* d, int code, const std::string& m) {
+  if (d) d->err = m;
+  return code;
+}
+
+#define DNCHK(d, expr)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return dn_fail(d, GEMPIC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static int check_box(gempic_dn* d, int Z, int Y, int X) {
+  if (Z < 1 || Y < TY || X < TX || Y % TY || X % TX)
+    return dn_fail(d, GEMPIC_EINVAL, "box must have Z >= 1, Y a multiple of 8 and X a multiple of 16");
+  return GEMPIC_OK;
+}
+
+static unsigned conv_blocks(int Z, int Y, int X) {
+  return (unsigned)((X / TX) * (Y / TY) * ((Z + TZ - 1) / TZ));
+}
+
+static int repack(gempic_dn* d, hipStream_t s) {
+  for (int l = 0; l < NLAYER; ++l) {
+    PackArgs p;
+    p.W = d->theta + layer_woff(l);
+    p.cin = L_CIN[l];
+    p.cout = L_COUT[l];
+    p.cinp = pad_in(L_CIN[l]);
+    p.coutp = pad_out(L_COUT[l]);
+    p.transpose = 0;
+    p.out = d->fw[l];
+    p.units = packed_units(p.cinp, p.coutp);
+    k_pack<<<nblk(p.units, 256), 256, 0, s>>>(p);
+    if (l > 0) {
+      p.cinp = pad_in(L_COUT[l]);
+      p.coutp = pad_out(L_CIN[l]);
+      p.transpose = 1;
+      p.out = d->bw[l];
+      p.units = packed_units(p.cinp, p.coutp);
+      k_pack<<<nblk(p.units, 256), 256, 0, s>>>(p);
+    }
+  }
+  d->packed = true;
+  return GEMPIC_OK;
+}
+
+static const float* bias_of(gempic_dn* d, int l) {
+  return d->theta + layer_woff(l) + (int64_t)L_COUT[l] * L_CIN[l] * 27;
+}
+
+// forward through the four layers: acts[0..2] (bf16), A (FP32 planar)
+static void net_forward(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const J[3],
+                        float in_scale, unsigned short* const acts[3], float* const Aout[3]) {
+  unsigned nb = conv_blocks(Z, Y, X);
+  ConvArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.Z = Z; a.Y = Y; a.X = X;
+  for (int q = 0; q < 3; ++q) a.inf[q] = J[q];
+  a.in_scale = in_scale;
+  a.wp = d->fw[0]; a.bias = bias_of(d, 0); a.out = acts[0];
+  k_conv<8, 16, 1, 0><<<nb, 256, 0, s>>>(a);
+  a.in = (const u32x4*)acts[0]; a.wp = d->fw[1]; a.bias = bias_of(d, 1); a.out = acts[1];
+  k_conv<16, 32, 0, 0><<<nb, 256, 0, s>>>(a);
+  a.in = (const u32x4*)acts[1]; a.wp = d->fw[2]; a.bias = bias_of(d, 2); a.out = acts[2];
+  k_conv<32, 16, 0, 0><<<nb, 256, 0, s>>>(a);
+  a.in = (const u32x4*)acts[2]; a.wp = d->fw[3]; a.bias = bias_of(d, 3); a.out = nullptr;
+  for (int q = 0; q < 3; ++q) a.outf[q] = Aout[q];
+  k_conv<16, 16, 0, 1><<<nb, 256, 0, s>>>(a);
+}
+
+static void filter(hipStream_t s, int Z, int Y, int X, const float* const in[3], float* const out[3],
+                   float* const tmp[3], int passes) {
+  Box B{Z, Y, X};
+  int64_t nv = (int64_t)Z * Y * X;
+  P3 pi{{in[0], in[1], in[2]}};
+  if (passes <= 0) {
+    for (int q = 0; q < 3; ++q) (void)hipMemcpyAsync(out[q], in[q], nv * 4, hipMemcpyDeviceToDevice, s);
+    return;
+  }
+  if (passes == 1) {
+    k_filter<<<nblk(nv, 256), 256, 0, s>>>(B, pi, W3{{out[0], out[1], out[2]}});
+    return;
+  }
+  k_filter<<<nblk(nv, 256), 256, 0, s>>>(B, pi, W3{{tmp[0], tmp[1], tmp[2]}});
+  k_filter<<<nblk(nv, 256), 256, 0, s>>>(B, P3{{tmp[0], tmp[1], tmp[2]}}, W3{{out[0], out[1], out[2]}});
+}
+
+int dn_reserve(gempic_dn* d, int64_t nv) {
+  if (nv <= d->cap) return GEMPIC_OK;
+  for (int q = 0; q < 3; ++q) { d->release(d->act[q]); d->act[q] = nullptr; }
+  d->release(d->A);
+  d->A = nullptr;
+  d->cap = 0;
+  d->act[0] = (unsigned short*)d->alloc(nv * 16 * 2);
+  d->act[1] = (unsigned short*)d->alloc(nv * 32 * 2);
+  d->act[2] = (unsigned short*)d->alloc(nv * 16 * 2);
+  d->A = (float*)d->alloc(nv * 3 * 4);
+  if (!d->act[0] || !d->act[1] || !d->act[2] || !d->A)
+    return dn_fail(d, GEMPIC_ENOMEM, "denoiser activation buffers");
+  d->cap = nv;
+  return GEMPIC_OK;
+}
+
+static int reserve_train(gempic_dn* d, int64_t nv) {
+  if (nv <= d->cap_train) return GEMPIC_OK;
+  for (int q = 0; q < 3; ++q) {
+    d->release(d->tact[q]); d->tact[q] = nullptr;
+    d->release(d->gact[q]); d->gact[q] = nullptr;
+  }
+  for (float** p : {&d->tJf, &d->tJt, &d->tgJ, &d->tgA, &d->tA}) { d->release(*p); *p = nullptr; }
+  d->cap_train = 0;
+  const int ch[3] = {16, 32, 16};
+  bool ok = true;
+  for (int q = 0; q < 3; ++q) {
+    d->tact[q] = (unsigned short*)d->alloc(nv * ch[q] * 2);
+    d->gact[q] = (unsigned short*)d->alloc(nv * ch[q] * 2);
+    ok = ok && d->tact[q] && d->gact[q];
+  }
+  for (float** p : {&d->tJf, &d->tJt, &d->tgJ, &d->tgA, &d->tA}) {
+    *p = (float*)d->alloc(nv * 3 * 4);
+    ok = ok && *p;
+  }
+  if (!ok) return dn_fail(d, GEMPIC_ENOMEM, "denoiser training buffers");
+  d->cap_train = nv;
+  return GEMPIC_OK;
+}
+
+static CurlArgs curl_args(int Z, int Y, int X, double n_e, const double hs[3]) {
+  CurlArgs c;
+  c.B = Box{Z, Y, X};
+  c.s = (float)(n_e * hs[2]);
+  c.ihx = (float)(1.0 / hs[0]);
+  c.ihy = (float)(1.0 / hs[1]);
+  c.ih = (float)(1.0 / hs[2]);
+  return c;
+}
+
+int dn_step(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const J[3], float* const Jf[3],
+            float* const Jd[3], float* const tmp[3], double n_e, const double hs[3], int passes, double thr,
+            int64_t* fallbacks, double* rel) {
+  int64_t nv = (int64_t)Z * Y * X;
+  int rc = check_box(d, Z, Y, X);
+  if (rc) return rc;
+  if (!(n_e > 0)) return dn_fail(d, GEMPIC_EINVAL, "denoiser needs n_e > 0");
+  if ((rc = dn_reserve(d, nv))) return rc;
+  if (!d->packed) repack(d, s);
+  filter(s, Z, Y, X, J, Jf, tmp, passes);
+  float* Ap[3] = {d->A, d->A + nv, d->A + 2 * nv};
+  net_forward(d, s, Z, Y, X, J, (float)(1.0 / n_e), d->act, Ap);
+  CurlArgs c = curl_args(Z, Y, X, n_e, hs);
+  k_combine<<<nblk(nv, 256), 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                          W3{{Jd[0], Jd[1], Jd[2]}}, d->red);
+  k_decide<<<1, 1, 0, s>>>(d->red, thr, d->use_net, rel ? rel : d->rel, fallbacks ? fallbacks : d->fallbacks);
+  k_select<<<nblk(nv, 256), 256, 0, s>>>(c.B, d->use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("denoiser launch: ") + hipGetErrorString(e));
+  return GEMPIC_OK;
+}
+
+const char* dn_error(const gempic_dn* d) { return d ? d->err.c_str() : ""; }
+
+// one crop of a training batch: accumulate gradients into d->grad
+static void train_crop(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const Jr[3],
+                       const float* const Jt[3], double n_e, const double hs[3], int passes, int lo, int hi,
+                       int nbatch) {
+  int64_t nv = (int64_t)Z * Y * X;
+  unsigned nb = conv_blocks(Z, Y, X);
+  float* Jf[3] = {d->tJf, d->tJf + nv, d->tJf + 2 * nv};
+  float* Jtf[3] = {d->tJt, d->tJt + nv, d->tJt + 2 * nv};
+  float* gJ[3] = {d->tgJ, d->tgJ + nv, d->tgJ + 2 * nv};
+  float* gA[3] = {d->tgA, d->tgA + nv, d->tgA + 2 * nv};
+  float* Ap[3] = {d->tA, d->tA + nv, d->tA + 2 * nv};
+  // gJ doubles as the scratch of a second filter pass (it is written later)
+  filter(s, Z, Y, X, Jr, Jf, gJ, passes);
+  filter(s, Z, Y, X, Jt, Jtf, gJ, passes);
+  float in_scale = (float)(1.0 / n_e);
+  net_forward(d, s, Z, Y, X, Jr, in_scale, d->tact, Ap);
+  LossArgs la;
+  la.c = curl_args(Z, Y, X, n_e, hs);
+  la.lo = lo;
+  la.hi = hi;
+  double N = 3.0 * (double)(hi - lo) * Y * X;
+  la.inv_ne = (float)(1.0 / n_e);
+  la.gscale = (float)(2.0 / (n_e * N * nbatch));
+  la.lscale = 1.0 / (N * nbatch);
+  k_loss<<<nblk(nv, 256), 256, 0, s>>>(la, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                       P3{{Jtf[0], Jtf[1], Jtf[2]}}, W3{{gJ[0], gJ[1], gJ[2]}}, d->red + 2);
+  k_curl_adj<<<nblk(nv, 256), 256, 0, s>>>(la.c, P3{{gJ[0], gJ[1], gJ[2]}}, W3{{gA[0], gA[1], gA[2]}});
+
+  float* gW[NLAYER];
+  float* gb[NLAYER];
+  for (int l = 0; l < NLAYER; ++l) {
+    gW[l] = d->grad + layer_woff(l);
+    gb[l] = gW[l] + (int64_t)L_COUT[l] * L_CIN[l] * 27;
+  }
+  WgradArgs w;
+  std::memset(&w, 0, sizeof(w));
+  w.Z = Z; w.Y = Y; w.X = X;
+  ConvArgs c;
+  std::memset(&c, 0, sizeof(c));
+  c.Z = Z; c.Y = Y; c.X = X;
+  // layer 4: gy = gA (planar), x = act3
+  w.x = (const u32x4*)d->tact[2];
+  for (int q = 0; q < 3; ++q) w.gyf[q] = gA[q];
+  w.gW = gW[3]; w.gb = gb[3];
+  k_wgrad<16, 3, 16, 4, 0, 1><<<nb, 256, 0, s>>>(w);
+  for (int q = 0; q < 3; ++q) c.inf[q] = gA[q];
+  c.in_scale = 1.0f;
+  c.wp = d->bw[3]; c.mask = d->tact[2]; c.out = d->gact[2];
+  k_conv<8, 16, 1, 2><<<nb, 256, 0, s>>>(c);
+  // layer 3: gy = g3 (16 ch), x = act2 (32 ch)
+  w.x = (const u32x4*)d->tact[1];
+  w.gy = (const u32x4*)d->gact[2];
+  w.gW = gW[2]; w.gb = gb[2];
+  k_wgrad<32, 16, 32, 16, 0, 0><<<nb, 256, 0, s>>>(w);
+  c.in = (const u32x4*)d->gact[2]; c.wp = d->bw[2]; c.mask = d->tact[1]; c.out = d->gact[1];
+  k_conv<16, 32, 0, 2><<<nb, 256, 0, s>>>(c);
+  // layer 2: gy = g2 (32 ch), x = act1 (16 ch)
+  w.x = (const u32x4*)d->tact[0];
+  w.gy = (const u32x4*)d->gact[1];
+  w.gW = gW[1]; w.gb = gb[1];
+  k_wgrad<16, 32, 16, 32, 0, 0><<<nb, 256, 0, s>>>(w);
+  c.in = (const u32x4*)d->gact[1]; c.wp = d->bw[1]; c.mask = d->tact[0]; c.out = d->gact[0];
+  k_conv<32, 16, 0, 2><<<nb, 256, 0, s>>>(c);
+  // layer 1: gy = g1 (16 ch), x = J / n_e (planar)
+  w.x = nullptr;
+  for (int q = 0; q < 3; ++q) w.xf[q] = Jr[q];
+  w.x_scale = in_scale;
+  w.gy = (const u32x4*)d->gact[0];
+  w.gW = gW[0]; w.gb = gb[0];
+  k_wgrad<3, 16, 4, 16, 1, 0><<<nb, 256, 0, s>>>(w);
+}
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t gempic_dn_nparams(void) { return (size_t)n_params(); }
+
+int gempic_dn_create(const float* theta, size_t n, void* stream, gempic_dn_t** out) {
+  if (!out) return GEMPIC_EINVAL;
+  *out = nullptr;
+  if (!theta || n != (size_t)n_params()) return GEMPIC_EINVAL;
+  gempic_dn* d = new gempic_dn();
+  d->s = (hipStream_t)stream;
+  size_t pb = (size_t)n_params() * 4;
+  d->theta = (float*)d->alloc(pb);
+  d->m = (float*)d->alloc(pb);
+  d->v = (float*)d->alloc(pb);
+  d->grad = (float*)d->alloc(pb);
+  bool ok = d->theta && d->m && d->v && d->grad;
+  for (int l = 0; l < NLAYER; ++l) {
+    d->fw[l] = (u32x4*)d->alloc(packed_units(pad_in(L_CIN[l]), pad_out(L_COUT[l])) * 16);
+    ok = ok && d->fw[l];
+    if (l > 0) {
+      d->bw[l] = (u32x4*)d->alloc(packed_units(pad_in(L_COUT[l]), pad_out(L_CIN[l])) * 16);
+      ok = ok && d->bw[l];
+    }
+  }
+  d->red = (double*)d->alloc(4 * 8);
+  d->use_net = (int*)d->alloc(sizeof(int));
+  d->rel = (double*)d->alloc(8);
+  d->fallbacks = (int64_t*)d->alloc(8);
+  ok = ok && d->red && d->use_net && d->rel && d->fallbacks;
+  if (!ok) { gempic_dn_destroy(d); return GEMPIC_ENOMEM; }
+  hipStream_t s = d->s;
+  bool cp = hipMemcpyAsync(d->theta, theta, pb, hipMemcpyHostToDevice, s) == hipSuccess;
+  k_zero<float><<<nblk(n_params(), 256), 256, 0, s>>>(d->m, n_params());
+  k_zero<float><<<nblk(n_params(), 256), 256, 0, s>>>(d->v, n_params());
+  k_zero<float><<<nblk(n_params(), 256), 256, 0, s>>>(d->grad, n_params());
+  k_zero<double><<<1, 64, 0, s>>>(d->red, 4);
+  k_zero<double><<<1, 64, 0, s>>>(d->rel, 1);
+  k_zero<int64_t><<<1, 64, 0, s>>>(d->fallbacks, 1);
+  repack(d, s);
+  if (!cp || hipStreamSynchronize(s) != hipSuccess) { gempic_dn_destroy(d); return GEMPIC_EDEVICE; }
+  *out = d;
+  return GEMPIC_OK;
+}
+
+void gempic_dn_destroy(gempic_dn_t* d) {
+  if (!d) return;
+  (void)hipStreamSynchronize(d->s);
+  for (void* p : d->ptrs) (void)hipFree(p);
+  delete d;
+}
+
+const char* gempic_dn_last_error(const gempic_dn_t* d) { return dn_error(d); }
+
+int gempic_dn_params(gempic_dn_t* d, float* theta, size_t n) {
+  if (!d || !theta || n < (size_t)n_params()) return dn_fail(d, GEMPIC_EINVAL, "bad arguments");
+  DNCHK(d, hipMemcpyAsync(theta, d->theta, n_params() * 4, hipMemcpyDeviceToHost, d->s));
+  DNCHK(d, hipStreamSynchronize(d->s));
+  return GEMPIC_OK;
+}
+
+int gempic_dn_grad(gempic_dn_t* d, float* grad, size_t n) {
+  if (!d || !grad || n < (size_t)n_params()) return dn_fail(d, GEMPIC_EINVAL, "bad arguments");
+  DNCHK(d, hipMemcpyAsync(grad, d->grad, n_params() * 4, hipMemcpyDeviceToHost, d->s));
+  DNCHK(d, hipStreamSynchronize(d->s));
+  return GEMPIC_OK;
+}
+
+int gempic_dn_apply(gempic_dn_t* d, const int32_t box[3], const float* jraw, double n_e, const double h[3],
+                    int32_t passes, double threshold, float* jout, float* aout, int32_t* used, double* rel) {
+  if (!d || !box || !jraw || !h || !jout) return dn_fail(d, GEMPIC_EINVAL, "null argument");
+  if (passes < 0 || passes > 2) return dn_fail(d, GEMPIC_EINVAL, "passes must be 0, 1 or 2");
+  int Z = box[0], Y = box[1], X = box[2];
+  int rc = check_box(d, Z, Y, X);
+  if (rc) return rc;
+  int64_t nv = (int64_t)Z * Y * X;
+  if ((rc = reserve_train(d, nv))) return rc;   // filtered current and scratch
+  const float* J[3] = {jraw, jraw + nv, jraw + 2 * nv};
+  float* Jf[3] = {d->tJf, d->tJf + nv, d->tJf + 2 * nv};
+  float* tmp[3] = {d->tgJ, d->tgJ + nv, d->tgJ + 2 * nv};
+  float* Jd[3] = {jout, jout + nv, jout + 2 * nv};
+  rc = dn_step(d, d->s, Z, Y, X, J, Jf, Jd, tmp, n_e, h, passes, threshold, nullptr, nullptr);
+  if (rc) return rc;
+  if (aout) DNCHK(d, hipMemcpyAsync(aout, d->A, nv * 3 * 4, hipMemcpyDeviceToDevice, d->s));
+  int un = 0;
+  double rv = 0.0;
+  DNCHK(d, hipMemcpyAsync(&un, d->use_net, sizeof(int), hipMemcpyDeviceToHost, d->s));
+  DNCHK(d, hipMemcpyAsync(&rv, d->rel, 8, hipMemcpyDeviceToHost, d->s));
+  DNCHK(d, hipStreamSynchronize(d->s));
+  if (used) *used = un;
+  if (rel) *rel = rv;
+  return GEMPIC_OK;
+}
+
+int gempic_dn_train(gempic_dn_t* d, const int32_t box[3], int32_t nbatch, const float* jraw,
+                    const float* jtarget, double n_e, const double h[3], int32_t passes, const int32_t region[2],
+                    double lr, double* loss) {
+  if (!d || !box || !jraw || !jtarget || !h || !region) return dn_fail(d, GEMPIC_EINVAL, "null argument");
+  if (nbatch < 1) return dn_fail(d, GEMPIC_EINVAL, "nbatch must be >= 1");
+  if (passes < 0 || passes > 2) return dn_fail(d, GEMPIC_EINVAL, "passes must be 0, 1 or 2");
+  if (!(n_e > 0)) return dn_fail(d, GEMPIC_EINVAL, "n_e must be > 0");
+  int Z = box[0], Y = box[1], X = box[2];
+  int rc = check_box(d, Z, Y, X);
+  if (rc) return rc;
+  if (region[0] < 0 || region[1] > Z || region[0] >= region[1])
+    return dn_fail(d, GEMPIC_EINVAL, "region must satisfy 0 <= lo < hi <= Z");
+  int64_t nv = (int64_t)Z * Y * X;
+  if ((rc = reserve_train(d, nv))) return rc;
+  hipStream_t s = d->s;
+  k_zero<float><<<nblk(n_params(), 256), 256, 0, s>>>(d->grad, n_params());
+  k_zero<double><<<1, 64, 0, s>>>(d->red + 2, 1);
+  for (int b = 0; b < nbatch; ++b) {
+    const float* jr = jraw + (int64_t)b * 3 * nv;
+    const float* jt = jtarget + (int64_t)b * 3 * nv;
+    const float* Jr[3] = {jr, jr + nv, jr + 2 * nv};
+    const float* Jt[3] = {jt, jt + nv, jt + 2 * nv};
+    train_crop(d, s, Z, Y, X, Jr, Jt, n_e, h, passes, region[0], region[1], nbatch);
+  }
+  if (lr > 0) {
+    d->t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)d->t)));
+    float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)d->t)));
+    k_adam<<<nblk(n_params(), 256), 256, 0, s>>>(d->theta, d->m, d->v, d->grad, n_params(), (float)lr,
+                                                 (float)b1, (float)b2, 1e-8f, c1, c2);
+    repack(d, s);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("training launch: ") + hipGetErrorString(e));
+  if (loss) {
+    DNCHK(d, hipMemcpyAsync(loss, d->red + 2, 8, hipMemcpyDeviceToHost, s));
+    DNCHK(d, hipStreamSynchronize(s));
+  }
+  return GEMPIC_OK;
+}
+
+}  // extern "C"

@@ -9,8 +9,10 @@
 #include <vector>
 
 #include "../../include/gempic.h"
+#include "../../include/gempic_denoise.h"
 #include "common.h"
 #include "diag.h"
+#include "dn_internal.h"
 #include "fields.h"
 #include "particles.h"
 
@@ -76,6 +78,14 @@ struct gempic {
   void* twy;
   double* partial;
   double* dres;
+  // learned current denoiser (not owned): filtered and denoised currents
+  gempic_dn* dn;
+  double dn_thr;
+  void* Jf[3];
+  void* Jd[3];
+  void* Jt[3];
+  int64_t* dn_fallbacks;
+  double* dn_rel;
   // timing: five events per step while enabled
   bool timing;
   std::vector<hipEvent_t> ev;
@@ -174,12 +184,16 @@ struct Impl {
   }
 
   // ---- field update: FFT(J) -> march -> iFFT ------------------------------
+  // The solver filters the current itself unless the denoiser has already
+  // produced the current it is to use (filter passes 0 in the march).
   static void field_update(gempic* g, bool with_current, T Delta) {
     const Geom& G = g->g;
     MarchArgs<T> a;
     a.g = G;
+    bool den = with_current && g->dn;
+    if (den) a.g.P = 0;
     for (int q = 0; q < 3; ++q) {
-      if (with_current) fft_fwd(g, (const T*)g->J[q], (C*)g->Jhat[q], G.NPF);
+      if (with_current) fft_fwd(g, (const T*)(den ? g->Jd[q] : g->J[q]), (C*)g->Jhat[q], G.NPF);
       a.J[q] = with_current ? (const C*)g->Jhat[q] : nullptr;
     }
     for (int q = 0; q < 4; ++q) a.st[q] = (C*)g->st[q];
@@ -387,6 +401,17 @@ struct Impl {
     rc = sort_and_inject(g, g->step + 1);
     if (rc) return rc;
     if ((rc = mark(g, 3))) return rc;
+    if (g->dn) {
+      if (sizeof(T) != 4) return fail(g, GEMPIC_EINVAL, "denoiser needs FP32");
+      const double hs[3] = {G.hx, G.hy, G.h};
+      const float* J[3] = {(const float*)g->J[0], (const float*)g->J[1], (const float*)g->J[2]};
+      float* Jf[3] = {(float*)g->Jf[0], (float*)g->Jf[1], (float*)g->Jf[2]};
+      float* Jd[3] = {(float*)g->Jd[0], (float*)g->Jd[1], (float*)g->Jd[2]};
+      float* Jt[3] = {(float*)g->Jt[0], (float*)g->Jt[1], (float*)g->Jt[2]};
+      rc = dn_step(g->dn, g->s, G.NPJ, G.Ny, G.Nx, J, Jf, Jd, Jt, g->cfg.n_e, hs, G.P, g->dn_thr,
+                   g->dn_fallbacks, g->dn_rel);
+      if (rc) return fail(g, rc, std::string("denoiser: ") + dn_error(g->dn));
+    }
     field_update(g, true, (T)G.dtau);
     if ((rc = mark(g, 4))) return rc;
     if (g->timing) g->tsteps += 1;
@@ -475,6 +500,12 @@ struct Impl {
     k_final<<<1, 256, 0, g->s>>>(g->partial, DIAG_BLOCKS, 1, g->dres);
     double res[4] = {0, 0, 0, 0};
     int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+    d->fallbacks = 0;
+    d->denoise_rel = 0.0;
+    if (g->dn_fallbacks) {
+      HIPCHK(g, hipMemcpyAsync(&d->fallbacks, g->dn_fallbacks, 8, hipMemcpyDeviceToHost, g->s));
+      HIPCHK(g, hipMemcpyAsync(&d->denoise_rel, g->dn_rel, 8, hipMemcpyDeviceToHost, g->s));
+    }
     if (g->cfg.deposit_rho) {
       k_partial<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->rho[1], nullptr, nullptr, nullptr, nullptr,
                                                   nullptr, 1, nJ, 0, g->partial + 2 * DIAG_BLOCKS);
@@ -923,6 +954,38 @@ int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes) {
       k_interleave<float><<<nblk(nf, 256), 256, 0, g->s>>>((float*)g->F6, (const float*)g->outs[0], q, nf);
   }
   HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
+int gempic_set_denoiser(gempic_t* g, gempic_dn_t* d, double threshold) {
+  if (!g) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  const Geom& G = g->g;
+  if (!d) { g->dn = nullptr; return GEMPIC_OK; }
+  if (g->prec != 1 || G.dims != 3) return fail(g, GEMPIC_EINVAL, "the denoiser needs an FP32 3-D simulation");
+  if (G.Nx % 16 || G.Ny % 8) return fail(g, GEMPIC_EINVAL, "the denoiser needs Nx % 16 == 0 and Ny % 8 == 0");
+  if (!(g->cfg.n_e > 0)) return fail(g, GEMPIC_EINVAL, "the denoiser needs a plasma (n_e > 0)");
+  if (threshold != threshold) return fail(g, GEMPIC_EINVAL, "threshold is NaN");
+  int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+  if (!g->Jf[0]) {
+    bool ok = true;
+    for (int q = 0; q < 3; ++q) {
+      g->Jf[q] = g->dev.alloc(nJ * 4);
+      g->Jd[q] = g->dev.alloc(nJ * 4);
+      g->Jt[q] = g->dev.alloc(nJ * 4);
+      ok = ok && g->Jf[q] && g->Jd[q] && g->Jt[q];
+    }
+    g->dn_fallbacks = (int64_t*)g->dev.alloc(8);
+    g->dn_rel = (double*)g->dev.alloc(8);
+    if (!ok || !g->dn_fallbacks || !g->dn_rel) return fail(g, GEMPIC_ENOMEM, "denoiser current buffers");
+    k_fill<int64_t><<<1, 64, 0, g->s>>>(g->dn_fallbacks, 1, 0);
+    k_fill<double><<<1, 64, 0, g->s>>>(g->dn_rel, 1, 0.0);
+  }
+  int rc = dn_reserve(d, nJ);
+  if (rc) return fail(g, rc, std::string("denoiser: ") + dn_error(d));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  g->dn = d;
+  g->dn_thr = threshold;
   return GEMPIC_OK;
 }
 

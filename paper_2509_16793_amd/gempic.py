@@ -1,9 +1,11 @@
-"""Thin ctypes binding of the gfx950 Galilean PIC library (include/gempic.h).
+"""Thin ctypes binding of the gfx950 Galilean PIC library (include/gempic.h,
+include/gempic_denoise.h).
 
 Argument marshalling only: every step of the path runs in the HIP library.
 The functions keep the C names (gempic_create, gempic_step, gempic_fields,
-gempic_particles, gempic_set_state, gempic_get_spectral, gempic_destroy);
-``Sim`` wraps a handle for tests and the benchmark.  PyTorch is optional and
+gempic_particles, gempic_set_state, gempic_get_spectral, gempic_destroy,
+gempic_dn_*); ``Sim`` and ``Denoiser`` wrap handles for tests and the
+benchmark.  PyTorch is optional and
 only supplies device buffers and the current stream.
 """
 import ctypes
@@ -48,6 +50,7 @@ class gempic_diag(ctypes.Structure):
         ("tau", ctypes.c_double), ("step", ctypes.c_int64), ("n_particles", ctypes.c_int64),
         ("charge_particles", ctypes.c_double), ("charge_grid", ctypes.c_double),
         ("field_energy", ctypes.c_double), ("continuity_rel", ctypes.c_double),
+        ("fallbacks", ctypes.c_int64), ("denoise_rel", ctypes.c_double),
     ]
 
 
@@ -74,6 +77,23 @@ _SIGS = {
     "gempic_destroy": (None, [ctypes.c_void_p]),
     "gempic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gempic_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "gempic_set_denoiser": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
+    "gempic_dn_nparams": (ctypes.c_size_t, []),
+    "gempic_dn_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "gempic_dn_destroy": (None, [ctypes.c_void_p]),
+    "gempic_dn_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "gempic_dn_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "gempic_dn_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "gempic_dn_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p,
+                                       ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "gempic_dn_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -178,6 +198,16 @@ def gempic_destroy(h):
     lib().gempic_destroy(h)
 
 
+def gempic_set_denoiser(h, dn, threshold):
+    _check(lib().gempic_set_denoiser(h, dn, float(threshold)), h)
+
+
+def _dn_check(rc, d):
+    if rc != 0:
+        msg = lib().gempic_dn_last_error(d)
+        raise GempicError(rc, msg.decode() if msg else "")
+
+
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
@@ -257,6 +287,22 @@ class Sim:
         ms, n = gempic_get_timing(self.h)
         return dict(zip(("clear", "push_deposit", "sort_window", "fields", "step"), ms)), n
 
+    def fields_device(self, names, out):
+        """Copy fields into a contiguous device tensor ``out`` (torch), in
+        the order of ``names``, each [planes][Ny][Nx]."""
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_NAMES.index(nm)
+        if [nm for nm in FIELD_NAMES if mask & (1 << FIELD_NAMES.index(nm))] != list(names):
+            raise ValueError("names must follow the library order " + str(FIELD_NAMES))
+        gempic_fields(self.h, mask, 1, ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size())
+        return out
+
+    def set_denoiser(self, dn, threshold=1e-3):
+        """Attach a Denoiser (None detaches); the Denoiser must outlive it."""
+        gempic_set_denoiser(self.h, None if dn is None else dn.h, threshold)
+        self._dn = dn
+
     def set_fields(self, F6):
         a = np.ascontiguousarray(F6, self.dtype)
         gempic_set_fields(self.h, _ptr(a), a.nbytes)
@@ -270,3 +316,72 @@ class Sim:
         idv = None if ids is None else np.ascontiguousarray(ids, np.int64)
         gempic_set_state(self.h, step, _ptr(cell), _ptr(off), _ptr(u), _ptr(idv), len(cell),
                          _ptr(sp), 0 if sp is None else sp.nbytes)
+
+
+class Denoiser:
+    """Handle of the learned current denoiser (include/gempic_denoise.h).
+    Currents are contiguous float32 device tensors [.., 3, Z, Y, X]."""
+
+    def __init__(self, theta, stream=None):
+        theta = np.ascontiguousarray(theta, np.float32)
+        n = lib().gempic_dn_nparams()
+        if theta.size != n:
+            raise ValueError(f"expected {n} parameters, got {theta.size}")
+        self.h = ctypes.c_void_p()
+        _dn_check(lib().gempic_dn_create(_ptr(theta), n, stream, ctypes.byref(self.h)), None)
+        self.n = n
+
+    def close(self):
+        if self.h:
+            lib().gempic_dn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        a = np.empty(self.n, np.float32)
+        _dn_check(lib().gempic_dn_params(self.h, _ptr(a), self.n), self.h)
+        return a
+
+    def grad(self):
+        a = np.empty(self.n, np.float32)
+        _dn_check(lib().gempic_dn_grad(self.h, _ptr(a), self.n), self.h)
+        return a
+
+    @staticmethod
+    def _dptr(t):
+        if not (t.is_contiguous() and str(t.dtype) == "torch.float32" and t.is_cuda):
+            raise ValueError("expected a contiguous float32 device tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply(self, jraw, n_e, h, passes=1, threshold=1e-3, jout=None, aout=None):
+        """jraw [3, Z, Y, X] -> (J, used, rel); A into ``aout`` if given."""
+        import torch
+        box = (ctypes.c_int32 * 3)(*jraw.shape[1:])
+        if jout is None:
+            jout = torch.empty_like(jraw)
+        used = ctypes.c_int32()
+        rel = ctypes.c_double()
+        hs = (ctypes.c_double * 3)(*h)
+        _dn_check(lib().gempic_dn_apply(self.h, box, self._dptr(jraw), float(n_e), hs, int(passes),
+                                        float(threshold), self._dptr(jout),
+                                        None if aout is None else self._dptr(aout),
+                                        ctypes.byref(used), ctypes.byref(rel)), self.h)
+        return jout, bool(used.value), rel.value
+
+    def train(self, jraw, jtarget, n_e, h, region, lr, passes=1):
+        """One step over a batch [B, 3, Z, Y, X]; returns the batch loss."""
+        if jraw.shape != jtarget.shape or jraw.dim() != 5:
+            raise ValueError("jraw and jtarget must both be [B, 3, Z, Y, X]")
+        box = (ctypes.c_int32 * 3)(*jraw.shape[2:])
+        reg = (ctypes.c_int32 * 2)(*region)
+        hs = (ctypes.c_double * 3)(*h)
+        loss = ctypes.c_double()
+        _dn_check(lib().gempic_dn_train(self.h, box, int(jraw.shape[0]), self._dptr(jraw),
+                                        self._dptr(jtarget), float(n_e), hs, int(passes), reg,
+                                        float(lr), ctypes.byref(loss)), self.h)
+        return loss.value

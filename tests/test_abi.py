@@ -15,14 +15,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "gempic.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gempic_[a-z_]+)\s*\(", src)))
+    names = set()
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(gempic_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
-    assert "gempic_create" in names and "gempic_step" in names
+    assert "gempic_create" in names and "gempic_step" in names and "gempic_dn_train" in names
     L = gp.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -35,7 +39,7 @@ def test_struct_layout_matches_header():
     c = gp.gempic_config
     assert c.stream.offset % 8 == 0
     assert ctypes.sizeof(c) == c.stream.offset + 8
-    assert ctypes.sizeof(gp.gempic_diag) == 56
+    assert ctypes.sizeof(gp.gempic_diag) == 72
 
 
 def _create(cfg, **kw):
@@ -81,3 +85,13 @@ def test_rejects_non_power_of_two_and_bad_tile():
 def test_strerror():
     for code in range(0, -9, -1):
         assert gp.lib().gempic_strerror(code)
+
+
+def test_denoiser_parameter_count_and_rejections():
+    L = gp.lib()
+    assert L.gempic_dn_nparams() == 30307
+    h = ctypes.c_void_p()
+    assert L.gempic_dn_create(None, 30307, None, ctypes.byref(h)) == -1 and not h.value
+    assert L.gempic_dn_create(None, 5, None, ctypes.byref(h)) == -1
+    assert L.gempic_dn_apply(None, None, None, 1.0, None, 1, 1e-3, None, None, None, None) == -1
+    assert L.gempic_set_denoiser(None, None, 1e-3) == -1
