@@ -462,14 +462,18 @@ GP_DEV double block_sum_d(double v, double* sh) {
   return t;
 }
 
-// Jd = Jf + s curl(A); red[0] += |D.(s curl A)|^2, red[1] += |D.Jf|^2
-__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd, double* red) {
+// Jd = Jf + s curl(A); per-block partial sums of |D.(s curl A)|^2 and
+// |D.Jf|^2 into part[2 * block + {0, 1}] (a fixed grid of COMB_BLOCKS
+// blocks strides over the box, so that the sums need no global atomics)
+constexpr int COMB_BLOCKS = 2048;
+
+__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd, double* part) {
   __shared__ double sh[4];
   const Box& B = a.B;
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nv = (int64_t)B.Z * B.Y * B.X;
   double num = 0.0, den = 0.0;
-  if (v < nv) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+       v += (int64_t)gridDim.x * blockDim.x) {
     int x = (int)(v % B.X);
     int64_t r = v / B.X;
     int y = (int)(r % B.Y), z = (int)(r / B.Y);
@@ -484,28 +488,36 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
     float fz = z > 0 ? Jf.p[2][B.at(z - 1, y, x)] : 0.0f;
     double df = (double)(Jf.p[0][v] - Jf.p[0][vx]) * a.ihx + (double)(Jf.p[1][v] - Jf.p[1][vy]) * a.ihy +
                 (double)(Jf.p[2][v] - fz) * a.ih;
-    num = dc * dc;
-    den = df * df;
+    num += dc * dc;
+    den += df * df;
   }
   double tn = block_sum_d(num, sh);
   __syncthreads();
   double td = block_sum_d(den, sh);
   if (threadIdx.x == 0) {
-    atomicAdd(&red[0], tn);
-    atomicAdd(&red[1], td);
+    part[2 * blockIdx.x] = tn;
+    part[2 * blockIdx.x + 1] = td;
   }
 }
 
-// decide between the corrected and the filtered current; reset the sums
-__global__ void k_decide(double* red, double thr, int* use_net, double* rel, int64_t* fallbacks) {
-  double num = red[0], den = red[1];
+// sum the partials and decide between the corrected and the filtered current
+__global__ __launch_bounds__(256) void k_decide(const double* part, int nparts, double thr, int* use_net,
+                                                double* rel, int64_t* fallbacks) {
+  __shared__ double sh[4];
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    num += part[2 * i];
+    den += part[2 * i + 1];
+  }
+  num = block_sum_d(num, sh);
+  __syncthreads();
+  den = block_sum_d(den, sh);
+  if (threadIdx.x != 0) return;
   double q = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
   int ok = q <= thr;                         // false for NaN
   *use_net = ok;
   if (rel) *rel = q;
   if (!ok && fallbacks) *fallbacks += 1;
-  red[0] = 0.0;
-  red[1] = 0.0;
 }
 
 __global__ void k_select(Box B, const int* use_net, P3 Jf, W3 Jd) {
@@ -604,7 +616,8 @@ struct gempic_dn {
   float* A = nullptr;        // [3][cap]
   float *tJf = nullptr, *tJt = nullptr, *tgJ = nullptr, *tgA = nullptr, *tA = nullptr;
   unsigned short* tact[3] = {};
-  double* red = nullptr;     // num, den, loss
+  double* red = nullptr;     // loss
+  double* part = nullptr;    // partial sums of the continuity test
   int* use_net = nullptr;
   double* rel = nullptr;
   int64_t* fallbacks = nullptr;
@@ -776,9 +789,10 @@ int dn_step(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const
   float* Ap[3] = {d->A, d->A + nv, d->A + 2 * nv};
   net_forward(d, s, Z, Y, X, J, (float)(1.0 / n_e), d->act, Ap);
   CurlArgs c = curl_args(Z, Y, X, n_e, hs);
-  k_combine<<<nblk(nv, 256), 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
-                                          W3{{Jd[0], Jd[1], Jd[2]}}, d->red);
-  k_decide<<<1, 1, 0, s>>>(d->red, thr, d->use_net, rel ? rel : d->rel, fallbacks ? fallbacks : d->fallbacks);
+  k_combine<<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                        W3{{Jd[0], Jd[1], Jd[2]}}, d->part);
+  k_decide<<<1, 256, 0, s>>>(d->part, COMB_BLOCKS, thr, d->use_net, rel ? rel : d->rel,
+                             fallbacks ? fallbacks : d->fallbacks);
   k_select<<<nblk(nv, 256), 256, 0, s>>>(c.B, d->use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("denoiser launch: ") + hipGetErrorString(e));
@@ -885,10 +899,11 @@ int gempic_dn_create(const float* theta, size_t n, void* stream, gempic_dn_t** o
     }
   }
   d->red = (double*)d->alloc(4 * 8);
+  d->part = (double*)d->alloc(2 * COMB_BLOCKS * 8);
   d->use_net = (int*)d->alloc(sizeof(int));
   d->rel = (double*)d->alloc(8);
   d->fallbacks = (int64_t*)d->alloc(8);
-  ok = ok && d->red && d->use_net && d->rel && d->fallbacks;
+  ok = ok && d->red && d->part && d->use_net && d->rel && d->fallbacks;
   if (!ok) { gempic_dn_destroy(d); return GEMPIC_ENOMEM; }
   hipStream_t s = d->s;
   bool cp = hipMemcpyAsync(d->theta, theta, pb, hipMemcpyHostToDevice, s) == hipSuccess;
