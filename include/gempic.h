@@ -77,7 +77,8 @@ typedef struct {
   double  dtau;             /* slow step, config units; 0 selects h / 2.  2 dtau > h or
                                dtau * h > 4 / n_e is rejected with GEMPIC_ECFL          */
   int32_t precision;        /* gempic_precision                                         */
-  int32_t tile[3];          /* particle tile in cells; must divide n; 2-D: tile[1] = 1  */
+  int32_t tile[3];          /* particle tile in cells: 8x8x8, 8x8x4 or 4x4x4 (2-D:
+                               8x1x8, 8x1x4 or 4x1x4); must divide n                     */
   double  n_e;              /* electron density (units of the critical density); 0 = vacuum */
   int32_t ppc[3];           /* macro-particles per cell along x, y, zeta (2-D: ppc[1]=1) */
   int32_t load;             /* 0 = stratified random (SplitMix64), 1 = quiet lattice    */

@@ -343,9 +343,22 @@ struct Impl {
     int e2 = (int)std::floor(std::log2(sc));
     a.fscale = (T)std::ldexp(1.0, e2);
     a.finv = (T)std::ldexp(1.0, -e2);
-    a.ct = g->ct[g->ctc];
+    a.tile_base = g->tile_base;
+    a.tile_count = g->tile_count;
+    a.total = g->total;
+    // zeta segments: enough work-groups to fill the chip several times over,
+    // long segments so that most current planes are carried, not flushed
+    int ncol = G.nTx * G.nTy;
+    int nseg = std::min(G.nTz, std::max(1, (8192 + ncol - 1) / ncol));
+    a.seg_len = (G.nTz + nseg - 1) / nseg;
+    a.nseg = (G.nTz + a.seg_len - 1) / a.seg_len;
     a.err = g->err_dev;
     return a;
+  }
+
+  static unsigned push_blocks(const PushArgs<T>& a) {
+    int nitem = a.g.nTx * a.g.nTy * a.nseg;
+    return (unsigned)(8 * ((nitem + 7) / 8));
   }
 
   static void set_lds_limits() {
@@ -355,10 +368,15 @@ struct Impl {
     (void)hipFuncSetAttribute((const void*)k_fft_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   }
 
+  // work-group size: the register budget (about 96 VGPRs) allows five waves
+  // per SIMD, so small tiles (whose LDS footprint allows five work-groups per
+  // CU) run one wave per SIMD per work-group
   template <int DIM, int TX, int TY, int TZ>
   static void push_tile(gempic* g, const PushArgs<T>& a, PartPtrs<T> P, bool rho) {
-    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ><<<g->max_chunks, 512, 0, g->s>>>(a, P);
-    else k_push_deposit<T, DIM, false, TX, TY, TZ><<<g->max_chunks, 512, 0, g->s>>>(a, P);
+    unsigned nb = push_blocks(a);
+    constexpr int NTHR = TZ == 8 ? 512 : 256;
+    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR><<<nb, NTHR, 0, g->s>>>(a, P);
+    else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR><<<nb, NTHR, 0, g->s>>>(a, P);
   }
 
   static void launch_push(gempic* g) {
@@ -367,10 +385,12 @@ struct Impl {
     PushArgs<T> a = push_args(g);
     PartPtrs<T> P = parts(g, g->cur);
     if (G.dims == 3) {
-      if (G.Tx == 8) push_tile<3, 8, 8, 8>(g, a, P, rho);
+      if (G.Tx == 8 && G.Tz == 8) push_tile<3, 8, 8, 8>(g, a, P, rho);
+      else if (G.Tx == 8) push_tile<3, 8, 8, 4>(g, a, P, rho);
       else push_tile<3, 4, 4, 4>(g, a, P, rho);
     } else {
-      if (G.Tx == 8) push_tile<2, 8, 1, 8>(g, a, P, rho);
+      if (G.Tx == 8 && G.Tz == 8) push_tile<2, 8, 1, 8>(g, a, P, rho);
+      else if (G.Tx == 8) push_tile<2, 8, 1, 4>(g, a, P, rho);
       else push_tile<2, 4, 1, 4>(g, a, P, rho);
     }
   }
@@ -558,9 +578,10 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->Tx = c->tile[0];
   G->Ty = c->dims == 3 ? c->tile[1] : 1;
   G->Tz = c->tile[2];
-  bool tile_ok = (G->Tx == 8 || G->Tx == 4) && G->Tz == G->Tx && (c->dims == 2 || G->Ty == G->Tx);
+  bool tile_ok = (c->dims == 2 || G->Ty == G->Tx) &&
+                 ((G->Tx == 8 && (G->Tz == 8 || G->Tz == 4)) || (G->Tx == 4 && G->Tz == 4));
   if (!tile_ok || G->Nx % G->Tx || G->Ny % G->Ty || G->Nz % G->Tz) {
-    *why = "tile must be 8x8x8 or 4x4x4 (2-D: 8x1x8 or 4x1x4) and divide the grid";
+    *why = "tile must be 8x8x8, 8x8x4 or 4x4x4 (2-D: 8x1x8, 8x1x4 or 4x1x4) and divide the grid";
     return GEMPIC_EINVAL;
   }
   G->lnx = 0; while ((1 << G->lnx) < G->Nx) ++G->lnx;

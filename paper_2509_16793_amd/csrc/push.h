@@ -1,4 +1,9 @@
-// Fused gather + push + move + deposit: one work-group per chunk of a tile.
+// Fused gather + push + move + deposit.  A work-group walks a segment of a
+// column of tiles (fixed transverse tile, increasing zeta tile) and takes
+// every particle of each tile in one pass.  Particles only move towards -zeta
+// (at most one cell), so the current planes a tile shares with the next tile
+// of the column stay in LDS and only the planes no later tile touches are
+// flushed; the last node plane of the field tile is likewise carried over.
 //
 // Gather: linear (CIC) weights on the 8 (3-D) / 4 (2-D) nodes around the
 // particle, from an LDS copy of the tile's (T+1)^3 node records (E, B
@@ -37,7 +42,11 @@ struct PushArgs {
   T cjy;               // 2-D out-of-plane: q w / (hx h)
   T crho;              // q w / V
   T fscale, finv;      // fixed-point scale of the LDS tile (power of two) and its inverse
-  ChunkTab ct;
+  const int64_t* tile_base;   // [NT] first particle of each tile
+  const int64_t* tile_count;  // [NT] particles of each tile
+  const int64_t* total;       // particles in the buffer (0 after a capacity overflow)
+  int seg_len;                // zeta tiles per work-group segment
+  int nseg;                   // segments per column
   int* err;
 };
 
@@ -58,7 +67,13 @@ template <> struct Fix<double> {
   using t = unsigned long long;
   static GP_DEV unsigned long long to(double v) { return (unsigned long long)__double2ll_rn(v); }
 };
-GP_DEV double fix_value(unsigned long long v) { return (double)(long long)v; }
+// fixed-point sum -> value: exact rounding in FP64, within two ulp in FP32
+template <typename T>
+GP_DEV T fix_value(unsigned long long v) {
+  T hi = (T)(int)(unsigned)(v >> 32);
+  T lo = (T)(unsigned)(v & 0xFFFFFFFFull);
+  return hi * (T)4294967296.0 + lo;
+}
 
 // 3-node window starting at min(c0, c0 + k): old and new linear weights.
 template <typename T>
@@ -72,56 +87,121 @@ GP_DEV void window3(int k, T d0, T d1, T* S0, T* S1) {
   }
 }
 
-template <typename T, int DIM, bool RHO, int TX, int TY, int TZ>
-__global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
+// particle state of one lane, loaded one row ahead of its use
+template <typename T>
+struct PLoad {
+  int cell;
+  T ox, oy, oz, ux, uy, uz;
+};
+
+template <typename T, int DIM>
+GP_DEV PLoad<T> load_particle(const PartPtrs<T>& P, int p, bool ok) {
+  PLoad<T> s;
+  if (ok) {
+    s.cell = P.cell[p];
+    s.ox = P.ox[p];
+    s.oy = DIM == 3 ? P.oy[p] : (T)0;
+    s.oz = P.oz[p];
+    s.ux = P.ux[p];
+    s.uy = P.uy[p];
+    s.uz = P.uz[p];
+  } else {
+    s.cell = 0;
+    s.ox = s.oy = s.oz = s.ux = s.uy = s.uz = (T)0;
+  }
+  return s;
+}
+
+template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
   constexpr int FX = TX + 1, FY = DIM == 3 ? TY + 1 : 1, FZ = TZ + 1;
   constexpr int FN = FX * FY * FZ;
+  // current tile: J_x and J_y on planes 1 .. JZ-1, J_z on planes 0 .. JZ-1
+  // (plane jz = node z0 + jz - 2); slab q starts at JOFF(q) and holds plane
+  // JFIRST(q) first
   constexpr int JX = TX + 3, JY = DIM == 3 ? TY + 3 : 1, JZ = TZ + 4;
-  constexpr int JN = JX * JY * JZ;
+  constexpr int JP = JX * JY;                     // entries per plane
+  constexpr int JN = JP * (3 * JZ - 2);           // all three slabs
   constexpr int RX = TX + 3, RY = DIM == 3 ? TY + 3 : 1, RZ = TZ + 2;
   constexpr int RN = RX * RY * RZ;
-  constexpr int SJ = 3 * JN + (RHO ? 2 * RN : 0);
+  constexpr int SJ = JN + (RHO ? 2 * RN : 0);
   using A = typename Fix<T>::t;
   __shared__ __align__(16) T sF[6 * FN];
   __shared__ __align__(16) A sJ[SJ];
   using V2 = typename Vec2<T>::t;
 
   const Geom& g = a.g;
-  int c = blockIdx.x;
-  if (c >= *a.ct.n) return;
-  int t = a.ct.tile[c];
-  int p0 = a.ct.start[c], p1 = a.ct.end[c];
-  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
-  int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  // work item: XCD-major so that the blocks one XCD runs are neighbouring columns
+  const int ncol = g.nTx * g.nTy;
+  const int nitem = ncol * a.nseg;
+  const int per_xcd = (nitem + 7) / 8;
+  const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (item >= nitem) return;
+  const int seg = item / ncol, colm = item - seg * ncol;
+  const int tx = colm % g.nTx, ty = colm / g.nTx;
+  const int tz0 = seg * a.seg_len, tz1 = min(g.nTz, tz0 + a.seg_len);
+  if (tz0 >= tz1) return;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int64_t ntot = *a.total;
+  const int mx = g.Nx - 1, my = g.Ny - 1;
+  const int64_t plane_stride = (int64_t)g.Ny * g.Nx;
 
-  // node records of the tile (3 pairs per node)
-  for (int idx = threadIdx.x; idx < 3 * FN; idx += blockDim.x) {
-    int node = idx / 3, part = idx - node * 3;
-    int lx = node % FX, r = node / FX;
-    int ly = r % FY, lz = r / FY;
-    int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
-    int gy = y0 + ly; if (gy >= g.Ny) gy -= g.Ny;
-    int gz = z0 + lz;
-    V2 v;
-    if (gz < g.Nz) {
-      size_t gi = ((size_t)gz * g.Ny + gy) * g.Nx + gx;
-      v = reinterpret_cast<const V2*>(a.F6 + 6 * gi)[part];
-    } else {
-      v.x = (T)0; v.y = (T)0;
-    }
-    reinterpret_cast<V2*>(sF + 6 * node)[part] = v;
-  }
   for (int idx = threadIdx.x; idx < SJ; idx += blockDim.x) sJ[idx] = (A)0;
+
+  // particle range of a tile of this column
+  auto range = [&](int tzz, int* q0, int* q1) {
+    const int tt = (tzz * g.nTy + ty) * g.nTx + tx;
+    const int64_t pb = a.tile_base[tt];
+    *q0 = (int)min(pb, ntot);
+    *q1 = (int)min(pb + a.tile_count[tt], ntot);
+  };
+  int p0, p1;
+  range(tz0, &p0, &p1);
+  // the next row's particles are loaded while the current row is processed
+  PLoad<T> nxt = load_particle<T, DIM>(P, p0 + (int)threadIdx.x, p0 + (int)threadIdx.x < p1);
+
+  for (int tz = tz0; tz < tz1; ++tz) {
+  const int z0 = tz * TZ;
+  int np0 = 0, np1 = 0;
+  if (tz + 1 < tz1) range(tz + 1, &np0, &np1);
+  // field node records: all planes for the first tile, planes 1 .. TZ after
+  // the carried plane 0 (3 pairs per node, one thread per (y, x, pair))
+  {
+    const int lz_first = tz == tz0 ? 0 : 1;
+    for (int it = threadIdx.x; it < 3 * FX * FY; it += blockDim.x) {
+      int part = it % 3, r = it / 3;
+      int lx = r % FX, ly = r / FX;
+      int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
+      int gy = y0 + ly; if (gy >= g.Ny) gy -= g.Ny;
+      const V2* src = reinterpret_cast<const V2*>(a.F6) + 3 * ((int64_t)gy * g.Nx + gx) + part;
+      for (int lz = lz_first; lz < FZ; ++lz) {
+        int gz = z0 + lz;
+        V2 v;
+        if (gz < g.Nz) {
+          v = src[3 * (int64_t)gz * plane_stride];
+        } else {
+          v.x = (T)0; v.y = (T)0;
+        }
+        reinterpret_cast<V2*>(sF + 6 * ((lz * FY + ly) * FX + lx))[part] = v;
+      }
+    }
+  }
   __syncthreads();
 
-  const int mx = g.Nx - 1, my = g.Ny - 1;
   for (int row = p0; row < p1; row += blockDim.x) {
     int p = row + (int)threadIdx.x;
     bool valid = p < p1;
+    const PLoad<T> cur = nxt;
+    {
+      // prefetch: the next row of this tile, else the first row of the next tile
+      int pn = row + (int)blockDim.x < p1 ? p + (int)blockDim.x : np0 + (int)threadIdx.x;
+      bool okn = row + (int)blockDim.x < p1 ? pn < p1 : pn < np1;
+      nxt = load_particle<T, DIM>(P, pn, okn);
+    }
     int lx = 0, ly = 0, lz = 0, kx = 0, ky = 0, kz = 0;
     T dx0 = (T)0, dy0 = (T)0, dz0 = (T)0, dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
     if (valid) {
-      int cell = P.cell[p];
+      int cell = cur.cell;
       int ix = cell & mx;
       int iy = (cell >> g.lnx) & my;
       int iz = cell >> (g.lnx + g.lny);
@@ -131,10 +211,10 @@ __global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T>
         valid = false;
         lx = ly = lz = 0;
       } else {
-        dx0 = P.ox[p];
-        dz0 = P.oz[p];
-        if (DIM == 3) dy0 = P.oy[p];
-        T ux = P.ux[p], uy = P.uy[p], uz = P.uz[p];
+        dx0 = cur.ox;
+        dz0 = cur.oz;
+        if (DIM == 3) dy0 = cur.oy;
+        T ux = cur.ux, uy = cur.uy, uz = cur.uz;
 
         // gather
         T wx[2] = {(T)1 - dx0, dx0};
@@ -257,54 +337,68 @@ __global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T>
       int jx0 = lx + min(kx, 0) + 1;
       int jy0 = DIM == 3 ? ly + min(ky, 0) + 1 : 0;
       int jz0 = lz + kz + 2;            // node base_z (kz <= 0)
-      A* sJx = sJ + (jz0 * JY + jy0) * JX + jx0;
-      A* sJy = sJx + JN;
-      A* sJz = sJx + 2 * JN - JY * JX;  // half-node plane base_z - 1
+      A* sJx = sJ + ((jz0 - 1) * JY + jy0) * JX + jx0;
+      A* sJy = sJx + (JZ - 1) * JP;
+      A* sJz = sJx + 2 * (JZ - 1) * JP;  // half-node plane base_z - 1
       T qr = (T)0.25 * a.crho * fs;
       T cx = a.cx * fs, cy = a.cy * fs, cz = a.cz * fs;
       if (DIM == 3) {
-        bool general = __any(kx != 0 || ky != 0);
-        T Cy[3], Dy[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) { Cy[i] = S0y[i] + (T)0.5 * DSy[i]; Dy[i] = (T)0.5 * S0y[i] + third * DSy[i]; }
+        // Transverse window: 3 x 3 nodes when a particle of the wave crosses a
+        // transverse cell boundary, taken one node at a time (weights
+        // recomputed, J_x and J_y from running prefixes of DS_x, DS_y) to keep
+        // few values live; else 2 x 2, unrolled (the third window node, the
+        // second J_x half-node and the second J_y half-node carry exactly zero).
+        const bool general = __any(kx != 0 || ky != 0);
         T s0e[4], s1e[4];
         s0e[0] = S0z[0]; s0e[1] = S0z[0] + S0z[1]; s0e[2] = S0z[1] + S0z[2]; s0e[3] = S0z[2];
         s1e[0] = S1z[0]; s1e[1] = S1z[0] + S1z[1]; s1e[2] = S1z[1] + S1z[2]; s1e[3] = S1z[2];
         T pz0 = cz * DSz[0], pz1 = cz * (DSz[0] + DSz[1]);
         if (general) {
-          T px[2] = {cx * DSx[0], cx * (DSx[0] + DSx[1])};
-          T py[2] = {cy * DSy[0], cy * (DSy[0] + DSy[1])};
+          const int ox0 = kx < 0 ? 1 : 0, ox1 = kx > 0 ? 1 : 0;
+          const int oy0 = ky < 0 ? 1 : 0, oy1 = ky > 0 ? 1 : 0;
+          T prex = (T)0;
+#pragma unroll 1
+          for (int aa = 0; aa < 3; ++aa) {
+            T s0x = valid ? (aa == ox0 ? (T)1 - dx0 : (T)0) + (aa == ox0 + 1 ? dx0 : (T)0) : (T)0;
+            T s1x = valid ? (aa == ox1 ? (T)1 - dx1 : (T)0) + (aa == ox1 + 1 ? dx1 : (T)0) : (T)0;
+            T dsx = s1x - s0x;
+            prex += dsx;
+            T px = cx * prex;
+            T Fx[3];
 #pragma unroll
-          for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-              T F = S0y[b] * Az[cc] + DSy[b] * Bz[cc];
-              add(&sJx[(cc * JY + b) * JX + 0], px[0] * F);
-              add(&sJx[(cc * JY + b) * JX + 1], px[1] * F);
-            }
-#pragma unroll
-          for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-              T F = S0x[aa] * Az[cc] + DSx[aa] * Bz[cc];
-              add(&sJy[(cc * JY + 0) * JX + aa], py[0] * F);
-              add(&sJy[(cc * JY + 1) * JX + aa], py[1] * F);
-            }
-#pragma unroll
-          for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) Fx[cc] = s0x * Az[cc] + dsx * Bz[cc];
+            T prey = (T)0;
+#pragma unroll 1
             for (int b = 0; b < 3; ++b) {
-              T Fz = S0x[aa] * Cy[b] + DSx[aa] * Dy[b];
-              T t0 = qr * (S0x[aa] * S0y[b]), t1 = qr * (S1x[aa] * S1y[b]);
+              T s0y = (b == oy0 ? (T)1 - dy0 : (T)0) + (b == oy0 + 1 ? dy0 : (T)0);
+              T s1y = (b == oy1 ? (T)1 - dy1 : (T)0) + (b == oy1 + 1 ? dy1 : (T)0);
+              T dsy = s1y - s0y;
+              prey += dsy;
+              if (aa < 2) {
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                  add(&sJx[(cc * JY + b) * JX + aa], px * (s0y * Az[cc] + dsy * Bz[cc]));
+              }
+              if (b < 2) {
+                T py = cy * prey;
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) add(&sJy[(cc * JY + b) * JX + aa], py * Fx[cc]);
+              }
+              T Fz = s0x * (s0y + (T)0.5 * dsy) + dsx * ((T)0.5 * s0y + third * dsy);
+              T t0 = qr * (s0x * s0y), t1 = qr * (s1x * s1y);
               A* pz = &sJz[b * JX + aa];
               add(pz + 0 * JY * JX, t0 * s0e[0] + t1 * s1e[0]);
               add(pz + 1 * JY * JX, t0 * s0e[1] + t1 * s1e[1] + pz0 * Fz);
               add(pz + 2 * JY * JX, t0 * s0e[2] + t1 * s1e[2] + pz1 * Fz);
               add(pz + 3 * JY * JX, t0 * s0e[3] + t1 * s1e[3]);
             }
+          }
         } else {
           // no transverse crossing in this wave: x and y windows start at the
           // cell, the third window node and the second half-node carry zero
+          T Cy[2], Dy[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) { Cy[i] = S0y[i] + (T)0.5 * DSy[i]; Dy[i] = (T)0.5 * S0y[i] + third * DSy[i]; }
           T px0 = cx * DSx[0], py0 = cy * DSy[0];
 #pragma unroll
           for (int b = 0; b < 2; ++b)
@@ -361,7 +455,7 @@ __global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T>
       }
       if (RHO && valid) {
         // charge before and after the move; rho tile origin (x0-1, y0-1, node z0-1)
-        A* sR0 = sJ + 3 * JN;
+        A* sR0 = sJ + JN;
         A* sR1 = sR0 + RN;
         T cr = a.crho * fs;
         constexpr int oy = DIM == 3 ? 1 : 0;
@@ -383,34 +477,71 @@ __global__ __launch_bounds__(512) void k_push_deposit(PushArgs<T> a, PartPtrs<T>
   }
   __syncthreads();
 
-  // flush: global x = x0 - 1 + jx, y = y0 - 1 + jy, plane = z0 + jz
-  for (int idx = threadIdx.x; idx < 3 * JN; idx += blockDim.x) {
-    A iv = sJ[idx];
-    if (iv == (A)0) continue;
-    T v = (T)fix_value(iv) * a.finv;
-    int q = idx / JN, l = idx - q * JN;
-    int jx = l % JX, rr = l / JX;
-    int jy = rr % JY, jz = rr / JY;
-    int plane = z0 + jz;
-    if (plane >= g.NPJ) continue;
-    int gx = (x0 - 1 + jx) & mx;
-    int gy = DIM == 3 ? (y0 - 1 + jy) & my : 0;
-    atomicAdd(&a.J[q][((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
-  }
-  if (RHO) {
-    for (int idx = threadIdx.x; idx < 2 * RN; idx += blockDim.x) {
-      A iv = sJ[3 * JN + idx];
-      if (iv == (A)0) continue;
-      T v = (T)fix_value(iv) * a.finv;
-      int q = idx / RN, l = idx - q * RN;
-      int rx = l % RX, rr = l / RX;
-      int ry = rr % RY, rz = rr / RY;
-      int plane = z0 - 1 + rz + 2;
-      if (plane < 0 || plane >= g.NPJ) continue;
-      int gx = (x0 - 1 + rx) & mx;
-      int gy = DIM == 3 ? (y0 - 1 + ry) & my : 0;
-      T* dst = q == 0 ? a.rho0 : a.rho1;
-      atomicAdd(&dst[((size_t)plane * g.Ny + gy) * g.Nx + gx], v);
+  // flush the planes no later tile of the segment touches (all of them after
+  // the last tile), carry the rest down by TZ planes; one thread per column.
+  // Global x = x0 - 1 + jx, y = y0 - 1 + jy, plane = z0 + jz.
+  {
+    const bool last = tz + 1 == tz1;
+    // a slab's planes below TZ + first are final: the next tile's deposits of
+    // that component start at plane TZ + first
+    for (int col = threadIdx.x; col < 3 * JP; col += blockDim.x) {
+      int q = col / JP, l = col - q * JP;
+      int jx = l % JX, jy = l / JX;
+      int gx = (x0 - 1 + jx) & mx;
+      int gy = DIM == 3 ? (y0 - 1 + jy) & my : 0;
+      T* dst = a.J[q] + (int64_t)gy * g.Nx + gx;
+      const int first = q < 2 ? 1 : 0;
+      A* sc = sJ + q * (JZ - 1) * JP + l - first * JP;   // sc[jz * JP]: plane jz
+      const int nflush = last ? JZ : TZ + first;
+      for (int jz = first; jz < nflush; ++jz) {
+        A iv = sc[jz * JP];
+        int plane = z0 + jz;
+        if (iv != (A)0 && plane < g.NPJ) atomicAdd(dst + plane * plane_stride, fix_value<T>(iv) * a.finv);
+      }
+      if (!last) {
+        for (int jz = TZ + first; jz < JZ; ++jz) {
+          sc[(jz - TZ) * JP] = sc[jz * JP];
+          sc[jz * JP] = (A)0;
+        }
+        for (int jz = JZ - TZ; jz < TZ + first; ++jz) sc[jz * JP] = (A)0;
+      }
+    }
+    if (RHO) {
+      // rho tiles: origin node z0 - 1 (plane z0 + 1), RZ planes
+      const int rflush = last ? RZ : TZ;
+      for (int col = threadIdx.x; col < 2 * RY * RX; col += blockDim.x) {
+        int q = col / (RY * RX), l = col - q * (RY * RX);
+        int rx = l % RX, ry = l / RX;
+        int gx = (x0 - 1 + rx) & mx;
+        int gy = DIM == 3 ? (y0 - 1 + ry) & my : 0;
+        T* dst = (q == 0 ? a.rho0 : a.rho1) + (int64_t)gy * g.Nx + gx;
+        A* sc = sJ + JN + q * RN + ry * RX + rx;
+        for (int rz = 0; rz < rflush; ++rz) {
+          A iv = sc[rz * RY * RX];
+          int plane = z0 + 1 + rz;
+          if (iv != (A)0 && plane < g.NPJ) atomicAdd(dst + plane * plane_stride, fix_value<T>(iv) * a.finv);
+        }
+        if (!last) {
+          for (int rz = TZ; rz < RZ; ++rz) {
+            sc[(rz - TZ) * RY * RX] = sc[rz * RY * RX];
+            sc[rz * RY * RX] = (A)0;
+          }
+          for (int rz = RZ - TZ; rz < TZ; ++rz) sc[rz * RY * RX] = (A)0;
+        }
+      }
+    }
+    // the last field plane becomes the first one of the next tile
+    if (!last) {
+      for (int it = threadIdx.x; it < 3 * FX * FY; it += blockDim.x) {
+        V2* f = reinterpret_cast<V2*>(sF);
+        f[it] = f[3 * TZ * FX * FY + it];
+      }
     }
   }
+  __syncthreads();
+  // an empty tile consumed no prefetch: load the next tile's first row now
+  if (p0 >= p1) nxt = load_particle<T, DIM>(P, np0 + (int)threadIdx.x, np0 + (int)threadIdx.x < np1);
+  p0 = np0;
+  p1 = np1;
+  }  // zeta tiles of the segment
 }

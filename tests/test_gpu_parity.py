@@ -42,7 +42,8 @@ def test_initial_state(cfg):
     assert max(err.values()) < 1e-12, err
 
 
-@pytest.mark.parametrize("cfg", [workloads.lwfa2d_fp64(), _small3d()], ids=["lwfa2d", "small3d"])
+@pytest.mark.parametrize("cfg", [workloads.lwfa2d_fp64(), _small3d(), _small3d(tile=(8, 8, 4))],
+                         ids=["lwfa2d", "small3d", "small3d_t884"])
 def test_push_bit_exact_from_shared_state(cfg):
     o = Simulation(cfg).run(3)
     g = Sim(cfg, track_ids=True)
@@ -82,8 +83,9 @@ def test_lwfa2d_fp64_100_steps():
     assert max(err.values()) < 1e-10, err
 
 
-def test_small3d_fp64_steps():
-    cfg = _small3d()
+@pytest.mark.parametrize("tile", [(8, 8, 8), (8, 8, 4)], ids=["t888", "t884"])
+def test_small3d_fp64_steps(tile):
+    cfg = _small3d(tile=tile)
     o = Simulation(cfg)
     g = Sim(cfg, track_ids=True, deposit_rho=True)
     o.run(3)
@@ -108,9 +110,10 @@ def test_lwfa2d_fp32_50_steps():
     assert max(err.values()) < 2e-4, err
 
 
-def test_small3d_fp32_steps():
-    o = Simulation(_small3d()).run(4)
-    g = Sim(_small3d("fp32"))
+@pytest.mark.parametrize("tile", [(8, 8, 8), (8, 8, 4)], ids=["t888", "t884"])
+def test_small3d_fp32_steps(tile):
+    o = Simulation(_small3d(tile=tile)).run(4)
+    g = Sim(_small3d("fp32", tile=tile))
     g.step(4)
     err = rel_errors(oracle_fields(o), g.fields())
     assert max(err.values()) < 2e-4, err
