@@ -70,11 +70,13 @@ def _xi(p, key, m, j, i, sy, sx, axis):
     return rng.uniform(key, c)
 
 
-def _lattice(p, m_values):
-    """All lattice particles of the given sub-rows, in (m, j, i, sy, sx) order."""
-    m, j, i, sy, sx = np.meshgrid(np.asarray(m_values, np.int64), np.arange(p.Ny),
-                                  np.arange(p.Nx), np.arange(p.ppc[1]),
-                                  np.arange(p.ppc[0]), indexing="ij")
+def _lattice(p, m_values, j_values=None, i_values=None):
+    """Lattice particles of the given sub-rows (and transverse cells, default
+    all), in (m, j, i, sy, sx) order."""
+    jv = np.arange(p.Ny) if j_values is None else np.asarray(j_values, np.int64)
+    iv = np.arange(p.Nx) if i_values is None else np.asarray(i_values, np.int64)
+    m, j, i, sy, sx = np.meshgrid(np.asarray(m_values, np.int64), jv, iv,
+                                  np.arange(p.ppc[1]), np.arange(p.ppc[0]), indexing="ij")
     m, j, i, sy, sx = (a.ravel() for a in (m, j, i, sy, sx))
     key = rng.stream_key(p.seed, 0)
     xi_x = _xi(p, key, m, j, i, sy, sx, 0)
@@ -109,6 +111,30 @@ def load_full_cells(p):
     iz = m // p.ppc[2]
     dz = np.minimum(((m % p.ppc[2]) + xi_z) / p.ppc[2], ONE_MINUS)
     return _make(p, i, j, iz, dx, dy, dz)
+
+
+def load_box(p, i_values, j_values, iz_values):
+    """The particles that load_full_cells puts in the given cells (i, j
+    periodic indices, iz < N_zeta + ext - 1), with pid = their index in the
+    full load, in load order."""
+    if p.n_e <= 0.0:
+        return Particles.empty()
+    iv = np.asarray(i_values, np.int64) % p.Nx
+    jv = np.asarray(j_values, np.int64) % p.Ny
+    izv = np.asarray(iz_values, np.int64)
+    if np.any(izv < 0) or np.any(izv >= p.Nzp - 1):
+        raise ValueError("iz outside the fully loaded cells")
+    m_vals = (izv[:, None] * p.ppc[2] + np.arange(p.ppc[2])[None, :]).ravel()
+    m_vals = np.unique(m_vals)
+    m, j, i, dx, dy, xi_z = _lattice(p, m_vals, np.sort(np.unique(jv)), np.sort(np.unique(iv)))
+    iz = m // p.ppc[2]
+    dz = np.minimum(((m % p.ppc[2]) + xi_z) / p.ppc[2], ONE_MINUS)
+    P = _make(p, i, j, iz, dx, dy, dz)
+    n = len(i)
+    ppcy, ppcx = p.ppc[1], p.ppc[0]
+    sub = np.arange(n) % (ppcy * ppcx)
+    P.pid = ((m * p.Ny + j) * p.Nx + i) * (ppcy * ppcx) + sub
+    return P
 
 
 def inject_batch(p, b):

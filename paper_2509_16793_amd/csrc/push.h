@@ -220,7 +220,9 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
         T wx[2] = {(T)1 - dx0, dx0};
         T wz[2] = {(T)1 - dz0, dz0};
         T wy[2] = {(T)1 - dy0, dy0};
-        T f[6] = {(T)0, (T)0, (T)0, (T)0, (T)0, (T)0};
+        // sums start from the first node's products (0 + x differs from x
+        // only in the sign of a zero)
+        T f[6];
         int nb = (lz * FY + ly) * FX + lx;
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
@@ -231,12 +233,10 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
               T w = DIM == 3 ? (wx[aa] * wy[b]) * wz[cc] : wx[aa] * wz[cc];
               const V2* rec = reinterpret_cast<const V2*>(sF + 6 * (nb + (cc * FY + b) * FX + aa));
               V2 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-              f[0] = f[0] + w * r0.x;
-              f[1] = f[1] + w * r0.y;
-              f[2] = f[2] + w * r1.x;
-              f[3] = f[3] + w * r1.y;
-              f[4] = f[4] + w * r2.x;
-              f[5] = f[5] + w * r2.y;
+              const T v[6] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y};
+              const bool first = cc == 0 && b == 0 && aa == 0;
+#pragma unroll
+              for (int k = 0; k < 6; ++k) f[k] = first ? w * v[k] : f[k] + w * v[k];
             }
           }
         }

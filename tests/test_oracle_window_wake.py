@@ -108,3 +108,21 @@ def test_linear_wake_amplitude_and_wavelength():
     zc = zeta[win][:-1][np.sign(e[:-1]) != np.sign(e[1:])]
     assert len(zc) >= 2
     assert np.all(np.abs(np.diff(zc) - lam / 2) < 0.01 * lam / 2)
+
+
+def test_load_box_is_the_subset_of_the_full_load():
+    """The sampled-cell loader used at full size reproduces the full load's
+    particles (positions and load-order ids) cell by cell."""
+    import workloads
+    from oracle import params, plasma
+    cfg = workloads.small3d(precision="fp64", ppc=(1, 2, 2))
+    p = params.from_config(cfg)
+    full = plasma.load_full_cells(p)
+    full.pid = np.arange(len(full))
+    xs, ys, zs = [30, 31, 0, 1], [5, 6], [0, 13, 14, 66]
+    B = plasma.load_box(p, xs, ys, zs)
+    sel = np.isin(full.ix, xs) & np.isin(full.iy, ys) & np.isin(full.iz, zs)
+    F = full.take(np.nonzero(sel)[0])
+    assert len(B) == len(F) > 0
+    for k in plasma.Particles.FIELDS:
+        assert np.array_equal(getattr(B, k), getattr(F, k)), k

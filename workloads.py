@@ -41,9 +41,10 @@ def lwfa2d_fp64():
 
 def lwfa3d_fp32(ppc=(1, 1, 2), steps=1000):
     """3-D LWFA, 256 x 256 x 512, dx = dy = 0.4, dzeta = 0.05, n_e = 0.001, 2 ppc
-    (67,108,864 electrons), a0 = 2, waist 8, FWHM 8; FP32 cell + offset."""
+    (67,108,864 electrons), a0 = 2, waist 8, FWHM 8; FP32 cell + offset,
+    8 x 8 x 4 particle tiles."""
     return _base(dims=3, n=[256, 256, 512], d=[0.4, 0.4, 0.05], precision="fp32",
-                 tile=[8, 8, 8], n_e=0.001, ppc=list(ppc), a0=2.0, waist=8.0,
+                 tile=[8, 8, 4], n_e=0.001, ppc=list(ppc), a0=2.0, waist=8.0,
                  fwhm=8.0, zeta_c=None, steps=steps)
 
 
