@@ -10,24 +10,58 @@
 #include "common.h"
 
 // ---------------------------------------------------------------------------
-// Radix-2 Stockham FFT of nseq sequences of length N held in LDS (x -> result
-// pointer returned; y is the ping-pong buffer).  tw[t] = exp(-2 pi i t / N),
-// t < N/2; inverse uses the conjugate twiddles (no scaling here).
+// Stockham FFT of nseq sequences of length N (a power of two) held in LDS:
+// radix-4 passes, then one radix-2 pass when log2 N is odd.  x holds the
+// input, y is the ping-pong buffer; the pointer to the result is returned.
+// tl (LDS, N entries) receives the full circle of twiddles exp(-2 pi i t / N)
+// from tw (global, t < N/2); the inverse uses their conjugates (no scaling).
+// Every thread of the block must call it (it synchronises).
 template <typename T>
-GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, int N, int nseq, const cplx<T>* tw, bool inverse) {
-  int half = N >> 1;
-  int total = nseq * half;
-  for (int Ns = 1; Ns < N; Ns <<= 1) {
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, cplx<T>* tl, int N, int nseq, const cplx<T>* tw,
+                        bool inverse) {
+  const int half = N >> 1;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    cplx<T> w = tw[t < half ? t : t - half];
+    if (t >= half) w = mk(-w.x, -w.y);
+    if (inverse) w.y = -w.y;
+    tl[t] = w;
+  }
+  __syncthreads();
+  int Ns = 1;
+  const int q4 = N >> 2;
+  for (; Ns * 4 <= N; Ns <<= 2) {
+    const int step = N / (4 * Ns);
+    for (int idx = threadIdx.x; idx < nseq * q4; idx += blockDim.x) {
+      int sq = idx / q4, j = idx - sq * q4;
+      int k = j & (Ns - 1);
+      const cplx<T>* xs = x + sq * N;
+      int ts = k * step;
+      cplx<T> a0 = xs[j];
+      cplx<T> a1 = tl[ts] * xs[j + q4];
+      cplx<T> a2 = tl[2 * ts] * xs[j + 2 * q4];
+      cplx<T> a3 = tl[3 * ts] * xs[j + 3 * q4];
+      cplx<T> b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3, b3 = a1 - a3;
+      cplx<T> ib3 = mul_i(b3);
+      cplx<T>* ys = y + sq * N;
+      int d = ((j - k) << 2) + k;
+      ys[d] = b0 + b2;
+      ys[d + Ns] = inverse ? b1 + ib3 : b1 - ib3;
+      ys[d + 2 * Ns] = b0 - b2;
+      ys[d + 3 * Ns] = inverse ? b1 - ib3 : b1 + ib3;
+    }
+    __syncthreads();
+    cplx<T>* t = x; x = y; y = t;
+  }
+  if (Ns < N) {
+    // radix-2 pass, Ns = N / 2
+    for (int idx = threadIdx.x; idx < nseq * half; idx += blockDim.x) {
       int sq = idx / half, j = idx - sq * half;
       int k = j & (Ns - 1);
-      cplx<T> w = tw[k * (half / Ns)];
-      if (inverse) w.y = -w.y;
-      cplx<T>* xs = x + sq * N;
+      const cplx<T>* xs = x + sq * N;
       cplx<T> a = xs[j];
-      cplx<T> b = w * xs[j + half];
-      int d = ((j - k) << 1) + k;
+      cplx<T> b = tl[k * (half / Ns)] * xs[j + half];
       cplx<T>* ys = y + sq * N;
+      int d = ((j - k) << 1) + k;
       ys[d] = a + b;
       ys[d + Ns] = a - b;
     }
@@ -45,6 +79,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const T* in, cplx<T>* out, in
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* y = x + nseq * Nx;
+  cplx<T>* tl = y + nseq * Nx;
   int64_t pair0 = (int64_t)blockIdx.x * nseq;
   for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
     int sq = idx / Nx, n = idx - sq * Nx;
@@ -54,7 +89,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const T* in, cplx<T>* out, in
     x[idx] = mk(a, b);
   }
   __syncthreads();
-  cplx<T>* Z = lds_fft(x, y, Nx, nseq, tw, false);
+  cplx<T>* Z = lds_fft(x, y, tl, Nx, nseq, tw, false);
   int Nxh = Nx >> 1;
   for (int idx = threadIdx.x; idx < nseq * Nxh; idx += blockDim.x) {
     int sq = idx / Nxh, k = idx - sq * Nxh;
@@ -76,6 +111,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(const cplx<T>* in, T* out, in
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* y = x + nseq * Nx;
+  cplx<T>* tl = y + nseq * Nx;
   int64_t pair0 = (int64_t)blockIdx.x * nseq;
   int Nxh = Nx >> 1;
   for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
@@ -95,7 +131,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(const cplx<T>* in, T* out, in
     x[idx] = z;
   }
   __syncthreads();
-  cplx<T>* Z = lds_fft(x, y, Nx, nseq, tw, true);
+  cplx<T>* Z = lds_fft(x, y, tl, Nx, nseq, tw, true);
   T sc = (T)1 / (T)Nx;
   for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
     int sq = idx / Nx, n = idx - sq * Nx;
@@ -116,6 +152,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r6(const cplx<T>* i0, const cpl
   const cplx<T>* in[6] = {i0, i1, i2, i3, i4, i5};
   cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* y = x + 6 * nseq * Nx;
+  cplx<T>* tl = y + 6 * nseq * Nx;
   int64_t pair0 = (int64_t)blockIdx.x * nseq;
   int Nxh = Nx >> 1;
   for (int idx = threadIdx.x; idx < 6 * nseq * Nx; idx += blockDim.x) {
@@ -136,7 +173,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r6(const cplx<T>* i0, const cpl
     x[idx] = z;
   }
   __syncthreads();
-  cplx<T>* Z = lds_fft(x, y, Nx, 6 * nseq, tw, true);
+  cplx<T>* Z = lds_fft(x, y, tl, Nx, 6 * nseq, tw, true);
   T sc = (T)1 / (T)Nx;
   for (int idx = threadIdx.x; idx < 6 * nseq * Nx; idx += blockDim.x) {
     int q = idx % 6, r = idx / 6;
@@ -168,6 +205,7 @@ __global__ __launch_bounds__(256) void k_fft_y(cplx<T>* data, int Ny, int Nxh, i
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* y = x + ncol * Ny;
+  cplx<T>* tl = y + ncol * Ny;
   int cpp = Nxh / ncol;                       // column groups per plane
   int64_t plane = blockIdx.x / cpp;
   int c0 = (blockIdx.x % cpp) * ncol;
@@ -177,7 +215,7 @@ __global__ __launch_bounds__(256) void k_fft_y(cplx<T>* data, int Ny, int Nxh, i
     x[c * Ny + row] = base[(int64_t)row * Nxh + c];
   }
   __syncthreads();
-  cplx<T>* Z = lds_fft(x, y, Ny, ncol, tw, inverse != 0);
+  cplx<T>* Z = lds_fft(x, y, tl, Ny, ncol, tw, inverse != 0);
   T sc = inverse ? (T)1 / (T)Ny : (T)1;
   for (int idx = threadIdx.x; idx < ncol * Ny; idx += blockDim.x) {
     int row = idx / ncol, c = idx - row * ncol;
@@ -216,27 +254,41 @@ struct MarchArgs {
   T Delta;
 };
 
+// Raw current planes of one component around the plane being filtered:
+// r[k] = plane c - P + k for the centre plane c, plus the next lower plane.
+template <typename T, int P>
+struct PlaneWin {
+  cplx<T> r[2 * P + 1];
+  cplx<T> nxt;
+};
+
 template <typename T>
-GP_DEV cplx<T> filt_plane(const cplx<T>* A, int p, int NPF, int P, int64_t stride, int64_t m) {
-  // binomial filter along the plane index, P passes
+GP_DEV cplx<T> load_plane(const cplx<T>* A, int q, int NPF, int64_t stride, int64_t m) {
+  return (q >= 0 && q < NPF) ? A[(int64_t)q * stride + m] : mk((T)0, (T)0);
+}
+
+// binomial filter along the plane index (P passes), in the order of the
+// plane offsets -P .. P; out-of-range planes hold zero
+template <typename T, int P>
+GP_DEV cplx<T> win_filter(const PlaneWin<T, P>& w) {
+  if (P == 0) return w.r[0];
   const T w1[3] = {(T)0.25, (T)0.5, (T)0.25};
   const T w2[5] = {(T)0.0625, (T)0.25, (T)0.375, (T)0.25, (T)0.0625};
   cplx<T> r = mk((T)0, (T)0);
-  if (P == 0) {
-    if (p >= 0 && p < NPF) r = A[(int64_t)p * stride + m];
-    return r;
-  }
-  for (int d = -P; d <= P; ++d) {
-    int q = p + d;
-    if (q < 0 || q >= NPF) continue;
-    T w = P == 1 ? w1[d + 1] : w2[d + 2];
-    cplx<T> v = A[(int64_t)q * stride + m];
-    r = r + w * v;
-  }
+#pragma unroll
+  for (int k = 0; k < 2 * P + 1; ++k) r = r + (P == 1 ? w1[k] : w2[k]) * w.r[k];
   return r;
 }
 
-template <typename T>
+// move the window centre one plane down (the prefetched plane enters)
+template <typename T, int P>
+GP_DEV void win_slide(PlaneWin<T, P>& w) {
+#pragma unroll
+  for (int k = 2 * P; k > 0; --k) w.r[k] = w.r[k - 1];
+  w.r[0] = w.nxt;
+}
+
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_march(MarchArgs<T> a) {
   const Geom& g = a.g;
   int64_t M = (int64_t)g.Ny * g.Nxh;
@@ -268,42 +320,88 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs<T> a) {
   // transverse filter and half-cell shifts
   double fx = cos(0.5 * kxd * g.hx), fxy = fx * fx;
   if (g.dims == 3) { double fy = cos(0.5 * kyd * g.hy); fxy *= fy * fy; }
-  double phi = g.P == 0 ? 1.0 : (g.P == 1 ? fxy : fxy * fxy);
+  double phi = P == 0 ? 1.0 : (P == 1 ? fxy : fxy * fxy);
   cplx<T> sx = mk((T)(0.5 * phi * cos(0.5 * kxd * g.hx)), (T)(-0.5 * phi * sin(0.5 * kxd * g.hx)));
   cplx<T> sy = g.dims == 3 ? mk((T)(0.5 * phi * cos(0.5 * kyd * g.hy)), (T)(-0.5 * phi * sin(0.5 * kyd * g.hy)))
                            : mk((T)(0.5 * phi), (T)0);
   T phz = (T)phi;
-  bool hasJ = a.J[0] != nullptr;
+  const bool hasJ = a.J[0] != nullptr;
+  const int NPF = g.NPF;
   // filtered planes of Jx, Jy (nodal) carried between iterations
   cplx<T> fxp = mk((T)0, (T)0), fyp = fxp;   // filtered plane n + 2 (node n + 1 of half-node n + 1/2)
   cplx<T> jxp = fxp, jyp = fxp, jzp = fxp;   // solver currents on half-node n + 1/2
+  PlaneWin<T, P> W[3];
   if (hasJ) {
+    // windows centred on plane Nz + 2, then slid to Nz + 1
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int k = 0; k < 2 * P + 1; ++k) W[c].r[k] = load_plane(a.J[c], g.Nz + 2 - P + k, NPF, stride, m);
+    }
+    cplx<T> f2 = win_filter(W[0]), e2 = win_filter(W[1]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      W[c].nxt = load_plane(a.J[c], g.Nz + 1 - P, NPF, stride, m);
+      win_slide(W[c]);
+    }
     // half-node q = Nz: planes Nz + 1, Nz + 2
-    cplx<T> f1 = filt_plane(a.J[0], g.Nz + 1, g.NPF, g.P, stride, m);
-    cplx<T> f2 = filt_plane(a.J[0], g.Nz + 2, g.NPF, g.P, stride, m);
+    cplx<T> f1 = win_filter(W[0]), e1 = win_filter(W[1]);
     jxp = sx * (f1 + f2);
     fxp = f1;
-    cplx<T> e1 = filt_plane(a.J[1], g.Nz + 1, g.NPF, g.P, stride, m);
-    cplx<T> e2 = filt_plane(a.J[1], g.Nz + 2, g.NPF, g.P, stride, m);
     jyp = sy * (e1 + e2);
     fyp = e1;
-    jzp = phz * filt_plane(a.J[2], g.Nz + 1, g.NPF, g.P, stride, m);
+    jzp = phz * win_filter(W[2]);
+  }
+  // Node n uses its old state and the raw current plane n + 1 - P, both
+  // loaded PD nodes ahead into ring slot (Nz - 1 - n) mod PD (the loop is
+  // unrolled by PD so that every slot index is static).
+  constexpr int PD = 4;
+  cplx<T> S[PD][4], Pl[PD][3];
+#pragma unroll
+  for (int i = 0; i < PD; ++i) {
+    int n = g.Nz - 1 - i;
+    if (n >= 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S[i][q] = a.st[q][(int64_t)n * stride + m];
+      if (hasJ) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pl[i][c] = load_plane(a.J[c], n + 1 - P, NPF, stride, m);
+      }
+    }
   }
   cplx<T> Rx1 = mk((T)0, (T)0), Ry1 = Rx1, Lx1 = Rx1, Ly1 = Rx1, Ez1 = Rx1, Bz1 = Rx1;
-  for (int n = g.Nz - 1; n >= 0; --n) {
+  for (int n0 = g.Nz - 1; n0 >= 0; n0 -= PD) {
+#pragma unroll
+  for (int i = 0; i < PD; ++i) {
+    const int n = n0 - i;
+    if (n < 0) break;
+    int64_t o = (int64_t)n * stride + m;
+    const cplx<T> Rx0 = S[i][0], Ry0 = S[i][1], Ez0 = S[i][2], Bz0 = S[i][3];
     cplx<T> jxm = mk((T)0, (T)0), jym = jxm, jzm = jxm;
     if (hasJ) {
       // half-node n - 1/2: planes n + 1 (new) and n + 2 (carried)
-      cplx<T> f1 = filt_plane(a.J[0], n + 1, g.NPF, g.P, stride, m);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        W[c].nxt = Pl[i][c];
+        win_slide(W[c]);
+      }
+      cplx<T> f1 = win_filter(W[0]);
       jxm = sx * (f1 + fxp);
       fxp = f1;
-      cplx<T> e1 = filt_plane(a.J[1], n + 1, g.NPF, g.P, stride, m);
+      cplx<T> e1 = win_filter(W[1]);
       jym = sy * (e1 + fyp);
       fyp = e1;
-      jzm = phz * filt_plane(a.J[2], n + 1, g.NPF, g.P, stride, m);
+      jzm = phz * win_filter(W[2]);
     }
-    int64_t o = (int64_t)n * stride + m;
-    cplx<T> Rx0 = a.st[0][o], Ry0 = a.st[1][o], Ez0 = a.st[2][o], Bz0 = a.st[3][o];
+    // refill the slot with node n - PD
+    if (n - PD >= 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S[i][q] = a.st[q][o - PD * stride];
+      if (hasJ) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pl[i][c] = load_plane(a.J[c], n - PD + 1 - P, NPF, stride, m);
+      }
+    }
     cplx<T> Jx = (T)2 * (jxm + jxp);
     cplx<T> Jy = (T)2 * (jym + jyp);
     cplx<T> Wx = (Rx0 + Rx1) - (T)2 * Lx1;
@@ -340,6 +438,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs<T> a) {
     if (a.L[0]) { a.L[0][o] = Lx; a.L[1][o] = Ly; }
     Rx1 = Rx; Ry1 = Ry; Lx1 = Lx; Ly1 = Ly; Ez1 = Ez; Bz1 = Bz;
     jxp = jxm; jyp = jym; jzp = jzm;
+  }
   }
 }
 

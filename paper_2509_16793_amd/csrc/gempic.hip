@@ -155,11 +155,11 @@ struct Impl {
     int64_t rows = planes * G.Ny;
     int64_t pairs = (rows + 1) / 2;
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / G.Nx));
-    size_t sh = 2 * (size_t)nseq * G.Nx * sizeof(C);
+    size_t sh = (2 * (size_t)nseq + 1) * G.Nx * sizeof(C);
     k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
     if (G.Ny > 1) {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
-      size_t sh2 = 2 * (size_t)ncol * G.Ny * sizeof(C);
+      size_t sh2 = (2 * (size_t)ncol + 1) * G.Ny * sizeof(C);
       k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 256, sh2, g->s>>>(out, G.Ny, G.Nxh, ncol,
                                                                        (const C*)g->twy, 0);
     }
@@ -169,7 +169,7 @@ struct Impl {
     const Geom& G = g->g;
     if (G.Ny > 1) {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
-      size_t sh2 = 2 * (size_t)ncol * G.Ny * sizeof(C);
+      size_t sh2 = (2 * (size_t)ncol + 1) * G.Ny * sizeof(C);
       for (int q = 0; q < 6; ++q)
         k_fft_y<T><<<(unsigned)((int64_t)G.Nz * (G.Nxh / ncol)), 256, sh2, g->s>>>(
             (C*)g->outs[q], G.Ny, G.Nxh, ncol, (const C*)g->twy, 1);
@@ -177,7 +177,7 @@ struct Impl {
     int64_t rows = (int64_t)G.Nz * G.Ny;
     int64_t pairs = (rows + 1) / 2;
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / (6 * G.Nx)));
-    size_t sh = 2 * (size_t)6 * nseq * G.Nx * sizeof(C);
+    size_t sh = (2 * (size_t)6 * nseq + 1) * G.Nx * sizeof(C);
     k_fft_x_c2r6<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(
         (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
         (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, G.Nx, nseq, (const C*)g->twx);
@@ -202,7 +202,9 @@ struct Impl {
     a.L[1] = (C*)g->Lsp[1];
     a.Delta = Delta;
     int64_t M = (int64_t)G.Ny * G.Nxh;
-    k_march<T><<<nblk(M, 64), 64, 0, g->s>>>(a);
+    if (a.g.P == 0) k_march<T, 0><<<nblk(M, 64), 64, 0, g->s>>>(a);
+    else if (a.g.P == 1) k_march<T, 1><<<nblk(M, 64), 64, 0, g->s>>>(a);
+    else k_march<T, 2><<<nblk(M, 64), 64, 0, g->s>>>(a);
     fft_inv6(g);
   }
 
