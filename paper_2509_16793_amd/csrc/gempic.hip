@@ -65,6 +65,7 @@ struct gempic {
   int ctc;
   int32_t *code, *counts, *offs, *inj_count, *inj_off, *gflag, *grank;
   int64_t *tile_count, *tile_base, *total, *next_id, *inj_total, *pushed;
+  int64_t* scan_part;   // per-block partial sums of the tile scan
   int* err_dev;
   // grids
   void* F6;          // gather fields: node records [Nz][Ny][Nx][6]
@@ -112,6 +113,15 @@ static int fail(gempic* g, int code, const std::string& msg) {
   } while (0)
 
 static bool pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+// tile_base / total and the chunk table heads of t from g->tile_count
+static void scan_tiles(gempic* g, ChunkTab& t) {
+  const Geom& G = g->g;
+  int nb = (G.NT + SCAN_PER - 1) / SCAN_PER;
+  k_scan_tiles_sum<<<nb, 1024, 0, g->s>>>(G.NT, g->tile_count, g->scan_part);
+  k_scan_tiles_top<<<1, 1024, 0, g->s>>>(nb, g->scan_part, g->total, t.n, g->capacity, g->err_dev);
+  k_scan_tiles_apply<<<nb, 1024, 0, g->s>>>(G.NT, g->tile_count, g->scan_part, g->tile_base, t.first, t.count);
+}
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
@@ -261,8 +271,7 @@ struct Impl {
     oa.inj_off = g->inj_off;
     oa.tile_count = g->tile_count;
     k_tile_offsets<<<nblk(G.NT, 128), 128, 0, g->s>>>(oa);
-    k_scan_tiles<<<1, 1024, 0, g->s>>>(G.NT, g->tile_count, g->tile_base, g->total, newt.first,
-                                        newt.count, newt.n, g->capacity, g->err_dev);
+    scan_tiles(g, newt);
     k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, newt,
                                                        g->max_chunks);
     ScatArgs<T> sc;
@@ -470,8 +479,7 @@ struct Impl {
       k_load_full<T><<<G.NT, 256, 0, g->s>>>(la, parts(g, g->cur));
     }
     ChunkTab& t0 = g->ct[g->ctc];
-    k_scan_tiles<<<1, 1024, 0, g->s>>>(G.NT, g->tile_count, g->tile_base, g->total, t0.first, t0.count,
-                                        t0.n, g->capacity, g->err_dev);
+    scan_tiles(g, t0);
     k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, t0,
                                                        g->max_chunks);
     if (g->ids[0]) HIPCHK(g, hipMemcpyAsync(g->next_id, &tot, 8, hipMemcpyHostToDevice, g->s));
@@ -611,6 +619,7 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->NT = G->nTx * G->nTy * G->nTz;
   G->Nxh = G->Nx / 2;
   if ((int64_t)G->Nzp * G->Ny * G->Nx >= (1ll << 31)) { *why = "grid too large for int32 cells"; return GEMPIC_EINVAL; }
+  if ((int64_t)G->NT > (int64_t)SCAN_PER * SCAN_MAXB) { *why = "too many tiles"; return GEMPIC_EINVAL; }
   return GEMPIC_OK;
 }
 
@@ -722,6 +731,7 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   g->grank = cfg->track_ids ? (int32_t*)A(ng * 4) : nullptr;
   g->tile_count = (int64_t*)A((size_t)G.NT * 8);
   g->tile_base = (int64_t*)A((size_t)G.NT * 8);
+  g->scan_part = (int64_t*)A((size_t)2 * SCAN_MAXB * 8);
   g->total = (int64_t*)A(8);
   g->next_id = (int64_t*)A(8);
   g->inj_total = (int64_t*)A(8);
@@ -905,8 +915,7 @@ int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void*
   }
   HIPCHK(g, hipMemcpyAsync(g->tile_count, cnt.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
   ChunkTab& t0 = g->ct[g->ctc];
-  k_scan_tiles<<<1, 1024, 0, g->s>>>(G.NT, g->tile_count, g->tile_base, g->total, t0.first, t0.count, t0.n,
-                                      g->capacity, g->err_dev);
+  scan_tiles(g, t0);
   k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, t0, g->max_chunks);
   if (spectral) {
     const char* sp = (const char*)spectral;

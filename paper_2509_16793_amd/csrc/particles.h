@@ -345,27 +345,16 @@ __global__ void k_tile_offsets(OffArgs a) {
   a.tile_count[t] = run;
 }
 
-// Step 3 (single work-group): exclusive scans of the tile counts (-> tile base,
-// total) and of the chunks per tile (-> chunk first, number of chunks).
-__global__ __launch_bounds__(1024) void k_scan_tiles(int NT, const int64_t* tile_count,
-                                                     int64_t* tile_base, int64_t* total,
-                                                     int32_t* ch_first, int32_t* ch_count,
-                                                     int32_t* nchunks, int64_t capacity,
-                                                     int* err) {
-  __shared__ int64_t sa[1024];
-  __shared__ int64_t sb[1024];
+// Step 3: exclusive scans of the tile counts (-> tile_base, total) and of the chunk
+// counts per tile (-> ch_first, ch_count, nchunks) in three kernels: sums of
+// SCAN_PER tiles per block, a single-block scan of those sums (with the
+// capacity check), and the per-block scans offset by it.
+#define SCAN_PER 4096
+#define SCAN_MAXB 1024
+
+// in-place inclusive scan of two 1024-entry LDS arrays (all 1024 threads)
+GP_DEV void block_scan2(int64_t* sa, int64_t* sb) {
   int tid = threadIdx.x;
-  int per = (NT + 1023) / 1024;
-  int i0 = tid * per, i1 = min(NT, i0 + per);
-  int64_t s1 = 0, s2 = 0;
-  for (int i = i0; i < i1; ++i) {
-    int64_t n = tile_count[i];
-    s1 += n;
-    s2 += (n + GP_CHUNK - 1) / GP_CHUNK;
-  }
-  sa[tid] = s1;
-  sb[tid] = s2;
-  __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
     int64_t va = tid >= o ? sa[tid - o] : 0;
     int64_t vb = tid >= o ? sb[tid - o] : 0;
@@ -374,21 +363,82 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int NT, const int64_t* tile
     sb[tid] += vb;
     __syncthreads();
   }
-  int64_t r1 = tid ? sa[tid - 1] : 0, r2 = tid ? sb[tid - 1] : 0;
-  for (int i = i0; i < i1; ++i) {
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles_sum(int NT, const int64_t* tile_count, int64_t* part) {
+  __shared__ int64_t sa[1024];
+  __shared__ int64_t sb[1024];
+  int tid = threadIdx.x;
+  int i0 = blockIdx.x * SCAN_PER, i1 = min(NT, i0 + SCAN_PER);
+  int64_t s1 = 0, s2 = 0;
+  for (int i = i0 + tid; i < i1; i += 1024) {
     int64_t n = tile_count[i];
-    tile_base[i] = r1;
-    int nc = (int)((n + GP_CHUNK - 1) / GP_CHUNK);
-    ch_first[i] = (int32_t)r2;
-    ch_count[i] = nc;
-    r1 += n;
-    r2 += nc;
+    s1 += n;
+    s2 += (n + GP_CHUNK - 1) / GP_CHUNK;
+  }
+  sa[tid] = s1;
+  sb[tid] = s2;
+  __syncthreads();
+  block_scan2(sa, sb);
+  if (tid == 1023) {
+    part[2 * blockIdx.x] = sa[1023];
+    part[2 * blockIdx.x + 1] = sb[1023];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles_top(int nb, int64_t* part, int64_t* total, int32_t* nchunks,
+                                                         int64_t capacity, int* err) {
+  __shared__ int64_t sa[1024];
+  __shared__ int64_t sb[1024];
+  int tid = threadIdx.x;
+  int64_t a = tid < nb ? part[2 * tid] : 0, b = tid < nb ? part[2 * tid + 1] : 0;
+  sa[tid] = a;
+  sb[tid] = b;
+  __syncthreads();
+  block_scan2(sa, sb);
+  if (tid < nb) {
+    part[2 * tid] = sa[tid] - a;          // exclusive offsets
+    part[2 * tid + 1] = sb[tid] - b;
   }
   if (tid == 1023) {
     *total = sa[1023];
     *nchunks = (int32_t)sb[1023];
     // over capacity: no chunk is processed any more (the error is reported)
     if (sa[1023] > capacity) { atomicOr(err, ERR_CAPACITY); *nchunks = 0; *total = 0; }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles_apply(int NT, const int64_t* tile_count, const int64_t* part,
+                                                           int64_t* tile_base, int32_t* ch_first,
+                                                           int32_t* ch_count) {
+  __shared__ int64_t sa[1024];
+  __shared__ int64_t sb[1024];
+  constexpr int PER = SCAN_PER / 1024;
+  int tid = threadIdx.x;
+  int i0 = blockIdx.x * SCAN_PER + tid * PER;
+  int64_t n[PER];
+  int64_t s1 = 0, s2 = 0;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    n[r] = i0 + r < NT ? tile_count[i0 + r] : 0;
+    s1 += n[r];
+    s2 += (n[r] + GP_CHUNK - 1) / GP_CHUNK;
+  }
+  sa[tid] = s1;
+  sb[tid] = s2;
+  __syncthreads();
+  block_scan2(sa, sb);
+  int64_t r1 = part[2 * blockIdx.x] + sa[tid] - s1;
+  int64_t r2 = part[2 * blockIdx.x + 1] + sb[tid] - s2;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    if (i0 + r >= NT) break;
+    int nc = (int)((n[r] + GP_CHUNK - 1) / GP_CHUNK);
+    tile_base[i0 + r] = r1;
+    ch_first[i0 + r] = (int32_t)r2;
+    ch_count[i0 + r] = nc;
+    r1 += n[r];
+    r2 += nc;
   }
 }
 
