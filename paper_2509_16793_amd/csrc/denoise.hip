@@ -66,6 +66,19 @@ GP_DEV unsigned f2bf(float f) {               // round to nearest even
   u += 0x7FFFu + ((u >> 16) & 1u);
   return u >> 16;
 }
+// two floats -> packed bf16 (round to nearest even, v_cvt_pk_bf16_f32)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+GP_DEV unsigned pack_bf16(float lo, float hi) {
+  f32x2 v = {lo, hi};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+
+// LDS voxel offset of tap t in a halo tile (the padding taps t > 26 read tap
+// 26 with zero weights); a constant for a constant t
+GP_HD constexpr int tap_off(int t) {
+  return t > 26 ? tap_off(26) : ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * HX + (t % 3 - 1);
+}
 GP_DEV float bf2f(unsigned b) { return __uint_as_float(b << 16); }
 GP_DEV int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -137,7 +150,11 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   constexpr int NKS = (27 + TPK - 1) / TPK;
   constexpr int NCT = COUTP / 16;
   constexpr int RPW = TZ * TY / 4;          // 16-voxel rows per wave
-  __shared__ u32x4 sX[HALO * U];
+  // halo tile, unit-major: sX[unit * HALO_P + voxel], so that the 16 lanes of
+  // a lane group read 16 consecutive 16-byte units; the unit stride is padded
+  // so that the units start on different banks
+  constexpr int HALO_P = HALO + 2;
+  __shared__ u32x4 sX[HALO_P * U];
 
   const int nbx = a.X / TX, nby = a.Y / TY;
   int b = blockIdx.x;
@@ -146,18 +163,31 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int by = b % nby, bz = b / nby;
   const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+  // weights first: their loads overlap the halo staging
+  bf16x8 wr[NKS][NCT];
+#pragma unroll
+  for (int s = 0; s < NKS; ++s)
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) wr[s][j] = __builtin_bit_cast(bf16x8, a.wp[(s * NCT + j) * 64 + lane]);
 
   if (INMODE == 0) {
-    for (int u = tid; u < HALO * U; u += 256) {
-      int hv = u / U, part = u - hv * U;
-      int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
-      int gz = z0 + hz - 1;
+    // one halo row (HX voxels x U units, contiguous in global memory apart
+    // from the periodic wrap) per group of HX * U threads
+    constexpr int RW = HX * U;
+    const int iw = tid % RW;
+    const int hx = iw / U, part = iw - hx * U;
+    const int gx = wrapi(x0 + hx - 1, a.X);
+    const int first_row = tid < (256 / RW) * RW ? tid / RW : HZ * HY;   // spare threads idle
+    for (int row = first_row; row < HZ * HY; row += 256 / RW) {
+      const int hz = row / HY, hy = row - hz * HY;
+      const int gz = z0 + hz - 1;
       u32x4 v = {0u, 0u, 0u, 0u};
       if (gz >= 0 && gz < a.Z) {
-        int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
+        const int gy = wrapi(y0 + hy - 1, a.Y);
         v = a.in[(((int64_t)gz * a.Y + gy) * a.X + gx) * U + part];
       }
-      sX[u] = v;
+      sX[part * HALO_P + row * HX + hx] = v;
     }
   } else {
     for (int hv = tid; hv < HALO; hv += 256) {
@@ -171,46 +201,51 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         c1 = a.inf[1][o] * a.in_scale;
         c2 = a.inf[2][o] * a.in_scale;
       }
-      u32x4 v = {f2bf(c0) | (f2bf(c1) << 16), f2bf(c2), 0u, 0u};
+      u32x4 v = {pack_bf16(c0, c1), pack_bf16(c2, 0.0f), 0u, 0u};
       sX[hv] = v;
     }
   }
 
-  const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-  bf16x8 wr[NKS][NCT];
-#pragma unroll
-  for (int s = 0; s < NKS; ++s)
-#pragma unroll
-    for (int j = 0; j < NCT; ++j) wr[s][j] = __builtin_bit_cast(bf16x8, a.wp[(s * NCT + j) * 64 + lane]);
   __syncthreads();
 
-  for (int it = 0; it < RPW; it += 2) {
-    f32x4 acc[2][NCT];
-    int base[2];
+  // RR rows of 16 voxels at a time: RR independent accumulator chains and RR
+  // LDS reads in flight per k-step
+  constexpr int RR = 4;
+  for (int it = 0; it < RPW; it += RR) {
+    f32x4 acc[RR][NCT];
+    int base[RR];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < RR; ++r) {
       int rg = wave * RPW + it + r;
       int zz = rg / TY, yy = rg - zz * TY;
       base[r] = ((zz + 1) * HY + (yy + 1)) * HX + (n + 1);
 #pragma unroll
       for (int j = 0; j < NCT; ++j) acc[r][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     }
+    const int dt = (g * 8) / CINP;          // this lane group's tap within a k-step
+    const int c0u = ((g * 8) % CINP) / 8;   // and its 16-byte channel unit
+    int bb[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) bb[r] = c0u * HALO_P + base[r];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
-      int t = s * TPK + (g * 8) / CINP;
-      t = t > 26 ? 26 : t;                   // padding tap: zero weights
-      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-      int off = ((dz * HY + dy) * HX + dx) * U + ((g * 8) % CINP) / 8;
+      int toff;
+      if (TPK == 1) toff = tap_off(s);
+      else if (TPK == 2) toff = dt ? tap_off(2 * s + 1) : tap_off(2 * s);
+      else toff = dt == 0 ? tap_off(4 * s) : dt == 1 ? tap_off(4 * s + 1)
+                : dt == 2 ? tap_off(4 * s + 2) : tap_off(4 * s + 3);
+      const int off = toff;
+      bf16x8 bv[RR];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        bf16x8 bv = __builtin_bit_cast(bf16x8, sX[base[r] * U + off]);
+      for (int r = 0; r < RR; ++r) bv[r] = __builtin_bit_cast(bf16x8, sX[bb[r] + off]);
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
 #pragma unroll
         for (int j = 0; j < NCT; ++j)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[s][j], bv, acc[r][j], 0, 0, 0);
-      }
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[s][j], bv[r], acc[r][j], 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < RR; ++r) {
       int rg = wave * RPW + it + r;
       int zz = rg / TY, yy = rg - zz * TY;
       int z = z0 + zz;
@@ -239,8 +274,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             }
           }
           u32x2 o;
-          o[0] = f2bf(v[0]) | (f2bf(v[1]) << 16);
-          o[1] = f2bf(v[2]) | (f2bf(v[3]) << 16);
+          o[0] = pack_bf16(v[0], v[1]);
+          o[1] = pack_bf16(v[2], v[3]);
           *(u32x2*)(a.out + vox * COUTP + co0) = o;
         }
       }

@@ -243,14 +243,16 @@ __global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
     int code = -1;
     if (p < p1) {
       int cell = a.cell[p];
-      int ix = cell % g.Nx, r = cell / g.Nx;
-      int iy = r % g.Ny, iz = r / g.Ny;
       if (cell < 0) {
         code = CODE_REMOVED;
       } else {
-        int sx = tile_step(tx, ix / g.Tx, g.nTx);
-        int sy = tile_step(ty, iy / g.Ty, g.nTy);
-        int sz = iz / g.Tz - tz;
+        // power-of-two grid and tile sizes: shifts and masks
+        int ix = cell & (g.Nx - 1);
+        int iy = (cell >> g.lnx) & (g.Ny - 1);
+        int iz = cell >> (g.lnx + g.lny);
+        int sx = tile_step(tx, ix >> (__ffs(g.Tx) - 1), g.nTx);
+        int sy = tile_step(ty, iy >> (__ffs(g.Ty) - 1), g.nTy);
+        int sz = (iz >> (__ffs(g.Tz) - 1)) - tz;
         if (sx == 99 || sy == 99 || sz < -1 || sz > 0) {
           atomicOr(a.err, ERR_TILE);
           code = CODE_REMOVED;
