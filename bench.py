@@ -27,7 +27,7 @@ METRIC = "particle updates/s (gather+push+deposit), % HBM roofline; 1ppc+CNN vs 
 # HBM bytes per k_push_deposit launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this
 # workload, scaled by a plain-copy calibration (profiles/k_push_deposit_lwfa3d_*.md);
 # valid only for the kernel source it was measured on.
-MEASURED_TRAFFIC = {"push_h_sha256_prefix": "e1bb74c63113f18c", "bytes_per_launch": 6.214e9}
+MEASURED_TRAFFIC = {"push_h_sha256_prefix": "1f37f3e26fbf2dfd", "bytes_per_launch": 5.577e9}
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 28          # int32 cell + 3 x FP32 offset + 3 x FP32 momentum
 
@@ -146,7 +146,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lwfa3d_fp32: 3-D LWFA 256x256x512, dx=dy=0.4, dzeta=0.05 "
                                "(lambda_L), n_e=0.001 n_c, 2 ppc, a0=2, waist 8, FWHM 8, "
-                               "FP32 cell+offset particles",
+                               "FP32 cell+offset particles, 8x8x4 tiles",
                    "grid": cfg["n"], "ppc": ppc, "particles": int(n_avg)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

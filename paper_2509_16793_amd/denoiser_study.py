@@ -19,6 +19,7 @@ zeta after given steps, and wall time per step.
 
     python -m paper_2509_16793_amd.denoiser_study train --seeds 0-63 --out W.npy
     python -m paper_2509_16793_amd.denoiser_study eval --weights W.npy --seeds 64-67
+    python -m paper_2509_16793_amd.denoiser_study step --weights W.npy --steps 5
 """
 import argparse
 import json
@@ -195,6 +196,10 @@ def main(argv=None):
     ev.add_argument("--narrow", action="store_true", help="64 x 64 transverse box")
     ev.add_argument("--threshold", type=float, default=1e-3)
     ev.add_argument("--out", default=None)
+    st = sub.add_parser("step", help="time steps of the full-size 1-ppc run with the network")
+    st.add_argument("--weights", required=True)
+    st.add_argument("--steps", type=int, default=5)
+    st.add_argument("--warmup", type=int, default=3)
     a = ap.parse_args(argv)
     # torch carries its own HIP runtime: load it before the library so that
     # both share one runtime in this process
@@ -209,6 +214,21 @@ def main(argv=None):
             logf.flush()
 
     import workloads
+    if a.cmd == "step":
+        from .gempic import Denoiser, Sim
+        d = Denoiser(np.load(a.weights))
+        sim = Sim(workloads.denoiser_lwfa(ppc=(1, 1, 1)))
+        sim.set_denoiser(d, 1e-3)
+        sim.step(a.warmup)
+        sim.timing(True)
+        t = run_timed(sim, a.steps)
+        ph, n = sim.get_timing()
+        log(json.dumps(dict(ms_per_step=1e3 * t / a.steps,
+                            phase_ms_per_step={k: v / n for k, v in ph.items()},
+                            fallbacks=sim.step(0, diag=True)["fallbacks"])))
+        sim.close()
+        d.close()
+        return 0
     if a.cmd == "train":
         rng = np.random.default_rng(1234)
         cfg = workloads.denoiser_train()
