@@ -26,8 +26,41 @@ where several quotients share a denominator.
 Field shape (reading; the paper states none): linear (cloud-in-cell) on the
 nodes.  Fields sit at nodes at level k; the plane n = N_zeta is a ghost plane
 of zero fields.
+
+Every product-plus-addend below is written madd(a, b, c) = a b + c.  In FP64 it
+is a product rounded, then a sum rounded (the plain formula).  On FP32 inputs it
+is one fused multiply-add, rounded once, which is what an FP32 push on hardware
+with FMA computes; the grouping of every sum is the same in both precisions.
 """
 import numpy as np
+
+
+def fma32(a, b, c):
+    """Fused multiply-add in FP32, rounded once to nearest-even.
+
+    The product of two FP32 numbers is exact in FP64; the FP64 sum is made
+    round-to-odd (sticky last bit from the exact TwoSum error), and rounding a
+    round-to-odd value of at least p + 2 bits to p bits equals rounding the
+    exact value (Boldo & Melquiond, IEEE Trans. Computers 57(4), 2008)."""
+    a = np.asarray(a, np.float32)
+    b = np.asarray(b, np.float32)
+    c = np.asarray(c, np.float32)
+    p = a.astype(np.float64) * b.astype(np.float64)
+    c64 = c.astype(np.float64)
+    s = p + c64
+    bb = s - p
+    e = (p - (s - bb)) + (c64 - bb)
+    even = (np.asarray(s).view(np.int64) & 1) == 0
+    toward = np.where(e > 0, np.inf, -np.inf)
+    s = np.where((e != 0) & even, np.nextafter(s, toward), s)
+    return s.astype(np.float32)
+
+
+def madd(a, b, c):
+    """a * b + c: fused in FP32, product then sum in FP64."""
+    if np.result_type(a, b, c) == np.float32:
+        return fma32(a, b, c)
+    return a * b + c
 
 
 def cic_weights(d):
@@ -59,54 +92,56 @@ def gather(p, P, F):
                 else:
                     w = wx[a] * wz[c]
                 for comp in range(6):
-                    out[comp] = out[comp] + w * F[comp][zc, ys[b], xs[a]]
+                    out[comp] = madd(w, F[comp][zc, ys[b], xs[a]], out[comp])
     return out
 
 
 def higuera_cary(ux, uy, uz, E, B, eps):
     """One Higuera-Cary momentum step; E, B arrays of shape (3, N)."""
     Ex, Ey, Ez = E
-    umx = ux + eps * Ex
-    umy = uy + eps * Ey
-    umz = uz + eps * Ez
+    umx = madd(eps, Ex, ux)
+    umy = madd(eps, Ey, uy)
+    umz = madd(eps, Ez, uz)
     bx = eps * B[0]
     by = eps * B[1]
     bz = eps * B[2]
-    um2 = umx * umx + umy * umy + umz * umz
-    b2 = bx * bx + by * by + bz * bz
-    sigma = 1.0 + um2 - b2
-    bu = bx * umx + by * umy + bz * umz
-    gp = np.sqrt((sigma + np.sqrt(sigma * sigma + 4.0 * (b2 + bu * bu))) * 0.5)
+    um2 = madd(umz, umz, madd(umy, umy, umx * umx))
+    b2 = madd(bz, bz, madd(by, by, bx * bx))
+    sigma = (1.0 + um2) - b2
+    bu = madd(bz, umz, madd(by, umy, bx * umx))
+    gp = np.sqrt((sigma + np.sqrt(madd(sigma, sigma, 4.0 * madd(bu, bu, b2)))) * 0.5)
     rgp = 1.0 / gp
     tx = bx * rgp
     ty = by * rgp
     tz = bz * rgp
-    s = 1.0 / (1.0 + (tx * tx + ty * ty + tz * tz))
-    ut = umx * tx + umy * ty + umz * tz
-    upx = s * ((umx + ut * tx) + (umy * tz - umz * ty))
-    upy = s * ((umy + ut * ty) + (umz * tx - umx * tz))
-    upz = s * ((umz + ut * tz) + (umx * ty - umy * tx))
-    nx = (upx + eps * Ex) + (upy * tz - upz * ty)
-    ny = (upy + eps * Ey) + (upz * tx - upx * tz)
-    nz = (upz + eps * Ez) + (upx * ty - upy * tx)
+    s = 1.0 / (1.0 + madd(tz, tz, madd(ty, ty, tx * tx)))
+    ut = madd(umz, tz, madd(umy, ty, umx * tx))
+    upx = s * (madd(ut, tx, umx) + madd(umy, tz, -(umz * ty)))
+    upy = s * (madd(ut, ty, umy) + madd(umz, tx, -(umx * tz)))
+    upz = s * (madd(ut, tz, umz) + madd(umx, ty, -(umy * tx)))
+    nx = madd(eps, Ex, upx) + madd(upy, tz, -(upz * ty))
+    ny = madd(eps, Ey, upy) + madd(upz, tx, -(upx * tz))
+    nz = madd(eps, Ez, upz) + madd(upx, ty, -(upy * tx))
     return nx, ny, nz
 
 
 def velocities(ux, uy, uz):
     """Return (gamma, v_x, v_y, v_z - 1)."""
-    uperp2 = ux * ux + uy * uy
-    g = np.sqrt(1.0 + (uperp2 + uz * uz))
+    uperp2 = madd(uy, uy, ux * ux)
+    g = np.sqrt(1.0 + madd(uz, uz, uperp2))
     rg = 1.0 / g
     vx = ux * rg
     vy = uy * rg
-    vzm1 = np.where(uz >= 0.0, (-(1.0 + uperp2) * rg) / (g + uz), uz * rg - 1.0)
+    vzm1 = np.where(uz >= 0.0, (-(1.0 + uperp2) * rg) / (g + uz), madd(uz, rg, -1.0))
     return g, vx, vy, vzm1
 
 
-def renormalise(d, shift):
-    """Offset d plus displacement shift (cell units) -> (new offset, cell step k).
-    k = floor(d + shift); d' = d + shift - k; a rounded d' == 1 becomes 0, k + 1."""
-    t = d + shift
+def renormalise(d, shift, a=None):
+    """Offset d plus displacement (cell units) -> (new offset, cell step k).
+    The displacement is shift, or madd(shift, a, d) - d when a velocity shift
+    and a factor a are given.  k = floor(t); d' = t - k; a rounded d' == 1
+    becomes 0, k + 1."""
+    t = d + shift if a is None else madd(shift, a, d)
     k = np.floor(t)
     t = t - k
     up = t >= 1.0
@@ -126,13 +161,13 @@ def push_and_move(p, P, F):
     ax = p.dtau / p.hx
     az = p.dtau / p.h
     old = (P.ix.copy(), P.iy.copy(), P.iz.copy(), P.dx.copy(), P.dy.copy(), P.dz.copy())
-    P.dx, kx = renormalise(P.dx, vx * ax)
+    P.dx, kx = renormalise(P.dx, vx, ax)
     if p.dims == 3:
         ay = p.dtau / p.hy
-        P.dy, ky = renormalise(P.dy, vy * ay)
+        P.dy, ky = renormalise(P.dy, vy, ay)
     else:
         ky = np.zeros_like(kx)
-    P.dz, kz = renormalise(P.dz, vzm1 * az)
+    P.dz, kz = renormalise(P.dz, vzm1, az)
     if np.any(np.abs(kx) > 1) or np.any(np.abs(ky) > 1) or np.any(np.abs(kz) > 1):
         raise FloatingPointError("a particle crossed more than one cell in a step")
     P.ix = (P.ix + kx) % p.Nx

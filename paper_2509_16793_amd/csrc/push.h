@@ -12,7 +12,8 @@
 // v dtau / h_axis, zeta by (v_z - 1) dtau / h with the cancellation-free
 // v_z - 1; a cell step beyond one raises ERR_CFL and the particle is left
 // unchanged.  Gather, push and move follow a fixed operation order without
-// contraction, so FP64 (and FP32) results reproduce a reference bit for bit.
+// contraction beyond the fused multiply-adds written out (FP32 only), so FP64
+// and FP32 results reproduce a reference bit for bit.
 // Deposit: Esirkepov frame current W on the staggered grid plus the time- and
 // zeta-centred charge for the lab J_z, accumulated in an LDS tile of
 // (TX+3) x (TY+3) x (TZ+4) nodes per component (origin x0-1, y0-1, node z0-2),
@@ -54,6 +55,12 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using t = float2; };
 template <> struct Vec2<double> { using t = double2; };
 
+// a * b + c: one fused multiply-add in FP32 (rounded once); product, then sum,
+// in FP64.  The grouping of every sum of the push is the same in both.
+template <typename T> GP_DEV T madd(T a, T b, T c);
+template <> GP_DEV float madd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> GP_DEV double madd<double>(double a, double b, double c) { return a * b + c; }
+
 // fixed-point accumulator of the LDS deposit tile
 template <typename T> struct Fix;
 template <> struct Fix<float> {
@@ -94,21 +101,55 @@ struct PLoad {
   T ox, oy, oz, ux, uy, uz;
 };
 
-template <typename T, int DIM>
-GP_DEV PLoad<T> load_particle(const PartPtrs<T>& P, int p, bool ok) {
-  PLoad<T> s;
-  if (ok) {
-    s.cell = P.cell[p];
-    s.ox = P.ox[p];
-    s.oy = DIM == 3 ? P.oy[p] : (T)0;
-    s.oz = P.oz[p];
-    s.ux = P.ux[p];
-    s.uy = P.uy[p];
-    s.uz = P.uz[p];
-  } else {
-    s.cell = 0;
-    s.ox = s.oy = s.oz = s.ux = s.uy = s.uz = (T)0;
+// Particle rows go through buffer resources: a scalar base (the row's first
+// particle) and a range of the row's particles, with the lane's byte offset
+// as the only per-lane address part.  Lanes past the range read zero and
+// their stores are dropped by the hardware range check.
+template <int B> struct RowIO;
+template <> struct RowIO<4> {
+  template <typename Q> static GP_DEV Q ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(Q, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
   }
+  template <typename Q> static GP_DEV void st(Q v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+  }
+};
+template <> struct RowIO<8> {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  template <typename Q> static GP_DEV Q ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(Q, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  }
+  template <typename Q> static GP_DEV void st(Q v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, 0);
+  }
+};
+
+template <typename Q>
+GP_DEV __amdgpu_buffer_rsrc_t row_rsrc(Q* p, int base, int n) {
+  // raw buffer (no stride), n elements; dword 3 = 32-bit data format on gfx9
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(p + base), (short)0, max(n, 0) * (int)sizeof(Q),
+                                           0x00020000);
+}
+template <typename Q>
+GP_DEV Q row_ld(Q* p, int base, int n, unsigned lane) {
+  return RowIO<sizeof(Q)>::template ld<Q>(row_rsrc(p, base, n), lane * (unsigned)sizeof(Q));
+}
+template <typename Q>
+GP_DEV void row_st(Q v, Q* p, int base, int n, unsigned lane) {
+  RowIO<sizeof(Q)>::template st<Q>(v, row_rsrc(p, base, n), lane * (unsigned)sizeof(Q));
+}
+
+// the n particles base .. base + n - 1, one per lane (lanes >= n get zeros)
+template <typename T, int DIM>
+GP_DEV PLoad<T> load_row(const PartPtrs<T>& P, int base, int n, unsigned lane) {
+  PLoad<T> s;
+  s.cell = row_ld(P.cell, base, n, lane);
+  s.ox = row_ld(P.ox, base, n, lane);
+  s.oy = DIM == 3 ? row_ld(P.oy, base, n, lane) : (T)0;
+  s.oz = row_ld(P.oz, base, n, lane);
+  s.ux = row_ld(P.ux, base, n, lane);
+  s.uy = row_ld(P.uy, base, n, lane);
+  s.uz = row_ld(P.uz, base, n, lane);
   return s;
 }
 
@@ -126,8 +167,12 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   constexpr int RN = RX * RY * RZ;
   constexpr int SJ = JN + (RHO ? 2 * RN : 0);
   using A = typename Fix<T>::t;
-  __shared__ __align__(16) T sF[6 * FN];
-  __shared__ __align__(16) A sJ[SJ];
+  // one LDS block, field tile first: the gather's node offsets stay small
+  // enough for immediate LDS offsets
+  constexpr int NF8 = (6 * FN * (int)sizeof(T) + 15) / 16 * 2;
+  __shared__ __align__(16) A smem[NF8 + SJ];
+  T* const sF = reinterpret_cast<T*>(smem);
+  A* const sJ = smem + NF8;
   using V2 = typename Vec2<T>::t;
 
   const Geom& g = a.g;
@@ -146,19 +191,22 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   const int mx = g.Nx - 1, my = g.Ny - 1;
   const int64_t plane_stride = (int64_t)g.Ny * g.Nx;
 
-  for (int idx = threadIdx.x; idx < SJ; idx += blockDim.x) sJ[idx] = (A)0;
+  for (int idx = threadIdx.x; idx < SJ; idx += NTHR) sJ[idx] = (A)0;
 
   // particle range of a tile of this column
   auto range = [&](int tzz, int* q0, int* q1) {
     const int tt = (tzz * g.nTy + ty) * g.nTx + tx;
     const int64_t pb = a.tile_base[tt];
-    *q0 = (int)min(pb, ntot);
-    *q1 = (int)min(pb + a.tile_count[tt], ntot);
+    // uniform values: kept in scalar registers, so that row addresses are
+    // scalar bases plus the lane offset
+    *q0 = __builtin_amdgcn_readfirstlane((int)min(pb, ntot));
+    *q1 = __builtin_amdgcn_readfirstlane((int)min(pb + a.tile_count[tt], ntot));
   };
   int p0, p1;
   range(tz0, &p0, &p1);
   // the next row's particles are loaded while the current row is processed
-  PLoad<T> nxt = load_particle<T, DIM>(P, p0 + (int)threadIdx.x, p0 + (int)threadIdx.x < p1);
+  const unsigned lane = threadIdx.x;
+  PLoad<T> nxt = load_row<T, DIM>(P, p0, p1 - p0, lane);
 
   for (int tz = tz0; tz < tz1; ++tz) {
   const int z0 = tz * TZ;
@@ -168,7 +216,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   // the carried plane 0 (3 pairs per node, one thread per (y, x, pair))
   {
     const int lz_first = tz == tz0 ? 0 : 1;
-    for (int it = threadIdx.x; it < 3 * FX * FY; it += blockDim.x) {
+    for (int it = threadIdx.x; it < 3 * FX * FY; it += NTHR) {
       int part = it % 3, r = it / 3;
       int lx = r % FX, ly = r / FX;
       int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
@@ -188,15 +236,14 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   }
   __syncthreads();
 
-  for (int row = p0; row < p1; row += blockDim.x) {
-    int p = row + (int)threadIdx.x;
-    bool valid = p < p1;
+  for (int row = p0; row < p1; row += NTHR) {
+    bool valid = row + (int)lane < p1;
     const PLoad<T> cur = nxt;
+    // prefetch: the next row of this tile, else the first row of the next tile
     {
-      // prefetch: the next row of this tile, else the first row of the next tile
-      int pn = row + (int)blockDim.x < p1 ? p + (int)blockDim.x : np0 + (int)threadIdx.x;
-      bool okn = row + (int)blockDim.x < p1 ? pn < p1 : pn < np1;
-      nxt = load_particle<T, DIM>(P, pn, okn);
+      const bool same = row + NTHR < p1;
+      const int nb = same ? row + NTHR : np0;
+      nxt = load_row<T, DIM>(P, nb, (same ? p1 : np1) - nb, lane);
     }
     int lx = 0, ly = 0, lz = 0, kx = 0, ky = 0, kz = 0;
     T dx0 = (T)0, dy0 = (T)0, dz0 = (T)0, dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
@@ -236,53 +283,53 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
               const T v[6] = {r0.x, r0.y, r1.x, r1.y, r2.x, r2.y};
               const bool first = cc == 0 && b == 0 && aa == 0;
 #pragma unroll
-              for (int k = 0; k < 6; ++k) f[k] = first ? w * v[k] : f[k] + w * v[k];
+              for (int k = 0; k < 6; ++k) f[k] = first ? w * v[k] : madd(w, v[k], f[k]);
             }
           }
         }
 
         // Higuera-Cary push
         T eps = a.eps;
-        T umx = ux + eps * f[0];
-        T umy = uy + eps * f[1];
-        T umz = uz + eps * f[2];
+        T umx = madd(eps, f[0], ux);
+        T umy = madd(eps, f[1], uy);
+        T umz = madd(eps, f[2], uz);
         T bx = eps * f[3], by = eps * f[4], bz = eps * f[5];
-        T um2 = (umx * umx + umy * umy) + umz * umz;
-        T b2 = (bx * bx + by * by) + bz * bz;
+        T um2 = madd(umz, umz, madd(umy, umy, umx * umx));
+        T b2 = madd(bz, bz, madd(by, by, bx * bx));
         T sigma = ((T)1 + um2) - b2;
-        T bu = (bx * umx + by * umy) + bz * umz;
-        T gp = sqrt((sigma + sqrt(sigma * sigma + (T)4 * (b2 + bu * bu))) * (T)0.5);
+        T bu = madd(bz, umz, madd(by, umy, bx * umx));
+        T gp = sqrt((sigma + sqrt(madd(sigma, sigma, (T)4 * madd(bu, bu, b2)))) * (T)0.5);
         T rgp = (T)1 / gp;
         T tx_ = bx * rgp, ty_ = by * rgp, tz_ = bz * rgp;
-        T s = (T)1 / ((T)1 + ((tx_ * tx_ + ty_ * ty_) + tz_ * tz_));
-        T ut = (umx * tx_ + umy * ty_) + umz * tz_;
-        T upx = s * ((umx + ut * tx_) + (umy * tz_ - umz * ty_));
-        T upy = s * ((umy + ut * ty_) + (umz * tx_ - umx * tz_));
-        T upz = s * ((umz + ut * tz_) + (umx * ty_ - umy * tx_));
-        ux = (upx + eps * f[0]) + (upy * tz_ - upz * ty_);
-        uy = (upy + eps * f[1]) + (upz * tx_ - upx * tz_);
-        uz = (upz + eps * f[2]) + (upx * ty_ - upy * tx_);
+        T s = (T)1 / ((T)1 + madd(tz_, tz_, madd(ty_, ty_, tx_ * tx_)));
+        T ut = madd(umz, tz_, madd(umy, ty_, umx * tx_));
+        T upx = s * (madd(ut, tx_, umx) + madd(umy, tz_, -(umz * ty_)));
+        T upy = s * (madd(ut, ty_, umy) + madd(umz, tx_, -(umx * tz_)));
+        T upz = s * (madd(ut, tz_, umz) + madd(umx, ty_, -(umy * tx_)));
+        ux = madd(eps, f[0], upx) + madd(upy, tz_, -(upz * ty_));
+        uy = madd(eps, f[1], upy) + madd(upz, tx_, -(upx * tz_));
+        uz = madd(eps, f[2], upz) + madd(upx, ty_, -(upy * tx_));
 
         // move
-        T uperp2 = ux * ux + uy * uy;
-        T gam = sqrt((T)1 + (uperp2 + uz * uz));
+        T uperp2 = madd(uy, uy, ux * ux);
+        T gam = sqrt((T)1 + madd(uz, uz, uperp2));
         T rg = (T)1 / gam;
         T vx = ux * rg;
         vy = uy * rg;
-        T vzm1 = uz >= (T)0 ? (-((T)1 + uperp2) * rg) / (gam + uz) : uz * rg - (T)1;
-        T tnx = dx0 + vx * a.ax;
+        T vzm1 = uz >= (T)0 ? (-((T)1 + uperp2) * rg) / (gam + uz) : madd(uz, rg, (T)-1);
+        T tnx = madd(vx, a.ax, dx0);
         T kxf = floor(tnx);
         dx1 = tnx - kxf;
         kx = (int)kxf;
         if (dx1 >= (T)1) { dx1 = (T)0; kx += 1; }
         if (DIM == 3) {
-          T tny = dy0 + vy * a.ay;
+          T tny = madd(vy, a.ay, dy0);
           T kyf = floor(tny);
           dy1 = tny - kyf;
           ky = (int)kyf;
           if (dy1 >= (T)1) { dy1 = (T)0; ky += 1; }
         }
-        T tnz = dz0 + vzm1 * a.az;
+        T tnz = madd(vzm1, a.az, dz0);
         T kzf = floor(tnz);
         dz1 = tnz - kzf;
         kz = (int)kzf;
@@ -296,13 +343,14 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           int nix = (ix + kx) & mx;
           int niy = (iy + ky) & my;
           int niz = iz + kz;
-          P.cell[p] = (niz * g.Ny + niy) * g.Nx + nix;
-          P.ox[p] = dx1;
-          if (DIM == 3) P.oy[p] = dy1;
-          P.oz[p] = dz1;
-          P.ux[p] = ux;
-          P.uy[p] = uy;
-          P.uz[p] = uz;
+          const int nr = p1 - row;
+          row_st((niz * g.Ny + niy) * g.Nx + nix, P.cell, row, nr, lane);
+          row_st(dx1, P.ox, row, nr, lane);
+          if (DIM == 3) row_st(dy1, P.oy, row, nr, lane);
+          row_st(dz1, P.oz, row, nr, lane);
+          row_st(ux, P.ux, row, nr, lane);
+          row_st(uy, P.uy, row, nr, lane);
+          row_st(uz, P.uz, row, nr, lane);
         }
       }
     }
@@ -484,7 +532,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
     const bool last = tz + 1 == tz1;
     // a slab's planes below TZ + first are final: the next tile's deposits of
     // that component start at plane TZ + first
-    for (int col = threadIdx.x; col < 3 * JP; col += blockDim.x) {
+    for (int col = threadIdx.x; col < 3 * JP; col += NTHR) {
       int q = col / JP, l = col - q * JP;
       int jx = l % JX, jy = l / JX;
       int gx = (x0 - 1 + jx) & mx;
@@ -509,7 +557,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
     if (RHO) {
       // rho tiles: origin node z0 - 1 (plane z0 + 1), RZ planes
       const int rflush = last ? RZ : TZ;
-      for (int col = threadIdx.x; col < 2 * RY * RX; col += blockDim.x) {
+      for (int col = threadIdx.x; col < 2 * RY * RX; col += NTHR) {
         int q = col / (RY * RX), l = col - q * (RY * RX);
         int rx = l % RX, ry = l / RX;
         int gx = (x0 - 1 + rx) & mx;
@@ -532,7 +580,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
     }
     // the last field plane becomes the first one of the next tile
     if (!last) {
-      for (int it = threadIdx.x; it < 3 * FX * FY; it += blockDim.x) {
+      for (int it = threadIdx.x; it < 3 * FX * FY; it += NTHR) {
         V2* f = reinterpret_cast<V2*>(sF);
         f[it] = f[3 * TZ * FX * FY + it];
       }
@@ -540,7 +588,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   }
   __syncthreads();
   // an empty tile consumed no prefetch: load the next tile's first row now
-  if (p0 >= p1) nxt = load_particle<T, DIM>(P, np0 + (int)threadIdx.x, np0 + (int)threadIdx.x < np1);
+  if (p0 >= p1) nxt = load_row<T, DIM>(P, np0, np1 - np0, lane);
   p0 = np0;
   p1 = np1;
   }  // zeta tiles of the segment

@@ -8,6 +8,9 @@
   A_x = a0 cos(zeta) exp(-zeta^2 / 2 sigma^2), E_x = B_y = A_x'(zeta), an
   electron starting at rest has u_x = A_x, gamma - u_z = 1, and is at rest again
   after the pulse; the scheme's error is second order in (h, dtau).
+* FP32 fused multiply-add: equal to the exact a b + c rounded once to the
+  nearest FP32 number (exact rational arithmetic), including cases where a
+  product rounded first, or a sum rounded first to FP64, gives another result.
 """
 import math
 
@@ -16,7 +19,9 @@ import pytest
 
 from oracle import params
 from oracle.plasma import Particles
-from oracle.push import higuera_cary, push_and_move, renormalise, velocities
+from fractions import Fraction
+
+from oracle.push import fma32, higuera_cary, madd, push_and_move, renormalise, velocities
 
 
 def test_gyration_exact_rotation():
@@ -135,3 +140,58 @@ def test_plane_wave_electron_closed_form_and_order():
     # second order: halving (h, dtau) divides the error by ~4
     assert 3.0 < e1[0] / e2[0] < 5.0
     assert 3.0 < e1[1] / e2[1] < 5.0
+
+
+def _round_binary32(x):
+    """Exact rational -> nearest binary32 (ties to even), normal range."""
+    if x == 0:
+        return 0.0
+    sign = -1 if x < 0 else 1
+    x = abs(x)
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1
+    elif Fraction(2) ** (e + 1) <= x:
+        e += 1
+    m = x / Fraction(2) ** (e - 23)          # in [2^23, 2^24)
+    q = m.numerator // m.denominator
+    r = m - q
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and q % 2 == 1):
+        q += 1
+    return sign * float(Fraction(q) * Fraction(2) ** (e - 23))
+
+
+def test_fma32_is_the_exact_value_rounded_once():
+    rng = np.random.default_rng(7)
+    n = 4000
+    a = (rng.standard_normal(n) * 2.0 ** rng.integers(-20, 20, n)).astype(np.float32)
+    b = (rng.standard_normal(n) * 2.0 ** rng.integers(-20, 20, n)).astype(np.float32)
+    c = (rng.standard_normal(n) * 2.0 ** rng.integers(-40, 40, n)).astype(np.float32)
+    # heavy cancellation: c close to -a b
+    k = n // 4
+    c[:k] = -(a[:k] * b[:k]) * (1 + rng.integers(-4, 5, k) * 2.0 ** -23)
+    one = np.float32(1 + 2.0 ** -12)
+    hard_a = np.array([one, one, one], np.float32)
+    hard_c = np.array([2.0 ** -30, 2.0 ** -60, -(2.0 ** -60)], np.float32)
+    a = np.concatenate([a, hard_a])
+    b = np.concatenate([b, hard_a])
+    c = np.concatenate([c, hard_c])
+    got = fma32(a, b, c)
+    want = np.array([_round_binary32(Fraction(float(x)) * Fraction(float(y)) + Fraction(float(z)))
+                     for x, y, z in zip(a, b, c)], np.float32)
+    assert np.array_equal(got, want)
+    # (1 + 2^-12)^2 = 1 + 2^-11 + 2^-24: the product alone is a tie, so the
+    # addend decides; rounding the product first, or the sum to FP64 first,
+    # loses it
+    assert got[-3] == np.float32(1 + 2.0 ** -11 + 2.0 ** -23)
+    assert (a[-3] * b[-3]) + c[-3] == np.float32(1 + 2.0 ** -11)
+    assert got[-2] == np.float32(1 + 2.0 ** -11 + 2.0 ** -23)
+    assert np.float32(np.float64(a[-2]) * np.float64(b[-2]) + np.float64(c[-2])) == np.float32(1 + 2.0 ** -11)
+    assert got[-1] == np.float32(1 + 2.0 ** -11)
+
+
+def test_madd_fp64_is_product_then_sum():
+    rng = np.random.default_rng(8)
+    a, b, c = rng.standard_normal((3, 1000))
+    assert np.array_equal(madd(a, b, c), a * b + c)
+    assert madd(a.astype(np.float32), b.astype(np.float32), c.astype(np.float32)).dtype == np.float32
