@@ -213,25 +213,33 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   int np0 = 0, np1 = 0;
   if (tz + 1 < tz1) range(tz + 1, &np0, &np1);
   // field node records: all planes for the first tile, planes 1 .. TZ after
-  // the carried plane 0 (3 pairs per node, one thread per (y, x, pair))
+  // the carried plane 0 (3 pairs per node, one thread per (y, x, pair)); a
+  // plane's address is a uniform base plus the thread's 32-bit byte offset
   {
-    const int lz_first = tz == tz0 ? 0 : 1;
     for (int it = threadIdx.x; it < 3 * FX * FY; it += NTHR) {
       int part = it % 3, r = it / 3;
       int lx = r % FX, ly = r / FX;
       int gx = x0 + lx; if (gx >= g.Nx) gx -= g.Nx;
       int gy = y0 + ly; if (gy >= g.Ny) gy -= g.Ny;
-      const V2* src = reinterpret_cast<const V2*>(a.F6) + 3 * ((int64_t)gy * g.Nx + gx) + part;
-      for (int lz = lz_first; lz < FZ; ++lz) {
-        int gz = z0 + lz;
+      const unsigned boff = ((unsigned)(gy * g.Nx + gx) * 3u + (unsigned)part) * (unsigned)sizeof(V2);
+      V2* dst = reinterpret_cast<V2*>(sF + 6 * (ly * FX + lx)) + part;
+      auto fetch = [&](int lz) {
+        const int gz = z0 + lz;
         V2 v;
         if (gz < g.Nz) {
-          v = src[3 * (int64_t)gz * plane_stride];
+          const char* plane = reinterpret_cast<const char*>(a.F6 + 6 * (int64_t)gz * plane_stride);
+          v = *reinterpret_cast<const V2*>(plane + boff);
         } else {
           v.x = (T)0; v.y = (T)0;
         }
-        reinterpret_cast<V2*>(sF + 6 * ((lz * FY + ly) * FX + lx))[part] = v;
-      }
+        return v;
+      };
+      V2 v[FZ];
+#pragma unroll
+      for (int lz = 1; lz < FZ; ++lz) v[lz] = fetch(lz);
+      if (tz == tz0) dst[0] = fetch(0);
+#pragma unroll
+      for (int lz = 1; lz < FZ; ++lz) dst[3 * lz * FX * FY] = v[lz];
     }
   }
   __syncthreads();
@@ -526,32 +534,53 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   __syncthreads();
 
   // flush the planes no later tile of the segment touches (all of them after
-  // the last tile), carry the rest down by TZ planes; one thread per column.
+  // the last tile), carry the rest down by TZ planes.  One thread per column
+  // (x, y) of a slab; slab q is handled by waves 2q, 2q+1 of a 128-lane block
+  // (one column per lane, JP <= 128), so that q is uniform in a wave and the
+  // destination plane is a uniform base plus the lane's 32-bit byte offset.
   // Global x = x0 - 1 + jx, y = y0 - 1 + jy, plane = z0 + jz.
   {
     const bool last = tz + 1 == tz1;
-    // a slab's planes below TZ + first are final: the next tile's deposits of
-    // that component start at plane TZ + first
-    for (int col = threadIdx.x; col < 3 * JP; col += NTHR) {
-      int q = col / JP, l = col - q * JP;
-      int jx = l % JX, jy = l / JX;
-      int gx = (x0 - 1 + jx) & mx;
-      int gy = DIM == 3 ? (y0 - 1 + jy) & my : 0;
-      T* dst = a.J[q] + (int64_t)gy * g.Nx + gx;
-      const int first = q < 2 ? 1 : 0;
-      A* sc = sJ + q * (JZ - 1) * JP + l - first * JP;   // sc[jz * JP]: plane jz
-      const int nflush = last ? JZ : TZ + first;
-      for (int jz = first; jz < nflush; ++jz) {
-        A iv = sc[jz * JP];
-        int plane = z0 + jz;
-        if (iv != (A)0 && plane < g.NPJ) atomicAdd(dst + plane * plane_stride, fix_value<T>(iv) * a.finv);
-      }
-      if (!last) {
-        for (int jz = TZ + first; jz < JZ; ++jz) {
-          sc[(jz - TZ) * JP] = sc[jz * JP];
-          sc[jz * JP] = (A)0;
-        }
-        for (int jz = JZ - TZ; jz < TZ + first; ++jz) sc[jz * JP] = (A)0;
+    static_assert(JP <= 128, "one column per lane of a 128-lane block");
+    for (int col = threadIdx.x; col < 3 * 128; col += NTHR) {
+      const int q = __builtin_amdgcn_readfirstlane(col >> 7);
+      const int l = col & 127;
+      if (l < JP) {
+        int jx = l % JX, jy = l / JX;
+        int gx = (x0 - 1 + jx) & mx;
+        int gy = DIM == 3 ? (y0 - 1 + jy) & my : 0;
+        const unsigned boff = (unsigned)(gy * g.Nx + gx) * (unsigned)sizeof(T);
+        T* const dq = a.J[q];
+        auto put = [&](A iv, int jz) {
+          const int plane = z0 + jz;
+          if (iv != (A)0 && plane < g.NPJ) {
+            char* base = reinterpret_cast<char*>(dq + (int64_t)plane * plane_stride);
+            atomicAdd(reinterpret_cast<T*>(base + boff), fix_value<T>(iv) * a.finv);
+          }
+        };
+        // a slab's planes below TZ + first are final: the next tile's deposits
+        // of that component start at plane TZ + first
+        auto slab = [&](auto first_c) {
+          constexpr int first = decltype(first_c)::value;
+          A* sc = sJ + q * (JZ - 1) * JP + l - first * JP;   // sc[jz * JP]: plane jz
+          A iv[JZ];
+#pragma unroll
+          for (int jz = first; jz < JZ; ++jz) iv[jz] = sc[jz * JP];
+#pragma unroll
+          for (int jz = first; jz < TZ + first; ++jz) put(iv[jz], jz);
+          if (last) {
+#pragma unroll
+            for (int jz = TZ + first; jz < JZ; ++jz) put(iv[jz], jz);
+          } else {
+#pragma unroll
+            for (int jz = first; jz < JZ; ++jz) {
+              const int src = jz + TZ;
+              sc[jz * JP] = src < JZ ? iv[src] : (A)0;
+            }
+          }
+        };
+        if (q < 2) slab(std::integral_constant<int, 1>());
+        else slab(std::integral_constant<int, 0>());
       }
     }
     if (RHO) {
