@@ -43,7 +43,11 @@
 extern "C" {
 #endif
 
-#define GEMPIC_ABI_VERSION 1
+#define GEMPIC_ABI_VERSION 2
+
+/* Bit of a particle's cell word that marks a driver-beam electron (gempic_particles,
+ * gempic_set_state); the cell index itself is the word without this bit. */
+#define GEMPIC_BEAM_BIT (1 << 30)
 
 typedef struct gempic gempic_t;
 
@@ -91,6 +95,26 @@ typedef struct {
   int32_t filter_passes;    /* binomial 1-2-1 passes per axis: 0, 1 or 2                */
   int32_t track_ids;        /* 1: keep a per-particle id array (tests, checkpoints)     */
   int32_t deposit_rho;      /* 1: also deposit charge (diagnostics: continuity, charge) */
+  /* Electron driver beam (3-D only; beam_np = 0: none).  beam_np macro-particles
+   * sample the density beam_n exp(-r^2 / (2 beam_sr^2)) exp(-(zeta - beam_zc)^2 /
+   * (2 beam_sz^2)) (rms sizes; r from the axis at node (Nx/2, Ny/2); density in
+   * the units of n_e), each carrying an equal share of the bunch charge; u_perp
+   * = 0, gamma normal with mean beam_gamma and deviation beam_dgamma.  Sampled on
+   * the host in FP64: SplitMix64 uniforms keyed by (seed, particle, draw) and
+   * the Box-Muller transform; particles outside the field box in zeta are not
+   * created.  The bunch's own field starts as the field of a charge moving at c:
+   * per zeta node the transverse Poisson solution E_perp = -grad phi, phi^ =
+   * rho^ / K^2, as a forward wave (R_perp = 2 E_perp, L = 0), made consistent by
+   * one march with Delta = 0 like the laser.  Beam particles are pushed and
+   * deposited like plasma ones with their own weight; their cell words carry
+   * GEMPIC_BEAM_BIT. */
+  double  beam_n;           /* peak density                                             */
+  double  beam_sr;          /* rms radius, config units                                 */
+  double  beam_sz;          /* rms length, config units                                 */
+  double  beam_zc;          /* centre, config units; NaN = (Nzeta - 1) h - 6 beam_sz    */
+  double  beam_gamma;       /* mean Lorentz factor (> 1)                                */
+  double  beam_dgamma;      /* rms spread of gamma                                      */
+  int64_t beam_np;          /* macro-particles                                          */
   void*   stream;           /* hipStream_t or NULL                                      */
 } gempic_config;
 
@@ -98,8 +122,8 @@ typedef struct {
 typedef struct {
   double  tau;              /* slow time after the step                                  */
   int64_t step;             /* steps done since creation                                 */
-  int64_t n_particles;      /* plasma macro-particles in the box                         */
-  double  charge_particles; /* q w N                                                     */
+  int64_t n_particles;      /* macro-particles in the box (plasma and beam)              */
+  double  charge_particles; /* sum of q w over the macro-particles                       */
   double  charge_grid;      /* sum of rho V over the grid (needs deposit_rho)            */
   double  field_energy;     /* 1/2 sum (E^2 + B^2) V over the field nodes                */
   double  continuity_rel;   /* ||(rho1-rho0)/dtau - D rhobar + D.J|| / ||(rho1-rho0)/dtau||
@@ -144,8 +168,9 @@ int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size
 /* Number of bytes gempic_fields needs for mask. */
 size_t gempic_fields_bytes(const gempic_t* g, uint32_t mask);
 
-/* Copy the plasma particles (structure of arrays, in the handle's sorted
- * order): cell[i] = (iz * Ny + iy) * Nx + ix (int32); off = 3 planes of
+/* Copy the particles (structure of arrays, in the handle's sorted order):
+ * cell[i] = (iz * Ny + iy) * Nx + ix (int32), with GEMPIC_BEAM_BIT set for
+ * driver-beam electrons; off = 3 planes of
  * capacity entries (offset in [0,1) along x, y, zeta); u = 3 planes of
  * capacity entries (momentum gamma v); id (nullable) = capacity int64 ids
  * (needs track_ids).  Offsets and momenta are double for GEMPIC_FP64, float

@@ -73,14 +73,15 @@ class _Acc:
         return np.bincount(idx, weights=val, minlength=self.size).reshape(shape)
 
 
-def deposit(p, old, new, steps, vy):
+def deposit(p, old, new, steps, vy, wr=None):
     """Currents of one step.  ``old``/``new`` = (ix, iy, iz, dx, dy, dz) before
     and after the move, ``steps`` = per-axis cell steps, ``vy`` = v_y (used in
-    2-D only).  Returns (Jx, Jy, Jz) each of shape (nplanes, Ny, Nx)."""
+    2-D only), ``wr`` = per-particle weight over p.w (None: all 1, the
+    plasma).  Returns (Jx, Jy, Jz) each of shape (nplanes, Ny, Nx)."""
     ix0, iy0, iz0, dx0, dy0, dz0 = old
     ix1, iy1, iz1, dx1, dy1, dz1 = new
     kx, ky, kz = steps
-    qw = p.q * p.w
+    qw = p.q * p.w if wr is None else p.q * p.w * wr
     V = p.hx * p.hy_eff * p.h
     bx, S0x, S1x = _window(ix0, kx, dx0, dx1)
     bz, S0z, S1z = _window(iz0, kz, dz0, dz1)
@@ -150,9 +151,10 @@ def deposit(p, old, new, steps, vy):
     return ax.result(), ay.result(), az.result()
 
 
-def deposit_rho(p, ix, iy, iz, dx, dy, dz):
-    """Charge density (linear shape) on nodes, same plane layout as the currents."""
-    qw = p.q * p.w
+def deposit_rho(p, ix, iy, iz, dx, dy, dz, wr=None):
+    """Charge density (linear shape) on nodes, same plane layout as the currents;
+    ``wr`` as in deposit."""
+    qw = p.q * p.w if wr is None else p.q * p.w * wr
     V = p.hx * p.hy_eff * p.h
     acc = _Acc(p)
     wx = (1.0 - dx, dx)

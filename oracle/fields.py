@@ -205,16 +205,63 @@ def real_fields(p, s):
     return out
 
 
-def laser_state(p):
+def beam_field(p, s, rho_b):
+    """Add the field of a charge moving at c (driver beam) to the state:
+    per zeta node the transverse Poisson problem div E_perp = rho with
+    E_perp = -grad phi, so phi^ = rho^ / K^2, E_perp^ = -i k_perp phi^ (K = 0
+    and Nyquist modes: 0), as a forward wave R_perp += 2 E_perp^ (B_perp = z x
+    E_perp, so L = 0).  rho_b: node charge density, shape (N_zeta, Ny, Nx),
+    filtered like the currents (binomial_filter, zero beyond the field nodes)
+    so that the field matches the filtered current the solver receives."""
+    KX, KY, nyq = wavenumbers(p)
+    K2 = KX * KX + KY * KY
+    for _ in range(p.filter_passes):
+        rho_b = binomial_filter(p, rho_b)
+    rh = fft2(rho_b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        phi = np.where(K2 > 0, rh / np.where(K2 > 0, K2, 1.0), 0.0)
+    Rx = -2j * KX * phi
+    Ry = -2j * KY * phi
+    Rx[:, nyq] = 0.0
+    Ry[:, nyq] = 0.0
+    s.Rx = s.Rx + Rx
+    s.Ry = s.Ry + Ry
+    return s
+
+
+def beam_current(p, rho_b):
+    """Lab current of charge moving at c, J_z(n + 1/2) = (rho(n) + rho(n+1))/2
+    (the time- and zeta-centred charge a step deposits for it), in the current
+    plane layout, filtered like a step's current; solver inputs."""
+    nplanes = p.Nz + p.ext + 4
+    Jz = np.zeros((nplanes, p.Ny, p.Nx))
+    r = np.zeros((p.Nz + 2, p.Ny, p.Nx))      # nodes -1 .. N_zeta
+    r[1:p.Nz + 1] = rho_b
+    Jz[G - 1:G + p.Nz] = 0.5 * (r[:-1] + r[1:])
+    zero = np.zeros_like(Jz)
+    J = [zero, zero.copy(), Jz]
+    for _ in range(p.filter_passes):
+        J = [binomial_filter(p, a) for a in J]
+    return half_node_currents(p, *J)
+
+
+def laser_state(p, rho_b=None):
     """Laser of Sec. 6 (eq. E_laser) as a pure forward wave in the Galilean
     frame: E_pol = a0 cos(phi) exp(-phi^2/T^2) exp(-r_perp^2/R^2), phi =
     zeta - zeta_c (k_0 = 1), on the field nodes n = 0 .. N_zeta - 1, axis at
-    node (Nx/2, Ny/2); R_pol = 2 E_pol, L = 0.
+    node (Nx/2, Ny/2); R_pol = 2 E_pol, L = 0; plus the field of a driver beam
+    of node charge density rho_b (beam_field), if given.
     The zeta-constraint fields (L, E_z, B_z) are then made consistent by one
-    march with Delta = 0 and no current."""
+    march with Delta = 0, with the beam's current (beam_current) if there is a
+    beam and no current otherwise."""
     s = SpectralState(p)
+    zero = np.zeros((p.Nz + 1, p.Ny, p.Nx), complex)
+    cur = (zero, zero, zero)
+    if rho_b is not None:
+        s = beam_field(p, s, rho_b)
+        cur = beam_current(p, rho_b)
     if p.a0 == 0.0:
-        return s
+        return s if rho_b is None else march(p, s, cur, 0.0)
     zeta = np.arange(p.Nz) * p.h
     phi = zeta - p.zeta_c
     lon = p.a0 * np.cos(phi) * np.exp(-(phi * phi) / (p.T * p.T))
@@ -233,8 +280,7 @@ def laser_state(p):
     R = fft2(2.0 * E)
     R[:, nyq] = 0.0
     if p.pol == 0:
-        s.Rx = R
+        s.Rx = s.Rx + R
     else:
-        s.Ry = R
-    zero = np.zeros((p.Nz + 1, p.Ny, p.Nx), complex)
-    return march(p, s, (zero, zero, zero), 0.0)
+        s.Ry = s.Ry + R
+    return march(p, s, cur, 0.0)

@@ -133,4 +133,22 @@ def from_config(cfg):
     # Beam/initialised macro-particle weight Q_b = q n h_x h_y h (Sec. 5.1),
     # shared among the ppc particles of a cell.
     p.w = n_e * hx * p.hy_eff * h / p.ppc_total
+    b = cfg.get("beam") or {}
+    if int(b.get("np", 0)) > 0:
+        # Electron driver (reading for a PWFA workload; the paper simulates
+        # none): Gaussian bunch n_b exp(-r^2/2 sr^2) exp(-(zeta - zc)^2/2 sz^2)
+        # (rms sizes) of n_b (2 pi)^(3/2) sr^2 sz electrons shared equally by
+        # np macro-particles; u_perp = 0, gamma ~ N(gamma, dgamma).
+        if dims != 3 or n_e <= 0.0:
+            raise ConfigError("a driver beam needs dims = 3 and a plasma")
+        sr, sz = float(b["sr"]) * lu, float(b["sz"]) * lu
+        zb = b.get("zc", None)
+        beam = dict(n=float(b["n"]), sr=sr, sz=sz,
+                    zc=(Nz - 1) * h - 6.0 * sz if zb is None else float(zb) * lu,
+                    gamma=float(b["gamma"]), dgamma=float(b.get("dgamma", 0.0)), np=int(b["np"]))
+        beam["w"] = beam["n"] * (2.0 * math.pi) ** 1.5 * sr * sr * sz / beam["np"]
+        beam["rb"] = beam["w"] / p.w
+        p.beam = beam
+    else:
+        p.beam = None
     return p

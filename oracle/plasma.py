@@ -22,6 +22,8 @@ m < (N_zeta + ext - 1) ppc_z); batch k + 1 is appended at the end of step k.
 Thresholds are computed once per batch in FP64 so that every lattice
 particle enters exactly once.
 """
+import math
+
 import numpy as np
 
 from . import rng
@@ -32,11 +34,15 @@ ONE_MINUS = np.nextafter(1.0, 0.0)
 class Particles:
     """Structure of arrays; every array has one entry per macro-particle."""
 
-    FIELDS = ("ix", "iy", "iz", "dx", "dy", "dz", "ux", "uy", "uz", "pid")
+    FIELDS = ("ix", "iy", "iz", "dx", "dy", "dz", "ux", "uy", "uz", "pid", "sp")
 
     def __init__(self, **arrays):
         for k in self.FIELDS:
-            setattr(self, k, arrays[k])
+            v = arrays.get(k)
+            if v is None and k == "sp":
+                # species: 0 plasma electron, 1 driver-beam electron
+                v = np.zeros(len(arrays["ix"]), np.int64)
+            setattr(self, k, v)
 
     def __len__(self):
         return len(self.ix)
@@ -46,7 +52,7 @@ class Particles:
         i = np.zeros(0, np.int64)
         f = np.zeros(0, np.float64)
         return Particles(ix=i, iy=i.copy(), iz=i.copy(), dx=f, dy=f.copy(), dz=f.copy(),
-                         ux=f.copy(), uy=f.copy(), uz=f.copy(), pid=i.copy())
+                         ux=f.copy(), uy=f.copy(), uz=f.copy(), pid=i.copy(), sp=i.copy())
 
     def take(self, idx):
         return Particles(**{k: getattr(self, k)[idx] for k in self.FIELDS})
@@ -55,6 +61,12 @@ class Particles:
     def concat(a, b):
         return Particles(**{k: np.concatenate([getattr(a, k), getattr(b, k)])
                             for k in Particles.FIELDS})
+
+    def weight_ratio(self, p):
+        """Macro-particle weight over the plasma weight p.w."""
+        if p.beam is None:
+            return np.ones(len(self))
+        return np.where(self.sp == 1, p.beam["rb"], 1.0)
 
     def cell(self, p):
         """Linear node/cell index (n * Ny + j) * Nx + i."""
@@ -161,3 +173,64 @@ def inject_batch(p, b):
     iz[low] = p.Nzp - 1
     dz[low] = 0.0
     return _make(p, i[sel], j[sel], iz, dx[sel], dy[sel], dz)
+
+
+def load_beam(p):
+    """Driver-beam macro-particles (species 1) in sample order.
+
+    Particle i takes four SplitMix64 uniforms u_k = uniform(key, 4 i + k) with
+    the beam's own stream key; the Box-Muller transform (Box & Muller 1958) of
+    (1 - u_0, u_1) gives the transverse normal pair, of (1 - u_2, u_3) the zeta
+    and gamma deviates:
+        x = x_c + sr r_1 cos(2 pi u_1),  y = y_c + sr r_1 sin(2 pi u_1),
+        zeta = zc + sz r_2 cos(2 pi u_3), gamma = gamma_0 + dgamma r_2 sin(2 pi u_3),
+    r = sqrt(-2 ln(1 - u)), axis at node (Nx/2, Ny/2), u_z = sqrt(gamma^2 - 1).
+    Positions wrap transversally; particles outside 0 <= zeta < (N_zeta - 1) h
+    are dropped.  Scalar FP64 arithmetic with the C library's log, cos, sin
+    and sqrt, one particle at a time, so that any implementation doing the
+    same operations gets the same bits."""
+    b = p.beam
+    if b is None:
+        return Particles.empty()
+    key = rng.stream_key(p.seed, 1)
+    Lx, Ly = p.Nx * p.hx, p.Ny * p.hy
+    xc, yc = (p.Nx // 2) * p.hx, (p.Ny // 2) * p.hy
+    zmax = (p.Nz - 1) * p.h
+    below1 = float(ONE_MINUS)
+    out = {k: [] for k in ("ix", "iy", "iz", "dx", "dy", "dz", "uz")}
+    u = rng.uniform(key, np.arange(4 * b["np"], dtype=np.uint64))
+    for i in range(b["np"]):
+        u0, u1, u2, u3 = 1.0 - float(u[4 * i]), float(u[4 * i + 1]), 1.0 - float(u[4 * i + 2]), float(u[4 * i + 3])
+        r1 = math.sqrt(-2.0 * math.log(u0))
+        r2 = math.sqrt(-2.0 * math.log(u2))
+        a1 = 2.0 * math.pi * u1
+        a2 = 2.0 * math.pi * u3
+        x = xc + b["sr"] * r1 * math.cos(a1)
+        y = yc + b["sr"] * r1 * math.sin(a1)
+        zeta = b["zc"] + b["sz"] * r2 * math.cos(a2)
+        gam = b["gamma"] + b["dgamma"] * r2 * math.sin(a2)
+        if not (0.0 <= zeta < zmax):
+            continue
+        x = math.fmod(x, Lx)
+        if x < 0.0:
+            x += Lx
+        y = math.fmod(y, Ly)
+        if y < 0.0:
+            y += Ly
+        fx, fy, fz = x / p.hx, y / p.hy, zeta / p.h
+        ix = min(math.floor(fx), p.Nx - 1)
+        iy = min(math.floor(fy), p.Ny - 1)
+        iz = math.floor(fz)
+        out["ix"].append(ix)
+        out["iy"].append(iy)
+        out["iz"].append(iz)
+        out["dx"].append(min(fx - ix, below1))
+        out["dy"].append(min(fy - iy, below1))
+        out["dz"].append(min(fz - iz, below1))
+        out["uz"].append(math.sqrt(gam * gam - 1.0) if gam > 1.0 else 0.0)
+    n = len(out["ix"])
+    i64 = lambda k: np.asarray(out[k], np.int64).reshape(n)
+    f64 = lambda k: np.asarray(out[k], np.float64).reshape(n)
+    return Particles(ix=i64("ix"), iy=i64("iy"), iz=i64("iz"), dx=f64("dx"), dy=f64("dy"),
+                     dz=f64("dz"), ux=np.zeros(n), uy=np.zeros(n), uz=f64("uz"),
+                     pid=np.zeros(n, np.int64), sp=np.ones(n, np.int64))

@@ -18,9 +18,9 @@ particles are dropped, new ones enter after all existing ones.
 import numpy as np
 
 from . import params as _params
-from .plasma import Particles, load_full_cells, inject_batch
+from .plasma import Particles, load_beam, load_full_cells, inject_batch
 from .push import push_and_move
-from .deposit import deposit, deposit_rho, continuity_residual
+from .deposit import G, deposit, deposit_rho, continuity_residual
 from .fields import (laser_state, real_fields, march, half_node_currents,
                      binomial_filter)
 
@@ -43,11 +43,18 @@ class Simulation:
         p = _params.from_config(cfg)
         self.p = p
         self.k = 0
-        P = Particles.concat(load_full_cells(p), inject_batch(p, 0))
+        # initial order before the tile sort: plasma load, driver beam, window
+        # batch 0
+        B = load_beam(p)
+        P = Particles.concat(Particles.concat(load_full_cells(p), B), inject_batch(p, 0))
         P.pid = np.arange(len(P), dtype=np.int64)
         self.next_pid = len(P)
         self.P = stable_sort(p, P)
-        self.state = laser_state(p)
+        rho_b = None
+        if len(B):
+            r = deposit_rho(p, B.ix, B.iy, B.iz, B.dx, B.dy, B.dz, B.weight_ratio(p))
+            rho_b = r[G:G + p.Nz]
+        self.state = laser_state(p, rho_b)
         self.F = real_fields(p, self.state)
         self.J = None
         self.diag = None
@@ -62,14 +69,15 @@ class Simulation:
     def step(self, diag=False):
         p = self.p
         P = self.P
+        wr = P.weight_ratio(p) if p.beam is not None else None
         if diag:
-            rho0 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
-        n_pushed = len(P)
+            rho0 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz, wr)
+        n_pushed = len(P) if wr is None else float(np.sum(wr))
         old, steps, vy = push_and_move(p, P, self.F)
         new = (P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
-        Jx, Jy, Jz = deposit(p, old, new, steps, vy)
+        Jx, Jy, Jz = deposit(p, old, new, steps, vy, wr)
         if diag:
-            rho1 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz)
+            rho1 = deposit_rho(p, P.ix, P.iy, P.iz, P.dx, P.dy, P.dz, wr)
         P = P.take(P.iz >= 0)
         B = inject_batch(p, self.k + 1)
         B.pid = self.next_pid + np.arange(len(B), dtype=np.int64)
@@ -100,7 +108,8 @@ class Simulation:
     def diagnostics(self, rho0=None, rho1=None, n_pushed=None):
         """FP64 diagnostics of the last step: particle count after the step;
         charge of the pushed particles (q w N) and on the grid after the move
-        (sum rho V, all particles before removal); field energy
+        (sum rho V, all particles before removal; beam particles count with
+        their weight); field energy
         1/2 sum (E^2 + B^2) V over the field nodes; continuity residual of
         the raw deposit; on-axis E_z."""
         p = self.p

@@ -469,6 +469,78 @@ __global__ void k_laser(T* out, const double* lon, const double* tra, int Nz, in
 }
 
 // zero a buffer of T
+// Field of the driver beam as a forward wave: per zeta node, phi^ = rho_f^ /
+// K^2, E_perp^ = -i k_perp phi^, R_perp += 2 E_perp^ (Nyquist rows and K = 0
+// give 0).  rho_f is the node charge after the current filter: P passes of
+// 1-2-1 along zeta (zero beyond the nodes 0 .. Nz-1, each pass) and the
+// transverse factor (cos^2(k_x h_x/2) cos^2(k_y h_y/2))^P.  rho_hat and R in
+// the [Nz][Ny][Nx/2] half-spectrum layout.
+template <typename T>
+__global__ void k_beam_R(const cplx<T>* rho_hat, cplx<T>* Rx, cplx<T>* Ry, int Nz, int Ny, int Nxh,
+                         double hx, double hy, int P) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nsp = (int64_t)Nz * Ny * Nxh;
+  if (idx >= nsp) return;
+  const int64_t pl = (int64_t)Ny * Nxh;
+  int i = (int)(idx % Nxh);
+  int j = (int)((idx / Nxh) % Ny);
+  int n = (int)(idx / pl);
+  if (Ny > 1 && j == Ny / 2) return;
+  double kx = 2.0 * M_PI * (double)i / ((double)(2 * Nxh) * hx);
+  int jj = j < (Ny + 1) / 2 ? j : j - Ny;
+  double ky = Ny > 1 ? 2.0 * M_PI * (double)jj / ((double)Ny * hy) : 0.0;
+  double K2 = kx * kx + ky * ky;
+  if (K2 == 0.0) return;
+  const int64_t m0 = idx - (int64_t)n * pl;   // this mode in plane 0
+  auto raw = [&](int m, double* re, double* im) {
+    if (m < 0 || m >= Nz) { *re = 0.0; *im = 0.0; return; }
+    cplx<T> v = rho_hat[(int64_t)m * pl + m0];
+    *re = (double)v.x; *im = (double)v.y;
+  };
+  auto pass1 = [&](int m, double* re, double* im) {
+    if (m < 0 || m >= Nz) { *re = 0.0; *im = 0.0; return; }
+    double a, b, c, d, e, f;
+    raw(m - 1, &a, &b); raw(m, &c, &d); raw(m + 1, &e, &f);
+    *re = 0.25 * (a + 2.0 * c + e);
+    *im = 0.25 * (b + 2.0 * d + f);
+  };
+  double pr, pi;
+  if (P == 0) {
+    raw(n, &pr, &pi);
+  } else if (P == 1) {
+    pass1(n, &pr, &pi);
+  } else {
+    double a, b, c, d, e, f;
+    pass1(n - 1, &a, &b); pass1(n, &c, &d); pass1(n + 1, &e, &f);
+    pr = 0.25 * (a + 2.0 * c + e);
+    pi = 0.25 * (b + 2.0 * d + f);
+  }
+  double cx = std::cos(0.5 * kx * hx), cy = Ny > 1 ? std::cos(0.5 * ky * hy) : 1.0;
+  double tr = 1.0;
+  for (int q = 0; q < P; ++q) tr *= (cx * cx) * (cy * cy);
+  pr *= tr / K2;
+  pi *= tr / K2;
+  // -2 i k (pr + i pi) = 2 k pi - 2 i k pr
+  Rx[idx].x += (T)(2.0 * kx * pi);
+  Rx[idx].y += (T)(-2.0 * kx * pr);
+  Ry[idx].x += (T)(2.0 * ky * pi);
+  Ry[idx].y += (T)(-2.0 * ky * pr);
+}
+
+// Lab current of charge moving at c from its node density: J_z(n + 1/2) =
+// (rho(n) + rho(n + 1)) / 2 on planes n + 2, n = -1 .. Nz - 1 (rho zero
+// outside the nodes 0 .. Nz - 1); Jz holds NPJ planes.
+template <typename T>
+__global__ void k_beam_jz(const T* rho, T* Jz, int Nz, int64_t nxy) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)(Nz + 1) * nxy) return;
+  int n = (int)(idx / nxy) - 1;
+  int64_t r = idx % nxy;
+  T a = n >= 0 ? rho[(int64_t)n * nxy + r] : (T)0;
+  T b = n + 1 < Nz ? rho[(int64_t)(n + 1) * nxy + r] : (T)0;
+  Jz[(int64_t)(n + 2) * nxy + r] = (T)0.5 * (a + b);
+}
+
 template <typename T>
 __global__ void k_fill(T* p, int64_t n, T v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

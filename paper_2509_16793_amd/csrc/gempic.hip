@@ -31,6 +31,14 @@ struct Dev {
     ptrs.push_back(p);
     return p;
   }
+  void free(void* p) {
+    for (size_t i = 0; i < ptrs.size(); ++i)
+      if (ptrs[i] == p) {
+        (void)hipFree(p);
+        ptrs.erase(ptrs.begin() + (long)i);
+        return;
+      }
+  }
   void release() {
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
@@ -48,6 +56,9 @@ struct gempic {
   int ppcx, ppcy, ppcz, quiet;
   uint64_t key;
   double L, hz, w, Tlas, zeta_c, waist;
+  int64_t nbeam;     // driver-beam particles created (0: no beam)
+  double wb;         // weight of a driver-beam particle
+  unsigned long long* bcount;   // diagnostics: beam particles in the buffer
   int64_t step;
   bool failed;
   std::string err;
@@ -125,6 +136,64 @@ static void scan_tiles(gempic* g, ChunkTab& t) {
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Driver beam sampled on the host in FP64.  Particle i draws four SplitMix64
+// uniforms u_k = uniform(key, 4 i + k); the Box-Muller transform of
+// (1 - u_0, u_1) gives the transverse pair, of (1 - u_2, u_3) the zeta and
+// gamma deviates.  Positions wrap transversally; particles outside the field
+// box in zeta, 0 <= zeta < (Nz - 1) h, are not created.
+struct HostBeam {
+  int64_t n = 0;
+  std::vector<int32_t> cell, tile;
+  std::vector<double> off;   // [3][n]
+  std::vector<double> uz;
+  std::vector<int64_t> dst;
+};
+
+static void sample_beam(const gempic* g, HostBeam* hb) {
+  const Geom& G = g->g;
+  const gempic_config* c = &g->cfg;
+  double lu = c->length_unit;
+  uint64_t key = sm_mix(c->seed ^ (1ull << 56));
+  double sr = c->beam_sr * lu, sz = c->beam_sz * lu;
+  double zc = std::isnan(c->beam_zc) ? (double)(G.Nz - 1) * G.h - 6.0 * sz : c->beam_zc * lu;
+  double Lx = (double)G.Nx * G.hx, Ly = (double)G.Ny * G.hy, zmax = (double)(G.Nz - 1) * G.h;
+  double xc = (double)(G.Nx / 2) * G.hx, yc = (double)(G.Ny / 2) * G.hy;
+  const double below1 = 0x1.fffffffffffffp-1;
+  std::vector<double> ox, oy, oz;
+  for (int64_t i = 0; i < c->beam_np; ++i) {
+    uint64_t k = 4ull * (uint64_t)i;
+    double u0 = 1.0 - sm_uniform(key, k), u1 = sm_uniform(key, k + 1);
+    double u2 = 1.0 - sm_uniform(key, k + 2), u3 = sm_uniform(key, k + 3);
+    double r1 = std::sqrt(-2.0 * std::log(u0)), r2 = std::sqrt(-2.0 * std::log(u2));
+    double a1 = 2.0 * M_PI * u1, a2 = 2.0 * M_PI * u3;
+    double x = xc + sr * r1 * std::cos(a1);
+    double y = yc + sr * r1 * std::sin(a1);
+    double zeta = zc + sz * r2 * std::cos(a2);
+    double gam = c->beam_gamma + c->beam_dgamma * r2 * std::sin(a2);
+    if (!(zeta >= 0.0 && zeta < zmax)) continue;
+    x = std::fmod(x, Lx);
+    if (x < 0.0) x += Lx;
+    y = std::fmod(y, Ly);
+    if (y < 0.0) y += Ly;
+    double fx = x / G.hx, fy = y / G.hy, fz = zeta / G.h;
+    int ix = std::min((int)std::floor(fx), G.Nx - 1);
+    int iy = std::min((int)std::floor(fy), G.Ny - 1);
+    int iz = (int)std::floor(fz);
+    hb->cell.push_back((iz * G.Ny + iy) * G.Nx + ix);
+    hb->tile.push_back(((iz / G.Tz) * G.nTy + iy / G.Ty) * G.nTx + ix / G.Tx);
+    ox.push_back(std::min(fx - (double)ix, below1));
+    oy.push_back(std::min(fy - (double)iy, below1));
+    oz.push_back(std::min(fz - (double)iz, below1));
+    hb->uz.push_back(gam > 1.0 ? std::sqrt(gam * gam - 1.0) : 0.0);
+  }
+  hb->n = (int64_t)hb->cell.size();
+  hb->off.reserve(3 * hb->n);
+  hb->off.insert(hb->off.end(), ox.begin(), ox.end());
+  hb->off.insert(hb->off.end(), oy.begin(), oy.end());
+  hb->off.insert(hb->off.end(), oz.begin(), oz.end());
+}
+
 template <typename T>
 struct Impl {
   using C = cplx<T>;
@@ -349,6 +418,9 @@ struct Impl {
                            std::max(std::fabs((double)a.cz) + std::fabs((double)a.crho),
                                     std::fabs((double)a.cjy)));
     cmax = std::max(cmax, std::fabs((double)a.crho));
+    // driver-beam particles carry rb times the plasma weight
+    a.rb = (T)(g->wb > 0 ? g->wb / g->w : 1.0);
+    if (g->wb > 0) cmax *= std::max(1.0, g->wb / g->w);
     double lim = sizeof(T) == 4 ? std::ldexp(1.0, 30) : std::ldexp(1.0, 61) / (double)GP_CHUNK;
     double sc = cmax > 0 ? lim / (cmax * 1.01) : 1.0;
     int e2 = (int)std::floor(std::log2(sc));
@@ -386,8 +458,15 @@ struct Impl {
   static void push_tile(gempic* g, const PushArgs<T>& a, PartPtrs<T> P, bool rho) {
     unsigned nb = push_blocks(a);
     constexpr int NTHR = TZ == 8 ? 512 : 256;
-    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR><<<nb, NTHR, 0, g->s>>>(a, P);
-    else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR><<<nb, NTHR, 0, g->s>>>(a, P);
+    if constexpr (DIM == 3) {
+      if (g->cfg.beam_np > 0) {
+        if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, true><<<nb, NTHR, 0, g->s>>>(a, P);
+        else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, true><<<nb, NTHR, 0, g->s>>>(a, P);
+        return;
+      }
+    }
+    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, false><<<nb, NTHR, 0, g->s>>>(a, P);
+    else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, false><<<nb, NTHR, 0, g->s>>>(a, P);
   }
 
   static void launch_push(gempic* g) {
@@ -466,6 +545,26 @@ struct Impl {
         tot += n;
       }
     }
+    // driver beam: sampled on the host, placed behind the plasma particles of
+    // its tiles (sample order within a tile)
+    HostBeam hb;
+    if (g->cfg.beam_np > 0) {
+      sample_beam(g, &hb);
+      std::vector<int64_t> bcnt(G.NT, 0);
+      for (int64_t i = 0; i < hb.n; ++i) bcnt[hb.tile[i]] += 1;
+      tot = 0;
+      for (int t = 0; t < G.NT; ++t) {
+        base[t] = tot;
+        tot += cnt[t] + bcnt[t];
+      }
+      std::vector<int64_t> fill_(G.NT, 0);
+      hb.dst.resize(hb.n);
+      for (int64_t i = 0; i < hb.n; ++i) {
+        int t = hb.tile[i];
+        hb.dst[i] = base[t] + cnt[t] + fill_[t]++;
+      }
+      for (int t = 0; t < G.NT; ++t) cnt[t] += bcnt[t];
+    }
     if (tot > g->capacity) return fail(g, GEMPIC_EINVAL, "capacity too small for the initial load");
     HIPCHK(g, hipMemcpyAsync(g->tile_count, cnt.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
     HIPCHK(g, hipMemcpyAsync(g->tile_base, base.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
@@ -477,6 +576,27 @@ struct Impl {
       la.key = g->key;
       la.tile_base = g->tile_base;
       k_load_full<T><<<G.NT, 256, 0, g->s>>>(la, parts(g, g->cur));
+    }
+    BeamArgs ba{};
+    if (hb.n > 0) {
+      int64_t n = hb.n;
+      ba.n = n;
+      int32_t* dc = (int32_t*)g->dev.alloc(n * 4);
+      double* doff = (double*)g->dev.alloc(3 * n * 8);
+      double* duz = (double*)g->dev.alloc(n * 8);
+      int64_t* ddst = (int64_t*)g->dev.alloc(n * 8);
+      if (!dc || !doff || !duz || !ddst) return fail(g, GEMPIC_ENOMEM, "beam staging buffers");
+      HIPCHK(g, hipMemcpyAsync(dc, hb.cell.data(), n * 4, hipMemcpyHostToDevice, g->s));
+      HIPCHK(g, hipMemcpyAsync(doff, hb.off.data(), 3 * n * 8, hipMemcpyHostToDevice, g->s));
+      HIPCHK(g, hipMemcpyAsync(duz, hb.uz.data(), n * 8, hipMemcpyHostToDevice, g->s));
+      HIPCHK(g, hipMemcpyAsync(ddst, hb.dst.data(), n * 8, hipMemcpyHostToDevice, g->s));
+      ba.cell = dc;
+      ba.off = doff;
+      ba.uz = duz;
+      ba.dst = ddst;
+      ba.id0 = tot - n;
+      k_place_beam<T><<<nblk(n, 256), 256, 0, g->s>>>(ba, parts(g, g->cur), G.dims);
+      g->nbeam = n;
     }
     ChunkTab& t0 = g->ct[g->ctc];
     scan_tiles(g, t0);
@@ -511,7 +631,26 @@ struct Impl {
       k_laser<T><<<nblk((int64_t)G.Nz * nxy, 256), 256, 0, g->s>>>((T*)g->J[0], dl, dt, G.Nz, nxy);
       fft_fwd(g, (const T*)g->J[0], (C*)g->st[g->cfg.pol == 0 ? 0 : 1], G.Nz);
     }
-    field_update(g, false, (T)0);
+    if (hb.n > 0) {
+      // the bunch's own field: charge on the nodes, transverse Poisson solve
+      // per zeta node, R_perp += 2 E_perp
+      int64_t nf = (int64_t)G.Nz * nxy;
+      fill(g, g->J[1], nf);
+      k_beam_rho<T><<<nblk(hb.n, 256), 256, 0, g->s>>>(ba, G, -g->wb / G.V, (T*)g->J[1]);
+      fft_fwd(g, (const T*)g->J[1], (C*)g->outs[0], G.Nz);
+      k_beam_R<T><<<nblk(nsp, 256), 256, 0, g->s>>>((const C*)g->outs[0], (C*)g->st[0], (C*)g->st[1], G.Nz,
+                                                     G.Ny, G.Nxh, G.hx, G.hy, G.P);
+      // its current J_z = rhobar enters the consistency march
+      int64_t nJ = (int64_t)G.NPJ * nxy;
+      fill(g, g->J[0], nJ);
+      fill(g, g->J[2], nJ);
+      k_beam_jz<T><<<nblk((int64_t)(G.Nz + 1) * nxy, 256), 256, 0, g->s>>>((const T*)g->J[1], (T*)g->J[2],
+                                                                           G.Nz, nxy);
+      fill(g, g->J[1], nJ);
+      HIPCHK(g, hipStreamSynchronize(g->s));
+      for (void* p : {(void*)ba.cell, (void*)ba.off, (void*)ba.uz, (void*)ba.dst}) g->dev.free(p);
+    }
+    field_update(g, hb.n > 0, (T)0);
     int64_t nJ = (int64_t)G.NPJ * nxy;
     for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
     if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
@@ -554,6 +693,15 @@ struct Impl {
     d->charge_grid = g->cfg.deposit_rho ? res[1] * G.V : 0.0;
     d->continuity_rel = g->cfg.deposit_rho && res[3] > 0 ? std::sqrt(res[2]) / std::sqrt(res[3]) : 0.0;
     d->charge_particles = G.qw * (double)np;
+    if (g->bcount) {
+      // beam particles counted in the buffer after the step
+      unsigned long long nb = 0;
+      HIPCHK(g, hipMemsetAsync(g->bcount, 0, 8, g->s));
+      k_count_beam<<<256, 256, 0, g->s>>>((const int32_t*)g->part[g->cur][0], g->total, g->bcount);
+      HIPCHK(g, hipMemcpyAsync(&nb, g->bcount, 8, hipMemcpyDeviceToHost, g->s));
+      HIPCHK(g, hipStreamSynchronize(g->s));
+      d->charge_particles = G.qw * (double)(np - (int64_t)nb) - g->wb * (double)nb;
+    }
     return GEMPIC_OK;
   }
 };
@@ -618,7 +766,17 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->nTz = (G->Nzp + G->Tz - 1) / G->Tz;
   G->NT = G->nTx * G->nTy * G->nTz;
   G->Nxh = G->Nx / 2;
-  if ((int64_t)G->Nzp * G->Ny * G->Nx >= (1ll << 31)) { *why = "grid too large for int32 cells"; return GEMPIC_EINVAL; }
+  if ((int64_t)G->Nzp * G->Ny * G->Nx >= (1ll << 30)) { *why = "grid too large: cells must stay below 2^30"; return GEMPIC_EINVAL; }
+  if (c->beam_np < 0) { *why = "beam_np must be >= 0"; return GEMPIC_EINVAL; }
+  if (c->beam_np > 0) {
+    if (c->dims != 3) { *why = "a driver beam needs dims = 3"; return GEMPIC_EINVAL; }
+    if (!(c->n_e > 0)) { *why = "a driver beam needs a plasma (n_e > 0)"; return GEMPIC_EINVAL; }
+    if (!(c->beam_n > 0 && c->beam_sr > 0 && c->beam_sz > 0 && c->beam_gamma > 1 && c->beam_dgamma >= 0)) {
+      *why = "beam needs beam_n, beam_sr, beam_sz > 0, beam_gamma > 1, beam_dgamma >= 0";
+      return GEMPIC_EINVAL;
+    }
+    if (c->beam_np > (1ll << 28)) { *why = "beam_np too large"; return GEMPIC_EINVAL; }
+  }
   if ((int64_t)G->NT > (int64_t)SCAN_PER * SCAN_MAXB) { *why = "too many tiles"; return GEMPIC_EINVAL; }
   return GEMPIC_OK;
 }
@@ -675,6 +833,12 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   int ppc = g->ppcx * g->ppcy * g->ppcz;
   double hy_eff = G.dims == 3 ? G.hy : 1.0;
   g->w = cfg->n_e * G.hx * hy_eff * G.h / (double)ppc;
+  // driver beam: the bunch holds beam_n (2 pi)^(3/2) sr^2 sz electrons, shared
+  // equally by beam_np macro-particles
+  g->nbeam = 0;
+  g->wb = cfg->beam_np > 0 ? cfg->beam_n * std::pow(2.0 * M_PI, 1.5) * (cfg->beam_sr * lu) *
+                                 (cfg->beam_sr * lu) * (cfg->beam_sz * lu) / (double)cfg->beam_np
+                           : 0.0;
   G.qw = -1.0 * g->w;
   G.V = G.hx * hy_eff * G.h;
   g->L = (double)(G.Nz - 1 + G.ext) * G.h;
@@ -695,7 +859,7 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   // capacities
   int64_t ncell_p = (int64_t)G.Nzp * G.Ny * G.Nx;
   int64_t n0 = cfg->n_e > 0 ? ncell_p * ppc : 0;
-  g->capacity = n0 + n0 / 4 + 4096;
+  g->capacity = n0 + n0 / 4 + 4096 + cfg->beam_np;
   g->max_nm = (int64_t)std::ceil(G.dtau * g->ppcz / G.h) + 5;
   g->stage_per_tile = g->max_nm * G.Ty * G.Tx * g->ppcx * g->ppcy;
   g->max_chunks = (int)(G.NT + g->capacity / GP_CHUNK + 1);
@@ -737,6 +901,7 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   g->inj_total = (int64_t*)A(8);
   g->pushed = (int64_t*)A(8);
   g->err_dev = (int*)A(sizeof(int));
+  g->bcount = cfg->beam_np > 0 ? (unsigned long long*)A(8) : nullptr;
   int64_t nf = (int64_t)G.Nz * G.Ny * G.Nx;
   int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
   int64_t nsp = (int64_t)G.Nz * G.Ny * G.Nxh;
@@ -891,6 +1056,10 @@ int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void*
   int64_t maxid = -1;
   for (size_t i = 0; i < count; ++i) {
     int c = cell[i];
+    if (c >= 0 && (c & GEMPIC_BEAM_BIT)) {
+      if (g->cfg.beam_np <= 0) return fail(g, GEMPIC_EINVAL, "beam particle on a handle without a beam");
+      c &= ~GEMPIC_BEAM_BIT;
+    }
     if (c < 0 || c >= G.Nzp * G.Ny * G.Nx) return fail(g, GEMPIC_EINVAL, "cell out of range");
     int ix = c % G.Nx, r = c / G.Nx, iy = r % G.Ny, iz = r / G.Ny;
     int t = ((iz / G.Tz) * G.nTy + iy / G.Ty) * G.nTx + ix / G.Tx;

@@ -97,6 +97,71 @@ __global__ void k_load_full(LoadArgs a, PartPtrs<T> P) {
 }
 
 // ---------------------------------------------------------------------------
+// Driver beam (sampled on the host in FP64, already in tile order): particle
+// i goes to slot dst[i]; its cell word carries GEMPIC_BEAM_BIT.
+struct BeamArgs {
+  int64_t n;
+  const int32_t* cell;
+  const double* off;     // [3][n]
+  const double* uz;
+  const int64_t* dst;
+  int64_t id0;           // id of beam particle 0
+};
+
+template <typename T>
+__global__ void k_place_beam(BeamArgs a, PartPtrs<T> P, int dims) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int64_t o = a.dst[i];
+  P.cell[o] = a.cell[i] | GEMPIC_BEAM_BIT;
+  P.ox[o] = store_offset<T>(a.off[i]);
+  if (dims == 3) P.oy[o] = store_offset<T>(a.off[a.n + i]);
+  P.oz[o] = store_offset<T>(a.off[2 * a.n + i]);
+  P.ux[o] = (T)0;
+  P.uy[o] = (T)0;
+  P.uz[o] = (T)a.uz[i];
+  if (P.id) P.id[o] = a.id0 + i;
+}
+
+// Charge density q w_b / V of the beam on the field nodes n < Nz (linear
+// weights from the FP64 offsets); rho is [Nz][Ny][Nx].
+template <typename T>
+__global__ void k_beam_rho(BeamArgs a, Geom g, double qv, T* rho) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int c = a.cell[i];
+  int ix = c & (g.Nx - 1), iy = (c >> g.lnx) & (g.Ny - 1), iz = c >> (g.lnx + g.lny);
+  double dx = a.off[i], dy = a.off[a.n + i], dz = a.off[2 * a.n + i];
+  const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
+  for (int cc = 0; cc < 2; ++cc) {
+    int z = iz + cc;
+    if (z >= g.Nz) continue;
+    for (int b = 0; b < 2; ++b)
+      for (int aa = 0; aa < 2; ++aa) {
+        int x = (ix + aa) & (g.Nx - 1), y = (iy + b) & (g.Ny - 1);
+        atomicAdd(rho + ((int64_t)z * g.Ny + y) * g.Nx + x, (T)(qv * ((wx[aa] * wy[b]) * wz[cc])));
+      }
+  }
+}
+
+// Driver-beam particles (cell words with GEMPIC_BEAM_BIT) among the first n.
+__global__ __launch_bounds__(256) void k_count_beam(const int32_t* cell, const int64_t* n, unsigned long long* out) {
+  __shared__ unsigned long long s;
+  if (threadIdx.x == 0) s = 0;
+  __syncthreads();
+  const int64_t N = *n;
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    int w = cell[i];
+    c += (w >= 0 && (w & GEMPIC_BEAM_BIT)) ? 1ull : 0ull;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&s, c);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, s);
+}
+
+// ---------------------------------------------------------------------------
 // Window batch b: lattice particles with lo <= z_m < hi (no lower bound for
 // b = 0) among sub-rows m_lo .. m_hi, placed at zeta = z_m - b dtau in the
 // entry cell.  One work-group per transverse tile; candidates in
@@ -246,6 +311,7 @@ __global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
       if (cell < 0) {
         code = CODE_REMOVED;
       } else {
+        cell &= ~GEMPIC_BEAM_BIT;
         // power-of-two grid and tile sizes: shifts and masks
         int ix = cell & (g.Nx - 1);
         int iy = (cell >> g.lnx) & (g.Ny - 1);

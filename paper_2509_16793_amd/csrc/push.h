@@ -42,6 +42,7 @@ struct PushArgs {
   T cx, cy, cz;        // -q w / (dtau hy h), -q w / (dtau hx h), -q w / (dtau hx hy) (2-D: hy = 1)
   T cjy;               // 2-D out-of-plane: q w / (hx h)
   T crho;              // q w / V
+  T rb;                // weight of a driver-beam particle over the plasma weight
   T fscale, finv;      // fixed-point scale of the LDS tile (power of two) and its inverse
   const int64_t* tile_base;   // [NT] first particle of each tile
   const int64_t* tile_count;  // [NT] particles of each tile
@@ -153,7 +154,9 @@ GP_DEV PLoad<T> load_row(const PartPtrs<T>& P, int base, int n, unsigned lane) {
   return s;
 }
 
-template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR>
+// SPEC: cell words may carry GEMPIC_BEAM_BIT (driver-beam particles, weight rb
+// times the plasma weight); the bit is kept through the move.
+template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR, bool SPEC>
 __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
   constexpr int FX = TX + 1, FY = DIM == 3 ? TY + 1 : 1, FZ = TZ + 1;
   constexpr int FN = FX * FY * FZ;
@@ -254,9 +257,10 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
       nxt = load_row<T, DIM>(P, nb, (same ? p1 : np1) - nb, lane);
     }
     int lx = 0, ly = 0, lz = 0, kx = 0, ky = 0, kz = 0;
+    const int spec = SPEC ? (cur.cell & GEMPIC_BEAM_BIT) : 0;
     T dx0 = (T)0, dy0 = (T)0, dz0 = (T)0, dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
     if (valid) {
-      int cell = cur.cell;
+      int cell = cur.cell ^ spec;
       int ix = cell & mx;
       int iy = (cell >> g.lnx) & my;
       int iz = cell >> (g.lnx + g.lny);
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           int niy = (iy + ky) & my;
           int niz = iz + kz;
           const int nr = p1 - row;
-          row_st((niz * g.Ny + niy) * g.Nx + nix, P.cell, row, nr, lane);
+          row_st(((niz * g.Ny + niy) * g.Nx + nix) | spec, P.cell, row, nr, lane);
           row_st(dx1, P.ox, row, nr, lane);
           if (DIM == 3) row_st(dy1, P.oy, row, nr, lane);
           row_st(dz1, P.oz, row, nr, lane);
@@ -396,8 +400,9 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
       A* sJx = sJ + ((jz0 - 1) * JY + jy0) * JX + jx0;
       A* sJy = sJx + (JZ - 1) * JP;
       A* sJz = sJx + 2 * (JZ - 1) * JP;  // half-node plane base_z - 1
-      T qr = (T)0.25 * a.crho * fs;
-      T cx = a.cx * fs, cy = a.cy * fs, cz = a.cz * fs;
+      const T wr = SPEC && spec ? a.rb : (T)1;
+      T qr = (T)0.25 * a.crho * fs * wr;
+      T cx = a.cx * fs * wr, cy = a.cy * fs * wr, cz = a.cz * fs * wr;
       if (DIM == 3) {
         // Transverse window: 3 x 3 nodes when a particle of the wave crosses a
         // transverse cell boundary, taken one node at a time (weights
@@ -487,7 +492,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           add(&sJx[cc * JX + 0], px[0] * Az[cc]);
           add(&sJx[cc * JX + 1], px[1] * Az[cc]);
         }
-        T cyv = a.cjy * fs * vy;
+        T cyv = a.cjy * fs * wr * vy;
 #pragma unroll
         for (int aa = 0; aa < 3; ++aa)
 #pragma unroll
@@ -513,7 +518,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
         // charge before and after the move; rho tile origin (x0-1, y0-1, node z0-1)
         A* sR0 = sJ + JN;
         A* sR1 = sR0 + RN;
-        T cr = a.crho * fs;
+        T cr = a.crho * fs * wr;
         constexpr int oy = DIM == 3 ? 1 : 0;
         T w0x[2] = {(T)1 - dx0, dx0}, w0y[2] = {(T)1 - dy0, dy0}, w0z[2] = {(T)1 - dz0, dz0};
         T w1x[2] = {(T)1 - dx1, dx1}, w1y[2] = {(T)1 - dy1, dy1}, w1z[2] = {(T)1 - dz1, dz1};

@@ -17,7 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libgempic.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
+BEAM_BIT = 1 << 30
 FP64, FP32_CELL = 0, 1
 EX, EY, EZ, BX, BY, BZ, JX, JY, JZ, RHO = (1 << i for i in range(10))
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
@@ -41,7 +42,10 @@ class gempic_config(ctypes.Structure):
         ("ppc", ctypes.c_int32 * 3), ("load", ctypes.c_int32), ("a0", ctypes.c_double),
         ("waist", ctypes.c_double), ("fwhm", ctypes.c_double), ("zeta_c", ctypes.c_double),
         ("pol", ctypes.c_int32), ("seed", ctypes.c_uint64), ("filter_passes", ctypes.c_int32),
-        ("track_ids", ctypes.c_int32), ("deposit_rho", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("track_ids", ctypes.c_int32), ("deposit_rho", ctypes.c_int32),
+        ("beam_n", ctypes.c_double), ("beam_sr", ctypes.c_double), ("beam_sz", ctypes.c_double),
+        ("beam_zc", ctypes.c_double), ("beam_gamma", ctypes.c_double), ("beam_dgamma", ctypes.c_double),
+        ("beam_np", ctypes.c_int64), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -145,6 +149,15 @@ def make_config(cfg, stream=None, track_ids=False, deposit_rho=False):
     c.filter_passes = int(cfg.get("filter_passes", 1))
     c.track_ids = int(bool(track_ids))
     c.deposit_rho = int(bool(deposit_rho))
+    b = cfg.get("beam") or {}
+    c.beam_n = float(b.get("n", 0.0))
+    c.beam_sr = float(b.get("sr", 0.0))
+    c.beam_sz = float(b.get("sz", 0.0))
+    zb = b.get("zc", None)
+    c.beam_zc = math.nan if zb is None else float(zb)
+    c.beam_gamma = float(b.get("gamma", 1.0))
+    c.beam_dgamma = float(b.get("dgamma", 0.0))
+    c.beam_np = int(b.get("np", 0))
     c.stream = stream
     return c
 

@@ -9,9 +9,12 @@ SPEC_NAMES = ("Rx", "Ry", "Lx", "Ly", "Ez", "Bz")
 FIELDS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
 
+BEAM_BIT = 1 << 30   # the library's marker of driver-beam particles in a cell word
+
+
 def oracle_particles(o):
     P, p = o.P, o.p
-    cell = ((P.iz * p.Ny + P.iy) * p.Nx + P.ix).astype(np.int64)
+    cell = ((P.iz * p.Ny + P.iy) * p.Nx + P.ix).astype(np.int64) | (P.sp.astype(np.int64) << 30)
     return cell, np.stack([P.dx, P.dy, P.dz]), np.stack([P.ux, P.uy, P.uz]), P.pid
 
 
@@ -29,13 +32,15 @@ def upload(gpu, o, with_fields=False):
 
 
 def gpu_particles_to_oracle(p, d, dtype=np.float64):
-    cell = d["cell"].astype(np.int64)
+    word = d["cell"].astype(np.int64)
+    sp = (word >> 30) & 1
+    cell = word & ~BEAM_BIT
     ix = cell % p.Nx
     iy = (cell // p.Nx) % p.Ny
     iz = cell // (p.Nx * p.Ny)
     off, u = d["off"].astype(dtype), d["u"].astype(dtype)
     return Particles(ix=ix, iy=iy, iz=iz, dx=off[0], dy=off[1], dz=off[2], ux=u[0], uy=u[1],
-                     uz=u[2], pid=d.get("id", np.zeros(len(cell), np.int64)))
+                     uz=u[2], pid=d.get("id", np.zeros(len(cell), np.int64)), sp=sp)
 
 
 def rel_errors(ref, got, floor=1e-6):

@@ -1,0 +1,75 @@
+"""Parity of the driver-beam (PWFA) path of the HIP library with the FP64
+oracle, on a small plasma-unit case (32 x 32 x 64 cells, 1 ppc, a 3000-particle
+Gaussian driver of peak density 10 n_e at gamma = 2000).
+
+Bars: the host-sampled beam, the load and the stable sort bit for bit
+(cells, species bit, offsets, momenta, ids); fields within relative L2 1e-10
+in FP64 (initial beam field and after steps) and 2e-4 in FP32; charge
+conservation to roundoff; beam particles counted with their own weight."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.sim import Simulation
+from paper_2509_16793_amd.gempic import BEAM_BIT, Sim
+from parity import oracle_particles, rel_errors, oracle_fields, oracle_currents
+
+pytestmark = pytest.mark.gpu
+
+
+def _exact(o, g):
+    cell, off, u, pid = oracle_particles(o)
+    d = g.particles(ids=True)
+    assert len(d["cell"]) == len(cell)
+    assert np.array_equal(d["id"], pid), "sort permutation differs"
+    assert np.array_equal(d["cell"].astype(np.int64), cell), "cells / species differ"
+    return d, off, u
+
+
+@pytest.mark.parametrize("tile", [(8, 8, 8), (8, 8, 4)], ids=["t888", "t884"])
+def test_pwfa_initial_state(tile):
+    cfg = workloads.pwfa_small(tile=tile)
+    o = Simulation(cfg)
+    g = Sim(cfg, track_ids=True)
+    d, off, u = _exact(o, g)
+    assert int(np.count_nonzero(d["cell"] & BEAM_BIT)) == cfg["beam"]["np"]
+    for a in range(3):
+        assert np.array_equal(d["off"][a], off[a]), f"offset axis {a}"
+        assert np.array_equal(d["u"][a], u[a]), f"momentum axis {a}"
+    err = rel_errors(oracle_fields(o), g.fields())
+    assert max(err.values()) < 1e-10, err
+
+
+@pytest.mark.parametrize("tile", [(8, 8, 8), (8, 8, 4)], ids=["t888", "t884"])
+def test_pwfa_fp64_steps(tile):
+    cfg = workloads.pwfa_small(tile=tile)
+    o = Simulation(cfg)
+    g = Sim(cfg, track_ids=True, deposit_rho=True)
+    o.run(3)
+    o.step(diag=True)
+    dg = g.step(4, diag=True)
+    err = rel_errors(oracle_fields(o), g.fields())
+    assert max(err.values()) < 1e-10, err
+    # after the first step the two sides gather from fields equal to ~1e-15
+    # (current sums in another order), so offsets and momenta agree to
+    # roundoff, not bit for bit; cells and the permutation stay exact
+    d, off, u = _exact(o, g)
+    assert np.max(np.abs(d["off"] - off)) < 1e-9
+    assert np.max(np.abs(d["u"] - u)) < 1e-9 * max(1.0, np.abs(u).max())
+    J = g.fields(("Jx", "Jy", "Jz"))
+    err = rel_errors(oracle_currents(o, g.NPJ), J)
+    assert max(err.values()) < 1e-10, err
+    assert dg["continuity_rel"] < 1e-12
+    assert abs(dg["charge_grid"] - o.diag["charge_grid"]) < 1e-12 * abs(o.diag["charge_grid"])
+    assert abs(dg["charge_particles"] - dg["charge_grid"]) < 1e-12 * abs(dg["charge_grid"])
+
+
+def test_pwfa_fp32_steps():
+    o = Simulation(workloads.pwfa_small()).run(8)
+    g = Sim(workloads.pwfa_small("fp32"))
+    g.step(8)
+    # B_z is ~1e-3 of the transverse fields here: FP32 roundoff of the large
+    # fields (~1e-7 of them) is ~1e-4 of it, so components below 1e-3 of the
+    # largest are measured against the largest
+    err = rel_errors(oracle_fields(o), g.fields(), floor=1e-3)
+    assert max(err.values()) < 2e-4, err

@@ -58,13 +58,26 @@ def precision_study(mode):
 
 def pwfa3d_fp32():
     """3-D PWFA in plasma units: 512 x 512 x 1024, dx = dy = 0.1, dzeta = 0.05,
-    n_e = 1, 4 ppc, Gaussian driver sigma_r = 0.5, sigma_zeta = 1, peak 10 n_e,
-    gamma = 2000 with 0.1 % spread, 1e7 macro-particles; 500 steps."""
+    n_e = 1, 4 ppc (1,073,741,824 electrons at load), Gaussian driver
+    sigma_r = 0.5, sigma_zeta = 1, peak 10 n_e, gamma = 2000 with 0.1 % spread,
+    1e7 macro-particles; 500 steps; FP32 cell + offset, 8 x 8 x 4 tiles."""
     return _base(dims=3, n=[512, 512, 1024], d=[0.1, 0.1, 0.05], length_unit=1.0,
-                 precision="fp32", tile=[8, 8, 8], n_e=1.0, ppc=[1, 2, 2],
-                 steps=500,
-                 beam=dict(n_peak=10.0, sigma_r=0.5, sigma_z=1.0, gamma=2000.0,
+                 precision="fp32", tile=[8, 8, 4], n_e=1.0, ppc=[1, 2, 2],
+                 steps=500, a0=0.0,
+                 beam=dict(n=10.0, sr=0.5, sz=1.0, zc=None, gamma=2000.0,
                            dgamma=2.0, np=10_000_000))
+
+
+def pwfa_small(precision="fp64", n=(32, 32, 64), tile=(8, 8, 8), ppc=(1, 1, 1),
+               np_beam=3000, seed=5, steps=4):
+    """Small PWFA case for parity tests: the plasma-unit physics of pwfa3d_fp32
+    with a shorter, narrower driver (sigma_r = sigma_zeta = 0.3) that fits the
+    small box."""
+    return _base(dims=3, n=list(n), d=[0.1, 0.1, 0.05], length_unit=1.0,
+                 precision=precision, tile=list(tile), n_e=1.0, ppc=list(ppc),
+                 steps=steps, a0=0.0, seed=seed,
+                 beam=dict(n=10.0, sr=0.3, sz=0.3, zc=None, gamma=2000.0,
+                           dgamma=2.0, np=np_beam))
 
 
 def denoiser_lwfa(ppc=(1, 1, 1)):
