@@ -6,6 +6,9 @@ dzeta = 0.05 (laser wavelengths), n_e = 0.001 n_c, 2 particles per cell
 particles -- synthetic and seeded.  One step = gather + push + deposit, stable
 sort + window injection, and the field update (FFT, march, inverse FFT).
 
+--workload pwfa runs the PWFA setup instead (512 x 512 x 1024 cells, 4 ppc,
+1e7-particle driver, plasma units).
+
 Prints one JSON line.  value = particle updates per second of the
 gather + push + deposit kernel (HIP events around its launches, on the stream
 the library runs on); ms_per_step = wall time per whole step over the timed
@@ -29,6 +32,13 @@ METRIC = "particle updates/s (gather+push+deposit), % HBM roofline; 1ppc+CNN vs 
 # valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {"push_h_sha256_prefix": "1f37f3e26fbf2dfd", "bytes_per_launch": 5.577e9}
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "lwfa": "lwfa3d_fp32: 3-D LWFA 256x256x512, dx=dy=0.4, dzeta=0.05 (lambda_L), n_e=0.001 n_c, "
+            "2 ppc, a0=2, waist 8, FWHM 8, FP32 cell+offset particles, 8x8x4 tiles",
+    "pwfa": "pwfa3d_fp32: 3-D PWFA 512x512x1024, dx=dy=0.1, dzeta=0.05 (c/omega_p), n_e=1, 4 ppc, "
+            "Gaussian driver sigma_r=0.5, sigma_zeta=1, peak 10 n_e, gamma 2000 +- 0.1 %, "
+            "1e7 macro-particles, FP32 cell+offset particles, 8x8x4 tiles",
+}
 STATE_BYTES = 28          # int32 cell + 3 x FP32 offset + 3 x FP32 momentum
 
 
@@ -38,19 +48,28 @@ def algorithmic_bytes_per_update(ppc):
     return 2 * STATE_BYTES + (24.0 + 12.0) / ppc
 
 
-def cpu_baseline(seconds_budget=30.0):
-    """FP64 oracle gather + push + deposit on a 32 x 32 x 512 transverse crop of
-    the workload (same steps, density, ppc; laser waist scaled to the crop)."""
+def cpu_baseline(workload="lwfa", seconds_budget=30.0):
+    """FP64 oracle gather + push + deposit on a transverse crop of the workload:
+    LWFA 32 x 32 x 512 cells (same steps, density, ppc; laser waist scaled to
+    the crop); PWFA 16 x 16 x 512 cells of its plasma (same steps, density,
+    ppc; the driver is left out: its 1e7 particles do not fit a crop)."""
     import numpy as np
     import workloads
     from oracle.sim import Simulation
     from oracle.push import push_and_move
     from oracle.deposit import deposit
 
-    cfg = workloads.lwfa3d_fp32()
-    cfg["n"] = [32, 32, 512]
+    if workload == "pwfa":
+        cfg = workloads.pwfa3d_fp32()
+        cfg["n"] = [16, 16, 512]
+        cfg["beam"] = None
+        crop = "16x16x512 crop of the PWFA plasma (no driver)"
+    else:
+        cfg = workloads.lwfa3d_fp32()
+        cfg["n"] = [32, 32, 512]
+        cfg["waist"] = 2.0
+        crop = "32x32x512 crop of the workload"
     cfg["precision"] = "fp64"
-    cfg["waist"] = 2.0
     s = Simulation(cfg)
     p = s.p
     done = 0
@@ -67,7 +86,7 @@ def cpu_baseline(seconds_budget=30.0):
         P = P.take(P.iz >= 0)          # particles that left the box (untimed)
     return {"value": done / t_used, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 numpy oracle, gather+push+deposit, {steps} steps of a "
-                      f"32x32x512 crop of the workload ({len(s.P)} particles), single thread",
+                      f"{crop} ({len(s.P)} particles), single thread",
             "seconds": t_used}
 
 
@@ -77,6 +96,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("lwfa", "pwfa"), default="lwfa",
+                    help="lwfa: 3-D LWFA 256x256x512 at 2 ppc (default); pwfa: 3-D PWFA "
+                         "512x512x1024 at 4 ppc with a 1e7-particle driver")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -102,7 +124,7 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream(dev).cuda_stream
-    cfg = workloads.lwfa3d_fp32()
+    cfg = workloads.pwfa3d_fp32() if args.workload == "pwfa" else workloads.lwfa3d_fp32()
     ppc = cfg["ppc"][0] * cfg["ppc"][1] * cfg["ppc"][2]
     sim = Sim(cfg, stream=stream)
     print(f"[bench] created {cfg['n']} ppc={ppc}", file=sys.stderr, flush=True)
@@ -124,7 +146,7 @@ def main():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2509_16793_amd", "csrc", "push.h"), "rb").read()
     same_kernel = hashlib.sha256(src).hexdigest()[:16] == MEASURED_TRAFFIC["push_h_sha256_prefix"]
-    traffic = MEASURED_TRAFFIC["bytes_per_launch"] if same_kernel else None
+    traffic = MEASURED_TRAFFIC["bytes_per_launch"] if same_kernel and args.workload == "lwfa" else None
     n_avg = 0.5 * (n0 + n1)
     push_s = ph["push_deposit"] / 1e3
     value = n_avg * args.steps / push_s
@@ -144,9 +166,7 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": "lwfa3d_fp32: 3-D LWFA 256x256x512, dx=dy=0.4, dzeta=0.05 "
-                               "(lambda_L), n_e=0.001 n_c, 2 ppc, a0=2, waist 8, FWHM 8, "
-                               "FP32 cell+offset particles, 8x8x4 tiles",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "grid": cfg["n"], "ppc": ppc, "particles": int(n_avg)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -158,7 +178,7 @@ def main():
     sim.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a crop", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -185,7 +185,10 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   const int per_xcd = (nitem + 7) / 8;
   const int item = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (item >= nitem) return;
-  const int seg = item / ncol, colm = item - seg * ncol;
+  // segments from the front of the box backwards: the laser or a driver,
+  // whose tiles hold the most work, sit near the front and start first
+  const int segi = item / ncol, colm = item - segi * ncol;
+  const int seg = a.nseg - 1 - segi;
   const int tx = colm % g.nTx, ty = colm / g.nTx;
   const int tz0 = seg * a.seg_len, tz1 = min(g.nTz, tz0 + a.seg_len);
   if (tz0 >= tz1) return;
