@@ -65,8 +65,14 @@ typedef enum {
 
 typedef enum {
   GEMPIC_FP64 = 0,        /* every particle and field quantity in FP64             */
-  GEMPIC_FP32_CELL = 1    /* int32 cell + FP32 offsets/momenta/fields; FP64 tau,
+  GEMPIC_FP32_CELL = 1,   /* int32 cell + FP32 offsets/momenta/fields; FP64 tau,
                              window thresholds and diagnostics                    */
+  GEMPIC_FP32_ABS = 2     /* FP32 absolute positions (x, y, zeta from the grid
+                             origin, normalised units) + FP32 momenta/fields, 24 B
+                             per particle: the precision-study mode.  A particle's
+                             cell is floor(x * (1/h_x)) in FP32 (1/h_x rounded to
+                             FP32), the move x += v dtau is done in FP32.  No
+                             driver beam in this mode.                            */
 } gempic_precision;
 
 /* Configuration.  Lengths and times in "config units": multiplied by
@@ -174,7 +180,8 @@ size_t gempic_fields_bytes(const gempic_t* g, uint32_t mask);
  * capacity entries (offset in [0,1) along x, y, zeta); u = 3 planes of
  * capacity entries (momentum gamma v); id (nullable) = capacity int64 ids
  * (needs track_ids).  Offsets and momenta are double for GEMPIC_FP64, float
- * otherwise.  *count receives the particle count; GEMPIC_EINVAL if capacity
+ * otherwise.  GEMPIC_FP32_ABS: off holds the absolute positions (x, y, zeta)
+ * and cell the cells they decode to.  *count receives the particle count; GEMPIC_EINVAL if capacity
  * is smaller (then nothing is copied). */
 int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, void* u,
                      int64_t* id, size_t capacity, size_t* count);
@@ -186,7 +193,8 @@ int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, v
  * handle's precision: the transverse modes k_x = 2 pi i / (Nx hx),
  * i = 0 .. Nx/2 - 1, and k_y = 2 pi fftfreq(Ny, hy) of the forward transform
  * sum f exp(-i k.r).  step sets the step counter (tau = step * dtau).  Host
- * memory.  ids (nullable) as in gempic_particles. */
+ * memory.  ids (nullable) as in gempic_particles.  GEMPIC_FP32_ABS: off holds
+ * absolute positions and cell must equal the cells they decode to. */
 int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void* off,
                      const void* u, const int64_t* id, size_t count, const void* spectral,
                      size_t spectral_bytes);

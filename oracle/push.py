@@ -174,3 +174,58 @@ def push_and_move(p, P, F):
     P.iy = (P.iy + ky) % p.Ny
     P.iz = P.iz + kz
     return old, (kx, ky, kz), vy
+
+
+def decode_abs(x, ih, n=None):
+    """Cell and offset of absolute positions x along an axis: f = x * ih in the
+    precision of x, cell = floor(f), offset = f - cell; with n (periodic axis)
+    a cell equal to n wraps to 0."""
+    f = x * ih
+    c = np.floor(f)
+    off = f - c
+    c = c.astype(np.int64)
+    if n is not None:
+        c = np.where(c >= n, c - n, c)
+    return c, off
+
+
+def push_and_move_abs(p, X, Y, Z, ux, uy, uz, F):
+    """Gather, push and move with absolute positions (x, y, zeta from the grid
+    origin) instead of cell + offset, in the precision of the inputs (FP32 for
+    the absolute-position precision mode).  Cells and offsets are decoded with
+    the inverse steps rounded to that precision; the move adds v dtau to the
+    position, wraps x and y into the periodic box and decodes again.
+    Returns (X1, Y1, Z1, ux, uy, uz, old, new, steps) with old/new =
+    (ix, iy, iz, dx, dy, dz)."""
+    from .plasma import Particles
+    dt = X.dtype.type
+    ihx, ihy, ih = dt(1.0 / p.hx), dt(1.0 / p.hy), dt(1.0 / p.h)
+    Lx, Ly = dt(p.Nx * p.hx), dt(p.Ny * p.hy)
+    ix, dx = decode_abs(X, ihx, p.Nx)
+    iy, dy = decode_abs(Y, ihy, p.Ny)
+    iz, dz = decode_abs(Z, ih)
+    top = iz >= p.Nzp
+    iz = np.where(top, p.Nzp - 1, iz)
+    dz = np.where(top, np.nextafter(dt(1), dt(0)), dz)
+    P = Particles(ix=ix, iy=iy, iz=iz, dx=dx, dy=dy, dz=dz, ux=ux, uy=uy, uz=uz,
+                  pid=np.zeros(len(ix), np.int64))
+    Fp = gather(p, P, F)
+    eps = 0.5 * p.q * p.dtau
+    ux, uy, uz = higuera_cary(ux, uy, uz, Fp[0:3], Fp[3:6], eps)
+    g, vx, vy, vzm1 = velocities(ux, uy, uz)
+    dtau = dt(p.dtau)
+    X1 = madd(vx, dtau, X)
+    X1 = np.where(X1 >= Lx, X1 - Lx, np.where(X1 < 0, X1 + Lx, X1))
+    Y1 = madd(vy, dtau, Y)
+    Y1 = np.where(Y1 >= Ly, Y1 - Ly, np.where(Y1 < 0, Y1 + Ly, Y1))
+    Z1 = madd(vzm1, dtau, Z)
+    jx, ex = decode_abs(X1, ihx, p.Nx)
+    jy, ey = decode_abs(Y1, ihy, p.Ny)
+    jz, ez = decode_abs(Z1, ih)
+    kx = jx - ix
+    kx = np.where(kx > 1, kx - p.Nx, np.where(kx < -1, kx + p.Nx, kx))
+    ky = jy - iy
+    ky = np.where(ky > 1, ky - p.Ny, np.where(ky < -1, ky + p.Ny, ky))
+    kz = jz - iz
+    return (X1, Y1, Z1, ux, uy, uz, (ix, iy, iz, dx, dy, dz), (jx, jy, jz, ex, ey, ez),
+            (kx, ky, kz))

@@ -56,7 +56,20 @@ struct Geom {
   double hx, hy, h, dtau;
   double qw;             // charge q * w of a macro-particle
   double V;              // cell volume hx * hy_eff * h
+  int abs_pos;           // particles store absolute FP32 positions (no cell array)
+  float ihx, ihy, ih;    // FP32 inverse steps that decode an absolute position
+  float Lx, Ly;          // FP32 periodic lengths Nx hx, Ny hy
 };
+
+// Cell and offset of an absolute FP32 position along an axis of n cells:
+// f = x * (1/h) in FP32, cell = floor(f), offset = f - cell; a cell equal to n
+// (x rounded up to the periodic length) wraps to 0 when periodic.
+GP_DEV int abs_cell(float x, float ih, float* off) {
+  float f = x * ih;
+  float c = floorf(f);
+  *off = f - c;
+  return (int)c;
+}
 
 // Sort codes: destination tile relative to the source tile, steps
 // sz in {-1, 0}, sy, sx in {-1, 0, 1}: code = (sz + 1) * 9 + (sy + 1) * 3 + sx + 1.

@@ -297,6 +297,9 @@ struct Impl {
     sa.g = G;
     sa.ct = oldt;
     sa.cell = (const int32_t*)g->part[A][0];
+    sa.px = (const float*)g->part[A][1];
+    sa.py = (const float*)g->part[A][2];
+    sa.pz = (const float*)g->part[A][3];
     sa.code = g->code;
     sa.counts = g->counts;
     sa.err = g->err_dev;
@@ -420,6 +423,7 @@ struct Impl {
     cmax = std::max(cmax, std::fabs((double)a.crho));
     // driver-beam particles carry rb times the plasma weight
     a.rb = (T)(g->wb > 0 ? g->wb / g->w : 1.0);
+    a.dtau = (T)G.dtau;
     if (g->wb > 0) cmax *= std::max(1.0, g->wb / g->w);
     double lim = sizeof(T) == 4 ? std::ldexp(1.0, 30) : std::ldexp(1.0, 61) / (double)GP_CHUNK;
     double sc = cmax > 0 ? lim / (cmax * 1.01) : 1.0;
@@ -460,13 +464,20 @@ struct Impl {
     constexpr int NTHR = TZ == 8 ? 512 : 256;
     if constexpr (DIM == 3) {
       if (g->cfg.beam_np > 0) {
-        if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, true><<<nb, NTHR, 0, g->s>>>(a, P);
-        else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, true><<<nb, NTHR, 0, g->s>>>(a, P);
+        if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, true, false><<<nb, NTHR, 0, g->s>>>(a, P);
+        else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, true, false><<<nb, NTHR, 0, g->s>>>(a, P);
         return;
       }
+      if constexpr (std::is_same<T, float>::value) {
+        if (g->g.abs_pos) {
+          if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, false, true><<<nb, NTHR, 0, g->s>>>(a, P);
+          else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, false, true><<<nb, NTHR, 0, g->s>>>(a, P);
+          return;
+        }
+      }
     }
-    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, false><<<nb, NTHR, 0, g->s>>>(a, P);
-    else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, false><<<nb, NTHR, 0, g->s>>>(a, P);
+    if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, false, false><<<nb, NTHR, 0, g->s>>>(a, P);
+    else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, false, false><<<nb, NTHR, 0, g->s>>>(a, P);
   }
 
   static void launch_push(gempic* g) {
@@ -722,7 +733,14 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   if (c->abi_version != GEMPIC_ABI_VERSION) { *why = "abi_version mismatch"; return GEMPIC_EABI; }
   if (c->dims != 2 && c->dims != 3) { *why = "dims must be 2 or 3"; return GEMPIC_EINVAL; }
   if (!(c->length_unit > 0)) { *why = "length_unit must be > 0"; return GEMPIC_EINVAL; }
-  if (c->precision != GEMPIC_FP64 && c->precision != GEMPIC_FP32_CELL) { *why = "unknown precision"; return GEMPIC_EINVAL; }
+  if (c->precision != GEMPIC_FP64 && c->precision != GEMPIC_FP32_CELL && c->precision != GEMPIC_FP32_ABS) {
+    *why = "unknown precision";
+    return GEMPIC_EINVAL;
+  }
+  if (c->precision == GEMPIC_FP32_ABS && (c->dims != 3 || c->beam_np > 0)) {
+    *why = "GEMPIC_FP32_ABS needs dims = 3 and no driver beam";
+    return GEMPIC_EINVAL;
+  }
   if (c->filter_passes < 0 || c->filter_passes > 2) { *why = "filter_passes must be 0, 1 or 2"; return GEMPIC_EINVAL; }
   double lu = c->length_unit;
   G->dims = c->dims;
@@ -778,6 +796,12 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
     if (c->beam_np > (1ll << 28)) { *why = "beam_np too large"; return GEMPIC_EINVAL; }
   }
   if ((int64_t)G->NT > (int64_t)SCAN_PER * SCAN_MAXB) { *why = "too many tiles"; return GEMPIC_EINVAL; }
+  G->abs_pos = c->precision == GEMPIC_FP32_ABS ? 1 : 0;
+  G->ihx = (float)(1.0 / G->hx);
+  G->ihy = (float)(1.0 / G->hy);
+  G->ih = (float)(1.0 / G->h);
+  G->Lx = (float)((double)G->Nx * G->hx);
+  G->Ly = (float)((double)G->Ny * G->hy);
   return GEMPIC_OK;
 }
 
@@ -869,7 +893,7 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   bool ok = true;
   auto A = [&](size_t bytes) { void* p = d.alloc(bytes); ok = ok && p; return p; };
   for (int b = 0; b < 2; ++b) {
-    g->part[b][0] = A(g->capacity * 4);
+    g->part[b][0] = G.abs_pos ? nullptr : A(g->capacity * 4);
     for (int q = 1; q < 7; ++q) g->part[b][q] = (q == 2 && G.dims == 2) ? nullptr : A(g->capacity * es);
     g->ids[b] = cfg->track_ids ? (int64_t*)A(g->capacity * 8) : nullptr;
   }
@@ -1023,7 +1047,14 @@ int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, v
   hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   int b = g->cur;
   size_t es = g->esz;
-  if (cell) HIPCHK(g, hipMemcpyAsync(cell, g->part[b][0], n * 4, kind, g->s));
+  if (cell && g->g.abs_pos) {
+    // cells decoded from the absolute positions, staged in the sort-code array
+    k_abs_cells<<<nblk(n, 256), 256, 0, g->s>>>(g->g, (const float*)g->part[b][1], (const float*)g->part[b][2],
+                                                 (const float*)g->part[b][3], n, g->code);
+    HIPCHK(g, hipMemcpyAsync(cell, g->code, n * 4, kind, g->s));
+  } else if (cell) {
+    HIPCHK(g, hipMemcpyAsync(cell, g->part[b][0], n * 4, kind, g->s));
+  }
   for (int q = 0; q < 3; ++q) {
     char* o = off ? (char*)off + q * capacity * es : nullptr;
     char* v = u ? (char*)u + q * capacity * es : nullptr;
@@ -1069,7 +1100,22 @@ int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void*
     if (id) maxid = std::max<int64_t>(maxid, id[i]);
   }
   int b = g->cur;
-  HIPCHK(g, hipMemcpyAsync(g->part[b][0], cell, count * 4, hipMemcpyHostToDevice, g->s));
+  if (G.abs_pos) {
+    // the cells must be those the absolute positions decode to
+    const float* px = (const float*)off;
+    for (size_t i = 0; i < count; ++i) {
+      float o;
+      float x = px[i], y = px[count + i], z = px[2 * count + i];
+      int ix = (int)std::floor(x * G.ihx), iy = (int)std::floor(y * G.ihy), iz = (int)std::floor(z * G.ih);
+      (void)o;
+      if (ix >= G.Nx) ix -= G.Nx;
+      if (iy >= G.Ny) iy -= G.Ny;
+      if (iz >= G.Nzp) iz = G.Nzp - 1;
+      if (cell[i] != (iz * G.Ny + iy) * G.Nx + ix) return fail(g, GEMPIC_EINVAL, "cell does not match the absolute position");
+    }
+  } else {
+    HIPCHK(g, hipMemcpyAsync(g->part[b][0], cell, count * 4, hipMemcpyHostToDevice, g->s));
+  }
   for (int q = 0; q < 3; ++q) {
     if (g->part[b][1 + q])
       HIPCHK(g, hipMemcpyAsync(g->part[b][1 + q], (const char*)off + q * count * es, count * es,

@@ -41,6 +41,30 @@ template <typename T> GP_DEV T store_offset(double d) {
   return t < (T)1 ? t : one_minus<T>();
 }
 
+// A new particle of cell (i, j, iz) at FP64 offsets (dx, dy, dz): cell word
+// and offsets in T, or (g.abs_pos) the absolute position rounded once to FP32,
+// kept below the plasma edge (Nzp h); a staging buffer also keeps the cell.
+template <typename T>
+GP_DEV void put_particle(const PartPtrs<T>& P, int64_t o, const Geom& g, int i, int j, int iz,
+                         double dx, double dy, double dz) {
+  if (P.cell) P.cell[o] = (iz * g.Ny + j) * g.Nx + i;
+  if (g.abs_pos) {
+    P.ox[o] = (T)(((double)i + dx) * g.hx);
+    if (g.dims == 3) P.oy[o] = (T)(((double)j + dy) * g.hy);
+    T z = (T)(((double)iz + dz) * g.h);
+    const T edge = (T)((double)g.Nzp * g.h);
+    while (z >= edge) z = nextafter(z, (T)0);
+    P.oz[o] = z;
+  } else {
+    P.ox[o] = store_offset<T>(dx);
+    if (g.dims == 3) P.oy[o] = store_offset<T>(dy);
+    P.oz[o] = store_offset<T>(dz);
+  }
+  P.ux[o] = (T)0;
+  P.uy[o] = (T)0;
+  P.uz[o] = (T)0;
+}
+
 // ---------------------------------------------------------------------------
 // Loading: every lattice particle of the full cells 0 .. Nzp - 2 of one tile,
 // written at tile_base[t] in (m, j, i, sy, sx) order.  Sub-row m of lab z has
@@ -85,13 +109,7 @@ __global__ void k_load_full(LoadArgs a, PartPtrs<T> P) {
     }
     int iz = (int)(m / a.ppcz);
     int64_t o = base + l;
-    P.cell[o] = (iz * g.Ny + j) * g.Nx + i;
-    P.ox[o] = store_offset<T>(dx);
-    if (g.dims == 3) P.oy[o] = store_offset<T>(dy);
-    P.oz[o] = store_offset<T>(dz);
-    P.ux[o] = (T)0;
-    P.uy[o] = (T)0;
-    P.uz[o] = (T)0;
+    put_particle<T>(P, o, g, i, j, iz, dx, dy, dz);
     if (P.id) P.id[o] = (int64_t)gidx;
   }
 }
@@ -142,6 +160,20 @@ __global__ void k_beam_rho(BeamArgs a, Geom g, double qv, T* rho) {
         atomicAdd(rho + ((int64_t)z * g.Ny + y) * g.Nx + x, (T)(qv * ((wx[aa] * wy[b]) * wz[cc])));
       }
   }
+}
+
+// Cells of n particles with absolute FP32 positions (decoded as in the push).
+__global__ void k_abs_cells(Geom g, const float* px, const float* py, const float* pz, int64_t n,
+                            int32_t* cell) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float o;
+  int ix = abs_cell(px[i], g.ihx, &o);
+  if (ix >= g.Nx) ix -= g.Nx;
+  int iy = g.dims == 3 ? abs_cell(py[i], g.ihy, &o) : 0;
+  if (iy >= g.Ny) iy -= g.Ny;
+  int iz = min(abs_cell(pz[i], g.ih, &o), g.Nzp - 1);
+  cell[i] = iz < 0 ? -1 : (iz * g.Ny + iy) * g.Nx + ix;
 }
 
 // Driver-beam particles (cell words with GEMPIC_BEAM_BIT) among the first n.
@@ -241,13 +273,7 @@ __global__ __launch_bounds__(256) void k_inject(InjArgs a, PartPtrs<T> S) {
     for (int w = 0; w < wid; ++w) off += wsum[w];
     if (sel) {
       int64_t o = sbase + off + wrank;
-      S.cell[o] = (iz * g.Ny + j) * g.Nx + i;
-      S.ox[o] = store_offset<T>(dx);
-      if (g.dims == 3) S.oy[o] = store_offset<T>(dy);
-      S.oz[o] = store_offset<T>(dz);
-      S.ux[o] = (T)0;
-      S.uy[o] = (T)0;
-      S.uz[o] = (T)0;
+      put_particle<T>(S, o, g, i, j, iz, dx, dy, dz);
       a.stage_g[o] = (int32_t)gidx;
     }
     __syncthreads();
@@ -282,7 +308,10 @@ GP_DEV int tile_step(int src, int dst, int n) {
 struct SortArgs {
   Geom g;
   ChunkTab ct;
-  const int32_t* cell;
+  const int32_t* cell;     // null with absolute positions: cells from px, py, pz
+  const float* px;
+  const float* py;
+  const float* pz;
   int32_t* code;        // [N] code << 24 | rank
   int32_t* counts;      // [max_chunks * NCODE]
   int* err;
@@ -307,7 +336,18 @@ __global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
     int p = row + threadIdx.x;
     int code = -1;
     if (p < p1) {
-      int cell = a.cell[p];
+      int cell;
+      if (a.cell) {
+        cell = a.cell[p];
+      } else {
+        float o;
+        int ix = abs_cell(a.px[p], g.ihx, &o);
+        if (ix >= g.Nx) ix -= g.Nx;
+        int iy = g.dims == 3 ? abs_cell(a.py[p], g.ihy, &o) : 0;
+        if (iy >= g.Ny) iy -= g.Ny;
+        int iz = min(abs_cell(a.pz[p], g.ih, &o), g.Nzp - 1);
+        cell = iz < 0 ? -1 : (iz * g.Ny + iy) * g.Nx + ix;
+      }
       if (cell < 0) {
         code = CODE_REMOVED;
       } else {
@@ -557,7 +597,7 @@ __global__ __launch_bounds__(256) void k_scatter(ScatArgs<T> a, PartPtrs<T> A, P
     int dt = (dz * g.nTy + dy) * g.nTx + dx;
     int64_t o = a.tile_base[dt] + a.offs[c * NCODE + code] + rank;
     if (o >= a.capacity) { atomicOr(a.err, ERR_CAPACITY); continue; }
-    B.cell[o] = A.cell[p];
+    if (B.cell) B.cell[o] = A.cell[p];
     B.ox[o] = A.ox[p];
     if (DIM == 3) B.oy[o] = A.oy[p];
     B.oz[o] = A.oz[p];
@@ -594,7 +634,7 @@ __global__ __launch_bounds__(256) void k_inject_copy(InjCopyArgs a, PartPtrs<T> 
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     int64_t s = sb + k, o = db + k;
     if (o >= a.capacity) { atomicOr(a.err, ERR_CAPACITY); continue; }
-    B.cell[o] = S.cell[s];
+    if (B.cell) B.cell[o] = S.cell[s];
     B.ox[o] = S.ox[s];
     if (DIM == 3) B.oy[o] = S.oy[s];
     B.oz[o] = S.oz[s];

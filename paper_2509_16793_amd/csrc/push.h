@@ -43,6 +43,7 @@ struct PushArgs {
   T cjy;               // 2-D out-of-plane: q w / (hx h)
   T crho;              // q w / V
   T rb;                // weight of a driver-beam particle over the plasma weight
+  T dtau;              // slow step (absolute-position move)
   T fscale, finv;      // fixed-point scale of the LDS tile (power of two) and its inverse
   const int64_t* tile_base;   // [NT] first particle of each tile
   const int64_t* tile_count;  // [NT] particles of each tile
@@ -141,10 +142,11 @@ GP_DEV void row_st(Q v, Q* p, int base, int n, unsigned lane) {
 }
 
 // the n particles base .. base + n - 1, one per lane (lanes >= n get zeros)
-template <typename T, int DIM>
+template <typename T, int DIM, bool ABS>
 GP_DEV PLoad<T> load_row(const PartPtrs<T>& P, int base, int n, unsigned lane) {
   PLoad<T> s;
-  s.cell = row_ld(P.cell, base, n, lane);
+  // absolute positions: the offsets hold x, y, zeta and there is no cell word
+  s.cell = ABS ? 0 : row_ld(P.cell, base, n, lane);
   s.ox = row_ld(P.ox, base, n, lane);
   s.oy = DIM == 3 ? row_ld(P.oy, base, n, lane) : (T)0;
   s.oz = row_ld(P.oz, base, n, lane);
@@ -156,7 +158,10 @@ GP_DEV PLoad<T> load_row(const PartPtrs<T>& P, int base, int n, unsigned lane) {
 
 // SPEC: cell words may carry GEMPIC_BEAM_BIT (driver-beam particles, weight rb
 // times the plasma weight); the bit is kept through the move.
-template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR, bool SPEC>
+// ABS: particles hold absolute FP32 positions; cells and offsets are decoded
+// from them (abs_cell), the move adds v dtau to the position in FP32 (periodic
+// wrap transversally) and the new cell and offset are decoded again.
+template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR, bool SPEC, bool ABS>
 __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
   constexpr int FX = TX + 1, FY = DIM == 3 ? TY + 1 : 1, FZ = TZ + 1;
   constexpr int FN = FX * FY * FZ;
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   range(tz0, &p0, &p1);
   // the next row's particles are loaded while the current row is processed
   const unsigned lane = threadIdx.x;
-  PLoad<T> nxt = load_row<T, DIM>(P, p0, p1 - p0, lane);
+  PLoad<T> nxt = load_row<T, DIM, ABS>(P, p0, p1 - p0, lane);
 
   for (int tz = tz0; tz < tz1; ++tz) {
   const int z0 = tz * TZ;
@@ -257,25 +262,43 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
     {
       const bool same = row + NTHR < p1;
       const int nb = same ? row + NTHR : np0;
-      nxt = load_row<T, DIM>(P, nb, (same ? p1 : np1) - nb, lane);
+      nxt = load_row<T, DIM, ABS>(P, nb, (same ? p1 : np1) - nb, lane);
     }
     int lx = 0, ly = 0, lz = 0, kx = 0, ky = 0, kz = 0;
     const int spec = SPEC ? (cur.cell & GEMPIC_BEAM_BIT) : 0;
     T dx0 = (T)0, dy0 = (T)0, dz0 = (T)0, dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
     if (valid) {
       int cell = cur.cell ^ spec;
-      int ix = cell & mx;
-      int iy = (cell >> g.lnx) & my;
-      int iz = cell >> (g.lnx + g.lny);
+      int ix, iy, iz;
+      T ax0 = (T)0, ay0 = (T)0, az0 = (T)0;   // decoded offsets (absolute positions)
+      if constexpr (ABS) {
+        float o;
+        ix = abs_cell(cur.ox, g.ihx, &o);
+        if (ix >= g.Nx) ix -= g.Nx;
+        ax0 = o;
+        iy = 0;
+        if (DIM == 3) {
+          iy = abs_cell(cur.oy, g.ihy, &o);
+          if (iy >= g.Ny) iy -= g.Ny;
+          ay0 = o;
+        }
+        iz = abs_cell(cur.oz, g.ih, &o);
+        az0 = o;
+        if (iz >= g.Nzp) { iz = g.Nzp - 1; az0 = (T)0x1.fffffep-1f; }
+      } else {
+        ix = cell & mx;
+        iy = (cell >> g.lnx) & my;
+        iz = cell >> (g.lnx + g.lny);
+      }
       lx = ix - x0; ly = iy - y0; lz = iz - z0;
       if (lx < 0 || lx >= TX || ly < 0 || ly >= (DIM == 3 ? TY : 1) || lz < 0 || lz >= TZ) {
         atomicOr(a.err, ERR_TILE);
         valid = false;
         lx = ly = lz = 0;
       } else {
-        dx0 = cur.ox;
-        dz0 = cur.oz;
-        if (DIM == 3) dy0 = cur.oy;
+        dx0 = ABS ? ax0 : cur.ox;
+        dz0 = ABS ? az0 : cur.oz;
+        if (DIM == 3) dy0 = ABS ? ay0 : cur.oy;
         T ux = cur.ux, uy = cur.uy, uz = cur.uz;
 
         // gather
@@ -332,23 +355,48 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
         T vx = ux * rg;
         vy = uy * rg;
         T vzm1 = uz >= (T)0 ? (-((T)1 + uperp2) * rg) / (gam + uz) : madd(uz, rg, (T)-1);
-        T tnx = madd(vx, a.ax, dx0);
-        T kxf = floor(tnx);
-        dx1 = tnx - kxf;
-        kx = (int)kxf;
-        if (dx1 >= (T)1) { dx1 = (T)0; kx += 1; }
-        if (DIM == 3) {
-          T tny = madd(vy, a.ay, dy0);
-          T kyf = floor(tny);
-          dy1 = tny - kyf;
-          ky = (int)kyf;
-          if (dy1 >= (T)1) { dy1 = (T)0; ky += 1; }
+        T X1 = (T)0, Y1 = (T)0, Z1 = (T)0;
+        if constexpr (ABS) {
+          float o;
+          X1 = madd(vx, a.dtau, cur.ox);
+          if (X1 >= g.Lx) X1 -= g.Lx; else if (X1 < (T)0) X1 += g.Lx;
+          int ix1 = abs_cell(X1, g.ihx, &o);
+          if (ix1 >= g.Nx) ix1 -= g.Nx;
+          dx1 = o;
+          kx = ix1 - ix;
+          if (kx > 1) kx -= g.Nx; else if (kx < -1) kx += g.Nx;
+          if (DIM == 3) {
+            Y1 = madd(vy, a.dtau, cur.oy);
+            if (Y1 >= g.Ly) Y1 -= g.Ly; else if (Y1 < (T)0) Y1 += g.Ly;
+            int iy1 = abs_cell(Y1, g.ihy, &o);
+            if (iy1 >= g.Ny) iy1 -= g.Ny;
+            dy1 = o;
+            ky = iy1 - iy;
+            if (ky > 1) ky -= g.Ny; else if (ky < -1) ky += g.Ny;
+          }
+          Z1 = madd(vzm1, a.dtau, cur.oz);
+          int iz1 = abs_cell(Z1, g.ih, &o);
+          dz1 = o;
+          kz = iz1 - iz;
+        } else {
+          T tnx = madd(vx, a.ax, dx0);
+          T kxf = floor(tnx);
+          dx1 = tnx - kxf;
+          kx = (int)kxf;
+          if (dx1 >= (T)1) { dx1 = (T)0; kx += 1; }
+          if (DIM == 3) {
+            T tny = madd(vy, a.ay, dy0);
+            T kyf = floor(tny);
+            dy1 = tny - kyf;
+            ky = (int)kyf;
+            if (dy1 >= (T)1) { dy1 = (T)0; ky += 1; }
+          }
+          T tnz = madd(vzm1, a.az, dz0);
+          T kzf = floor(tnz);
+          dz1 = tnz - kzf;
+          kz = (int)kzf;
+          if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
         }
-        T tnz = madd(vzm1, a.az, dz0);
-        T kzf = floor(tnz);
-        dz1 = tnz - kzf;
-        kz = (int)kzf;
-        if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
         if (!(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
         if (kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 0) {
           atomicOr(a.err, ERR_CFL);
@@ -359,10 +407,16 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           int niy = (iy + ky) & my;
           int niz = iz + kz;
           const int nr = p1 - row;
-          row_st(((niz * g.Ny + niy) * g.Nx + nix) | spec, P.cell, row, nr, lane);
-          row_st(dx1, P.ox, row, nr, lane);
-          if (DIM == 3) row_st(dy1, P.oy, row, nr, lane);
-          row_st(dz1, P.oz, row, nr, lane);
+          if constexpr (ABS) {
+            row_st(X1, P.ox, row, nr, lane);
+            if (DIM == 3) row_st(Y1, P.oy, row, nr, lane);
+            row_st(Z1, P.oz, row, nr, lane);
+          } else {
+            row_st(((niz * g.Ny + niy) * g.Nx + nix) | spec, P.cell, row, nr, lane);
+            row_st(dx1, P.ox, row, nr, lane);
+            if (DIM == 3) row_st(dy1, P.oy, row, nr, lane);
+            row_st(dz1, P.oz, row, nr, lane);
+          }
           row_st(ux, P.ux, row, nr, lane);
           row_st(uy, P.uy, row, nr, lane);
           row_st(uz, P.uz, row, nr, lane);
@@ -625,7 +679,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   }
   __syncthreads();
   // an empty tile consumed no prefetch: load the next tile's first row now
-  if (p0 >= p1) nxt = load_row<T, DIM>(P, np0, np1 - np0, lane);
+  if (p0 >= p1) nxt = load_row<T, DIM, ABS>(P, np0, np1 - np0, lane);
   p0 = np0;
   p1 = np1;
   }  // zeta tiles of the segment

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgempic.so")
 
 ABI_VERSION = 2
 BEAM_BIT = 1 << 30
-FP64, FP32_CELL = 0, 1
+FP64, FP32_CELL, FP32_ABS = 0, 1, 2
 EX, EY, EZ, BX, BY, BZ, JX, JY, JZ, RHO = (1 << i for i in range(10))
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 
@@ -132,9 +132,10 @@ def make_config(cfg, stream=None, track_ids=False, deposit_rho=False):
     c.length_unit = float(cfg.get("length_unit", 1.0))
     c.dtau = float(cfg.get("dtau", 0.0))
     prec = cfg.get("precision", "fp32")
-    if prec not in ("fp64", "fp32"):
+    modes = {"fp64": FP64, "fp32": FP32_CELL, "fp32abs": FP32_ABS}
+    if prec not in modes:
         raise ValueError(f"precision {prec!r} not supported by the library")
-    c.precision = FP64 if prec == "fp64" else FP32_CELL
+    c.precision = modes[prec]
     c.tile[:] = [int(v) for v in cfg.get("tile", (8, 8, 8))]
     c.n_e = float(cfg.get("n_e", 0.0))
     c.ppc[:] = [int(v) for v in cfg.get("ppc", (1, 1, 1))]
