@@ -41,20 +41,27 @@ template <typename T> GP_DEV T store_offset(double d) {
   return t < (T)1 ? t : one_minus<T>();
 }
 
+// An FP64 position in cell c rounded to FP32, then moved by single ulps until
+// it decodes (abs_cell, unwrapped) to c: rounding never moves a new particle
+// into another cell, and so never into another tile.
+GP_DEV float place_abs(double pos, int c, float ih) {
+  float x = (float)pos, off;
+  while (abs_cell(x, ih, &off) > c) x = nextafterf(x, 0.0f);
+  while (abs_cell(x, ih, &off) < c) x = nextafterf(x, 3.0e38f);
+  return x;
+}
+
 // A new particle of cell (i, j, iz) at FP64 offsets (dx, dy, dz): cell word
-// and offsets in T, or (g.abs_pos) the absolute position rounded once to FP32,
-// kept below the plasma edge (Nzp h); a staging buffer also keeps the cell.
+// and offsets in T, or (g.abs_pos, FP32 only) the absolute position (place_abs);
+// a staging buffer also keeps the cell.
 template <typename T>
 GP_DEV void put_particle(const PartPtrs<T>& P, int64_t o, const Geom& g, int i, int j, int iz,
                          double dx, double dy, double dz) {
   if (P.cell) P.cell[o] = (iz * g.Ny + j) * g.Nx + i;
   if (g.abs_pos) {
-    P.ox[o] = (T)(((double)i + dx) * g.hx);
-    if (g.dims == 3) P.oy[o] = (T)(((double)j + dy) * g.hy);
-    T z = (T)(((double)iz + dz) * g.h);
-    const T edge = (T)((double)g.Nzp * g.h);
-    while (z >= edge) z = nextafter(z, (T)0);
-    P.oz[o] = z;
+    P.ox[o] = (T)place_abs(((double)i + dx) * g.hx, i, g.ihx);
+    if (g.dims == 3) P.oy[o] = (T)place_abs(((double)j + dy) * g.hy, j, g.ihy);
+    P.oz[o] = (T)place_abs(((double)iz + dz) * g.h, iz, g.ih);
   } else {
     P.ox[o] = store_offset<T>(dx);
     if (g.dims == 3) P.oy[o] = store_offset<T>(dy);

@@ -1,8 +1,8 @@
 """The absolute-position FP32 mode (GEMPIC_FP32_ABS) of the HIP library.
 
 * Creation: every particle's position is the oracle's FP64 position
-  (i + d) h rounded once to FP32 (kept below the plasma edge), in the oracle's
-  order and ids.
+  (i + d) h rounded to FP32 and, where rounding crossed into the next cell,
+  moved back by single ulps, in the oracle's order and ids.
 * One step from a shared state: positions, momenta and cells bit for bit
   against the oracle's absolute-position push run in FP32 on the same inputs
   (the cell decisions are taken in FP32 on both sides).
@@ -21,14 +21,22 @@ from parity import oracle_half_spectrum, oracle_fields, rel_errors
 pytestmark = pytest.mark.gpu
 
 
+def _place(pos, cell, h):
+    """FP64 position -> FP32, moved by single ulps until floor(x * (1/h)) in
+    FP32 is the cell the particle was created in."""
+    x = pos.astype(np.float32)
+    ih = np.float32(1.0 / h)
+    for _ in range(8):
+        d = np.floor(x * ih).astype(np.int64)
+        x = np.where(d > cell, np.nextafter(x, np.float32(0)),
+                     np.where(d < cell, np.nextafter(x, np.float32(np.inf)), x))
+    assert np.array_equal(np.floor(x * ih).astype(np.int64), cell)
+    return x
+
+
 def _abs_positions(p, P):
-    x = ((P.ix + P.dx) * p.hx).astype(np.float32)
-    y = ((P.iy + P.dy) * p.hy).astype(np.float32)
-    z = ((P.iz + P.dz) * p.h).astype(np.float32)
-    edge = np.float32(p.Nzp * p.h)
-    while np.any(z >= edge):
-        z = np.where(z >= edge, np.nextafter(z, np.float32(0)), z)
-    return x, y, z
+    return (_place((P.ix + P.dx) * p.hx, P.ix, p.hx), _place((P.iy + P.dy) * p.hy, P.iy, p.hy),
+            _place((P.iz + P.dz) * p.h, P.iz, p.h))
 
 
 def _cells(p, x, y, z):
