@@ -256,7 +256,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
   __syncthreads();
 
   for (int row = p0; row < p1; row += NTHR) {
-    bool valid = row + (int)lane < p1;
+    const bool inrow = row + (int)lane < p1;
     const PLoad<T> cur = nxt;
     // prefetch: the next row of this tile, else the first row of the next tile
     {
@@ -264,43 +264,46 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
       const int nb = same ? row + NTHR : np0;
       nxt = load_row<T, DIM, ABS>(P, nb, (same ? p1 : np1) - nb, lane);
     }
-    int lx = 0, ly = 0, lz = 0, kx = 0, ky = 0, kz = 0;
+    // Every lane runs the gather, push and move; lanes past the row (which
+    // loaded zeros) and lanes whose particle is not in this tile (an error)
+    // work on a stand-in at the tile's first node with zero offsets and
+    // momenta, and only valid lanes store, report errors or deposit.
     const int spec = SPEC ? (cur.cell & GEMPIC_BEAM_BIT) : 0;
-    T dx0 = (T)0, dy0 = (T)0, dz0 = (T)0, dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
-    if (valid) {
-      int cell = cur.cell ^ spec;
-      int ix, iy, iz;
-      T ax0 = (T)0, ay0 = (T)0, az0 = (T)0;   // decoded offsets (absolute positions)
-      if constexpr (ABS) {
-        float o;
-        ix = abs_cell(cur.ox, g.ihx, &o);
-        if (ix >= g.Nx) ix -= g.Nx;
-        ax0 = o;
-        iy = 0;
-        if (DIM == 3) {
-          iy = abs_cell(cur.oy, g.ihy, &o);
-          if (iy >= g.Ny) iy -= g.Ny;
-          ay0 = o;
-        }
-        iz = abs_cell(cur.oz, g.ih, &o);
-        az0 = o;
-        if (iz >= g.Nzp) { iz = g.Nzp - 1; az0 = (T)0x1.fffffep-1f; }
-      } else {
-        ix = cell & mx;
-        iy = (cell >> g.lnx) & my;
-        iz = cell >> (g.lnx + g.lny);
+    int ix, iy, iz;
+    T ax0 = (T)0, ay0 = (T)0, az0 = (T)0;   // decoded offsets (absolute positions)
+    if constexpr (ABS) {
+      float o;
+      ix = abs_cell(cur.ox, g.ihx, &o);
+      if (ix >= g.Nx) ix -= g.Nx;
+      ax0 = o;
+      iy = 0;
+      if (DIM == 3) {
+        iy = abs_cell(cur.oy, g.ihy, &o);
+        if (iy >= g.Ny) iy -= g.Ny;
+        ay0 = o;
       }
-      lx = ix - x0; ly = iy - y0; lz = iz - z0;
-      if (lx < 0 || lx >= TX || ly < 0 || ly >= (DIM == 3 ? TY : 1) || lz < 0 || lz >= TZ) {
-        atomicOr(a.err, ERR_TILE);
-        valid = false;
-        lx = ly = lz = 0;
-      } else {
-        dx0 = ABS ? ax0 : cur.ox;
-        dz0 = ABS ? az0 : cur.oz;
-        if (DIM == 3) dy0 = ABS ? ay0 : cur.oy;
-        T ux = cur.ux, uy = cur.uy, uz = cur.uz;
-
+      iz = abs_cell(cur.oz, g.ih, &o);
+      az0 = o;
+      if (iz >= g.Nzp) { iz = g.Nzp - 1; az0 = (T)0x1.fffffep-1f; }
+    } else {
+      const int cell = cur.cell ^ spec;
+      ix = cell & mx;
+      iy = (cell >> g.lnx) & my;
+      iz = cell >> (g.lnx + g.lny);
+    }
+    int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+    const bool intile = lx >= 0 && lx < TX && ly >= 0 && ly < (DIM == 3 ? TY : 1) && lz >= 0 && lz < TZ;
+    if (inrow && !intile) atomicOr(a.err, ERR_TILE);
+    bool valid = inrow && intile;
+    if (!valid) lx = ly = lz = 0;
+    T dx0 = valid ? (ABS ? ax0 : cur.ox) : (T)0;
+    T dz0 = valid ? (ABS ? az0 : cur.oz) : (T)0;
+    T dy0 = DIM == 3 && valid ? (ABS ? ay0 : cur.oy) : (T)0;
+    T ux = valid ? cur.ux : (T)0, uy = valid ? cur.uy : (T)0, uz = valid ? cur.uz : (T)0;
+    int kx = 0, ky = 0, kz = 0;
+    T dx1 = (T)0, dy1 = (T)0, dz1 = (T)0, vy = (T)0;
+    T X1 = (T)0, Y1 = (T)0, Z1 = (T)0;   // new absolute position (ABS)
+    {
         // gather
         T wx[2] = {(T)1 - dx0, dx0};
         T wz[2] = {(T)1 - dz0, dz0};
@@ -355,7 +358,6 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
         T vx = ux * rg;
         vy = uy * rg;
         T vzm1 = uz >= (T)0 ? (-((T)1 + uperp2) * rg) / (gam + uz) : madd(uz, rg, (T)-1);
-        T X1 = (T)0, Y1 = (T)0, Z1 = (T)0;
         if constexpr (ABS) {
           float o;
           X1 = madd(vx, a.dtau, cur.ox);
@@ -397,31 +399,30 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           kz = (int)kzf;
           if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
         }
-        if (!(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
-        if (kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 0) {
-          atomicOr(a.err, ERR_CFL);
-          valid = false;
-          kx = ky = kz = 0;
-        } else {
-          int nix = (ix + kx) & mx;
-          int niy = (iy + ky) & my;
-          int niz = iz + kz;
-          const int nr = p1 - row;
-          if constexpr (ABS) {
-            row_st(X1, P.ox, row, nr, lane);
-            if (DIM == 3) row_st(Y1, P.oy, row, nr, lane);
-            row_st(Z1, P.oz, row, nr, lane);
-          } else {
-            row_st(((niz * g.Ny + niy) * g.Nx + nix) | spec, P.cell, row, nr, lane);
-            row_st(dx1, P.ox, row, nr, lane);
-            if (DIM == 3) row_st(dy1, P.oy, row, nr, lane);
-            row_st(dz1, P.oz, row, nr, lane);
-          }
-          row_st(ux, P.ux, row, nr, lane);
-          row_st(uy, P.uy, row, nr, lane);
-          row_st(uz, P.uz, row, nr, lane);
-        }
+    }
+    if (valid && !(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
+    const bool cfl_bad = kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 0;
+    if (valid && cfl_bad) atomicOr(a.err, ERR_CFL);
+    valid = valid && !cfl_bad;
+    if (!valid) kx = ky = kz = 0;
+    if (valid) {
+      int nix = (ix + kx) & mx;
+      int niy = (iy + ky) & my;
+      int niz = iz + kz;
+      const int nr = p1 - row;
+      if constexpr (ABS) {
+        row_st(X1, P.ox, row, nr, lane);
+        if (DIM == 3) row_st(Y1, P.oy, row, nr, lane);
+        row_st(Z1, P.oz, row, nr, lane);
+      } else {
+        row_st(((niz * g.Ny + niy) * g.Nx + nix) | spec, P.cell, row, nr, lane);
+        row_st(dx1, P.ox, row, nr, lane);
+        if (DIM == 3) row_st(dy1, P.oy, row, nr, lane);
+        row_st(dz1, P.oz, row, nr, lane);
       }
+      row_st(ux, P.ux, row, nr, lane);
+      row_st(uy, P.uy, row, nr, lane);
+      row_st(uz, P.uz, row, nr, lane);
     }
 
     // ---- deposit (sums: FMA contraction allowed) ----
