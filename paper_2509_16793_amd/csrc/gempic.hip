@@ -434,9 +434,14 @@ struct Impl {
     a.tile_count = g->tile_count;
     a.total = g->total;
     // zeta segments: enough work-groups to fill the chip several times over,
-    // long segments so that most current planes are carried, not flushed
+    // segments long enough that most current planes are carried, not flushed,
+    // and short enough (at most 32 tiles) that the last work-groups leave no
+    // long tail; with a driver beam, whose tiles hold up to ~1e5 particles each,
+    // 4 tiles, so that one work-group does not walk all of them in turn
     int ncol = G.nTx * G.nTy;
-    int nseg = std::min(G.nTz, std::max(1, (8192 + ncol - 1) / ncol));
+    const int seg_target = g->cfg.beam_np > 0 ? 4 : 32;
+    int nseg = std::max((G.nTz + seg_target - 1) / seg_target, (8192 + ncol - 1) / ncol);
+    nseg = std::min(G.nTz, std::max(1, nseg));
     a.seg_len = (G.nTz + nseg - 1) / nseg;
     a.nseg = (G.nTz + a.seg_len - 1) / a.seg_len;
     a.err = g->err_dev;
