@@ -156,57 +156,129 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   constexpr int HALO_P = HALO + 2;
   __shared__ u32x4 sX[HALO_P * U];
 
+  // Persistent work-groups walk the output tiles t = blockIdx.x, + gridDim.x,
+  // ...  (INMODE 0) The first PU channel units of the next tile's halo are
+  // read into registers while the current tile is computed, the rest after
+  // it; the weights are loaded once per work-group.
   const int nbx = a.X / TX, nby = a.Y / TY;
-  int b = blockIdx.x;
-  const int bx = b % nbx;
-  b /= nbx;
-  const int by = b % nby, bz = b / nby;
-  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+  const int ntile = nbx * nby * ((a.Z + TZ - 1) / TZ);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-  // weights first: their loads overlap the halo staging
   bf16x8 wr[NKS][NCT];
 #pragma unroll
   for (int s = 0; s < NKS; ++s)
 #pragma unroll
     for (int j = 0; j < NCT; ++j) wr[s][j] = __builtin_bit_cast(bf16x8, a.wp[(s * NCT + j) * 64 + lane]);
 
-  if (INMODE == 0) {
-    // one halo row (HX voxels x U units, contiguous in global memory apart
-    // from the periodic wrap) per group of HX * U threads
-    constexpr int RW = HX * U;
+  constexpr int PU = U >= 4 ? 2 : 1;        // units prefetched into registers (register budget)
+  // staging of channel units [U0, U0 + UW): one halo row (HX voxels x UW
+  // units, contiguous in global memory apart from the periodic wrap) per
+  // group of HX * UW threads; row k of this thread is first + k * PER
+  auto halo_rows = [&](int t, auto u0c, auto uwc, auto&& put) {
+    constexpr int U0 = decltype(u0c)::value, UW = decltype(uwc)::value;
+    constexpr int RW = HX * UW, PER = 256 / RW, NR = (HZ * HY + PER - 1) / PER;
+    int b = t;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby, bz = b / nby;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int iw = tid % RW;
-    const int hx = iw / U, part = iw - hx * U;
+    const int hx = iw / UW, part = U0 + iw - hx * UW;
     const int gx = wrapi(x0 + hx - 1, a.X);
-    const int first_row = tid < (256 / RW) * RW ? tid / RW : HZ * HY;   // spare threads idle
-    for (int row = first_row; row < HZ * HY; row += 256 / RW) {
-      const int hz = row / HY, hy = row - hz * HY;
-      const int gz = z0 + hz - 1;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (gz >= 0 && gz < a.Z) {
+    const int first = tid < PER * RW ? tid / RW : HZ * HY;   // spare threads idle
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int row = first + k * PER;
+      if (row < HZ * HY) {
+        const int hz = row / HY, hy = row - hz * HY;
+        const int gz = z0 + hz - 1;
         const int gy = wrapi(y0 + hy - 1, a.Y);
-        v = a.in[(((int64_t)gz * a.Y + gy) * a.X + gx) * U + part];
+        const bool inz = gz >= 0 && gz < a.Z;
+        put(k, part * HALO_P + row * HX + hx, inz, (((int64_t)gz * a.Y + gy) * a.X + gx) * U + part);
       }
-      sX[part * HALO_P + row * HX + hx] = v;
     }
-  } else {
-    for (int hv = tid; hv < HALO; hv += 256) {
-      int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
-      int gz = z0 + hz - 1;
-      float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-      if (gz >= 0 && gz < a.Z) {
+  };
+  constexpr int NPR = (HZ * HY + 256 / (HX * PU) - 1) / (256 / (HX * PU));
+  u32x4 pre[INMODE == 0 ? NPR : 1];
+  using IC0 = std::integral_constant<int, 0>;
+  using ICPU = std::integral_constant<int, PU>;
+  using ICU = std::integral_constant<int, U>;
+  using ICR = std::integral_constant<int, (U > PU ? U - PU : 1)>;
+  auto ld = [&](bool inz, int64_t gi) {
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (inz) v = a.in[gi];
+    return v;
+  };
+  auto stage_direct_all = [&](int t) {
+    halo_rows(t, IC0{}, ICU{}, [&](int, int idx, bool inz, int64_t gi) { sX[idx] = ld(inz, gi); });
+  };
+  auto stage_rest = [&](int t) {      // units PU .. U - 1 (when U > PU)
+    halo_rows(t, ICPU{}, ICR{}, [&](int, int idx, bool inz, int64_t gi) { sX[idx] = ld(inz, gi); });
+  };
+  auto prefetch = [&](int t) {
+    halo_rows(t, IC0{}, ICPU{}, [&](int k, int, bool inz, int64_t gi) { pre[k] = ld(inz, gi); });
+  };
+  auto place = [&](int t) {
+    halo_rows(t, IC0{}, ICPU{}, [&](int k, int idx, bool, int64_t) { sX[idx] = pre[k]; });
+  };
+  // INMODE 1: FP32 planar input (3 components), scaled and packed to bf16;
+  // halo voxel hv = tid + k * 256
+  constexpr int NV = (HALO + 255) / 256;
+  float pin[INMODE == 1 ? 3 * NV : 1];
+  auto input_vox = [&](int t, auto&& put) {
+    int b = t;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby, bz = b / nby;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int hv = tid + k * 256;
+      if (hv < HALO) {
+        int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+        int gz = z0 + hz - 1;
         int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
-        int64_t o = ((int64_t)gz * a.Y + gy) * a.X + gx;
-        c0 = a.inf[0][o] * a.in_scale;
-        c1 = a.inf[1][o] * a.in_scale;
-        c2 = a.inf[2][o] * a.in_scale;
+        put(k, hv, gz >= 0 && gz < a.Z, ((int64_t)gz * a.Y + gy) * a.X + gx);
       }
-      u32x4 v = {pack_bf16(c0, c1), pack_bf16(c2, 0.0f), 0u, 0u};
-      sX[hv] = v;
     }
-  }
+  };
+  auto pack_in = [&](float c0, float c1, float c2) {
+    u32x4 v = {pack_bf16(c0 * a.in_scale, c1 * a.in_scale), pack_bf16(c2 * a.in_scale, 0.0f), 0u, 0u};
+    return v;
+  };
+  auto stage_input = [&](int t) {
+    input_vox(t, [&](int, int hv, bool inz, int64_t o) {
+      sX[hv] = inz ? pack_in(a.inf[0][o], a.inf[1][o], a.inf[2][o]) : pack_in(0.0f, 0.0f, 0.0f);
+    });
+  };
+  auto prefetch_input = [&](int t) {
+    input_vox(t, [&](int k, int, bool inz, int64_t o) {
+      pin[3 * k] = inz ? a.inf[0][o] : 0.0f;
+      pin[3 * k + 1] = inz ? a.inf[1][o] : 0.0f;
+      pin[3 * k + 2] = inz ? a.inf[2][o] : 0.0f;
+    });
+  };
+  auto place_input = [&](int t) {
+    input_vox(t, [&](int k, int hv, bool, int64_t) { sX[hv] = pack_in(pin[3 * k], pin[3 * k + 1], pin[3 * k + 2]); });
+  };
 
+  int t = blockIdx.x;
+  if (t >= ntile) return;
+  if (INMODE == 0) stage_direct_all(t);
+  else stage_input(t);
   __syncthreads();
+
+  for (; t < ntile; t += gridDim.x) {
+  const int tn = t + (int)gridDim.x;
+  if (tn < ntile) {
+    if (INMODE == 0) prefetch(tn);
+    else prefetch_input(tn);
+  }
+  int b = t;
+  const int bx = b % nbx;
+  b /= nbx;
+  const int by = b % nby, bz = b / nby;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
 
   // RR rows of 16 voxels at a time: RR independent accumulator chains and RR
   // LDS reads in flight per k-step
@@ -281,6 +353,17 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       }
     }
   }
+  if (tn < ntile) {
+    __syncthreads();
+    if (INMODE == 0) {
+      place(tn);
+      if (PU < U) stage_rest(tn);
+    } else {
+      place_input(tn);
+    }
+    __syncthreads();
+  }
+  }  // tiles of this work-group
 }
 
 // ---------------------------------------------------------------------------
@@ -691,6 +774,18 @@ static int check_box(gempic_dn* d, int Z, int Y, int X) {
   return GEMPIC_OK;
 }
 
+// k_conv runs persistent work-groups: as many as can be resident at once
+// (occupancy x compute units), each walking its share of the output tiles
+template <typename K>
+static unsigned conv_grid(K kernel, unsigned ntile) {
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0);
+  unsigned n = (unsigned)(std::max(1, per) * std::max(1, cus));
+  return std::min(ntile, n);
+}
+
 static unsigned conv_blocks(int Z, int Y, int X) {
   return (unsigned)((X / TX) * (Y / TY) * ((Z + TZ - 1) / TZ));
 }
@@ -734,14 +829,14 @@ static void net_forward(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const 
   for (int q = 0; q < 3; ++q) a.inf[q] = J[q];
   a.in_scale = in_scale;
   a.wp = d->fw[0]; a.bias = bias_of(d, 0); a.out = acts[0];
-  k_conv<8, 16, 1, 0><<<nb, 256, 0, s>>>(a);
+  k_conv<8, 16, 1, 0><<<conv_grid(k_conv<8, 16, 1, 0>, nb), 256, 0, s>>>(a);
   a.in = (const u32x4*)acts[0]; a.wp = d->fw[1]; a.bias = bias_of(d, 1); a.out = acts[1];
-  k_conv<16, 32, 0, 0><<<nb, 256, 0, s>>>(a);
+  k_conv<16, 32, 0, 0><<<conv_grid(k_conv<16, 32, 0, 0>, nb), 256, 0, s>>>(a);
   a.in = (const u32x4*)acts[1]; a.wp = d->fw[2]; a.bias = bias_of(d, 2); a.out = acts[2];
-  k_conv<32, 16, 0, 0><<<nb, 256, 0, s>>>(a);
+  k_conv<32, 16, 0, 0><<<conv_grid(k_conv<32, 16, 0, 0>, nb), 256, 0, s>>>(a);
   a.in = (const u32x4*)acts[2]; a.wp = d->fw[3]; a.bias = bias_of(d, 3); a.out = nullptr;
   for (int q = 0; q < 3; ++q) a.outf[q] = Aout[q];
-  k_conv<16, 16, 0, 1><<<nb, 256, 0, s>>>(a);
+  k_conv<16, 16, 0, 1><<<conv_grid(k_conv<16, 16, 0, 1>, nb), 256, 0, s>>>(a);
 }
 
 static void filter(hipStream_t s, int Z, int Y, int X, const float* const in[3], float* const out[3],
@@ -884,21 +979,21 @@ static void train_crop(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const f
   for (int q = 0; q < 3; ++q) c.inf[q] = gA[q];
   c.in_scale = 1.0f;
   c.wp = d->bw[3]; c.mask = d->tact[2]; c.out = d->gact[2];
-  k_conv<8, 16, 1, 2><<<nb, 256, 0, s>>>(c);
+  k_conv<8, 16, 1, 2><<<conv_grid(k_conv<8, 16, 1, 2>, nb), 256, 0, s>>>(c);
   // layer 3: gy = g3 (16 ch), x = act2 (32 ch)
   w.x = (const u32x4*)d->tact[1];
   w.gy = (const u32x4*)d->gact[2];
   w.gW = gW[2]; w.gb = gb[2];
   k_wgrad<32, 16, 32, 16, 0, 0><<<nb, 256, 0, s>>>(w);
   c.in = (const u32x4*)d->gact[2]; c.wp = d->bw[2]; c.mask = d->tact[1]; c.out = d->gact[1];
-  k_conv<16, 32, 0, 2><<<nb, 256, 0, s>>>(c);
+  k_conv<16, 32, 0, 2><<<conv_grid(k_conv<16, 32, 0, 2>, nb), 256, 0, s>>>(c);
   // layer 2: gy = g2 (32 ch), x = act1 (16 ch)
   w.x = (const u32x4*)d->tact[0];
   w.gy = (const u32x4*)d->gact[1];
   w.gW = gW[1]; w.gb = gb[1];
   k_wgrad<16, 32, 16, 32, 0, 0><<<nb, 256, 0, s>>>(w);
   c.in = (const u32x4*)d->gact[1]; c.wp = d->bw[1]; c.mask = d->tact[0]; c.out = d->gact[0];
-  k_conv<32, 16, 0, 2><<<nb, 256, 0, s>>>(c);
+  k_conv<32, 16, 0, 2><<<conv_grid(k_conv<32, 16, 0, 2>, nb), 256, 0, s>>>(c);
   // layer 1: gy = g1 (16 ch), x = J / n_e (planar)
   w.x = nullptr;
   for (int q = 0; q < 3; ++q) w.xf[q] = Jr[q];
