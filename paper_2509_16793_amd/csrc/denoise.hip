@@ -143,6 +143,10 @@ struct ConvArgs {
   const unsigned short* mask;
 };
 
+// 16 zero bytes: the source of halo voxels outside the box for direct
+// global-to-LDS loads
+__device__ u32x4 g_zero16;
+
 template <int CINP, int COUTP, int INMODE, int OUTMODE>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   constexpr int U = CINP / 8;               // 16-byte units per voxel
@@ -153,13 +157,22 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   // halo tile, unit-major: sX[unit * HALO_P + voxel], so that the 16 lanes of
   // a lane group read 16 consecutive 16-byte units; the unit stride is padded
   // so that the units start on different banks
-  constexpr int HALO_P = HALO + 2;
-  __shared__ u32x4 sX[HALO_P * U];
+  // DIRECT (two-unit inputs, 32 output channels): two halo buffers; the next
+  // tile's halo is read straight from global memory into the other buffer
+  // (global_load_lds, 64 voxels of one unit per wave instruction) while the
+  // current one is used.  (With 16 output channels the second buffer would cost
+  // a wave per SIMD: there the registers take part of the halo instead.)
+  constexpr bool DIRECT = INMODE == 0 && U == 2 && COUTP == 32;
+  constexpr int NCH = (HALO + 63) / 64;     // 64-voxel chunks per unit
+  constexpr int HALO_P = (DIRECT ? NCH * 64 : HALO) + 2;
+  __shared__ u32x4 sXbuf[(DIRECT ? 2 : 1) * HALO_P * U];
+  u32x4* sX = sXbuf;
 
   // Persistent work-groups walk the output tiles t = blockIdx.x, + gridDim.x,
-  // ...  (INMODE 0) The first PU channel units of the next tile's halo are
-  // read into registers while the current tile is computed, the rest after
-  // it; the weights are loaded once per work-group.
+  // ...  The weights are loaded once per work-group.  The next tile's halo is
+  // fetched while the current tile is computed: directly into the other LDS
+  // buffer (DIRECT), else its first PU channel units (INMODE 0) or its FP32
+  // input planes (INMODE 1) into registers, the rest after the tile.
   const int nbx = a.X / TX, nby = a.Y / TY;
   const int ntile = nbx * nby * ((a.Z + TZ - 1) / TZ);
   const int tid = threadIdx.x;
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     }
   };
   constexpr int NPR = (HZ * HY + 256 / (HX * PU) - 1) / (256 / (HX * PU));
-  u32x4 pre[INMODE == 0 ? NPR : 1];
+  u32x4 pre[INMODE == 0 && !DIRECT ? NPR : 1];
   using IC0 = std::integral_constant<int, 0>;
   using ICPU = std::integral_constant<int, PU>;
   using ICU = std::integral_constant<int, U>;
@@ -262,16 +275,49 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     input_vox(t, [&](int k, int hv, bool, int64_t) { sX[hv] = pack_in(pin[3 * k], pin[3 * k + 1], pin[3 * k + 2]); });
   };
 
+  auto direct_load = [&](int t, u32x4* dst) {
+    int b = t;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby, bz = b / nby;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    for (int c = wave; c < U * NCH; c += 4) {
+      const int u = c / NCH, ch = c - u * NCH;
+      const int hv = ch * 64 + lane;
+      const u32x4* src = &g_zero16;
+      if (hv < HALO) {
+        const int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+        const int gz = z0 + hz - 1;
+        if (gz >= 0 && gz < a.Z) {
+          const int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
+          src = a.in + ((((int64_t)gz * a.Y + gy) * a.X + gx) * U + u);
+        }
+      }
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)(dst + u * HALO_P + ch * 64),
+                                       16, 0, 0);
+    }
+  };
+
   int t = blockIdx.x;
   if (t >= ntile) return;
-  if (INMODE == 0) stage_direct_all(t);
-  else stage_input(t);
+  int buf = 0;
+  if (DIRECT) {
+    direct_load(t, sXbuf);
+    __builtin_amdgcn_s_waitcnt(0);
+  } else if (INMODE == 0) {
+    stage_direct_all(t);
+  } else {
+    stage_input(t);
+  }
   __syncthreads();
 
   for (; t < ntile; t += gridDim.x) {
   const int tn = t + (int)gridDim.x;
+  sX = sXbuf + buf * (HALO_P * U);
   if (tn < ntile) {
-    if (INMODE == 0) prefetch(tn);
+    if (DIRECT) direct_load(tn, sXbuf + (buf ^ 1) * (HALO_P * U));
+    else if (INMODE == 0) prefetch(tn);
     else prefetch_input(tn);
   }
   int b = t;
@@ -354,14 +400,21 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     }
   }
   if (tn < ntile) {
-    __syncthreads();
-    if (INMODE == 0) {
-      place(tn);
-      if (PU < U) stage_rest(tn);
+    if (DIRECT) {
+      // own loads done, then every wave's loads and every read of this buffer
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      buf ^= 1;
     } else {
-      place_input(tn);
+      __syncthreads();
+      if (INMODE == 0) {
+        place(tn);
+        if (PU < U) stage_rest(tn);
+      } else {
+        place_input(tn);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   }  // tiles of this work-group
 }
