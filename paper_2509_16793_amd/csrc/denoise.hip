@@ -50,10 +50,15 @@ int64_t layer_woff(int l) {
   return o;
 }
 int64_t n_params() { return layer_woff(NLAYER); }
+// 32-channel inputs are convolved in two phases of 16 channels (halves of
+// the halo tile in LDS, double-buffered); a phase reduces over 16 or fewer
+// channels
+GP_HD constexpr int conv_split(int cinp) { return cinp == 32 ? 2 : 1; }
 int64_t packed_units(int cinp, int coutp) {
-  int tpk = 32 / cinp;
-  int nks = (27 + tpk - 1) / tpk;
-  return (int64_t)nks * (coutp / 16) * 64;
+  int ce = cinp / conv_split(cinp);
+  int tpk = 32 / ce;
+  int nks = 3 * ((9 + tpk - 1) / tpk);
+  return (int64_t)conv_split(cinp) * nks * (coutp / 16) * 64;
 }
 
 constexpr int TZ = 4, TY = 8, TX = 16;        // output tile of one work-group
@@ -74,11 +79,6 @@ GP_DEV unsigned pack_bf16(float lo, float hi) {
   return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
 }
 
-// LDS voxel offset of tap t in a halo tile (the padding taps t > 26 read tap
-// 26 with zero weights); a constant for a constant t
-GP_HD constexpr int tap_off(int t) {
-  return t > 26 ? tap_off(26) : ((t / 9 - 1) * HY + ((t / 3) % 3 - 1)) * HX + (t % 3 - 1);
-}
 GP_DEV float bf2f(unsigned b) { return __uint_as_float(b << 16); }
 GP_DEV int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -100,11 +100,18 @@ __global__ void k_pack(PackArgs a) {
   int64_t r = u / 64;
   int nct = a.coutp / 16;
   int j = (int)(r % nct);
-  int s = (int)(r / nct);
+  r /= nct;
   int g = lane >> 4, n = lane & 15;
-  int tpk = 32 / a.cinp;
-  int tp = s * tpk + (g * 8) / a.cinp;      // tap of the packed convolution
-  int c0 = (g * 8) % a.cinp;
+  // phase p reduces over the packed input channels p ce .. p ce + ce - 1;
+  // its k-step s = 3 cg + (dy + 1) takes, in lane-group slot i, the (dz, dx)
+  // combination q = cg tpk + i (q > 8: zero padding) at that dy
+  int ce = a.cinp / conv_split(a.cinp);
+  int tpk = 32 / ce;
+  int nks = 3 * ((9 + tpk - 1) / tpk);
+  int s = (int)(r % nks), p = (int)(r / nks);
+  int q = (s / 3) * tpk + (g * 8) / ce;
+  int tp = q < 9 ? (q / 3) * 9 + (s % 3) * 3 + q % 3 : 27;   // tap of the packed convolution
+  int c0 = p * ce + (g * 8) % ce;
   int orow = 16 * j + n;                    // packed output channel
   unsigned w[8];
   for (int e = 0; e < 8; ++e) {
@@ -148,24 +155,30 @@ struct ConvArgs {
 __device__ u32x4 g_zero16;
 
 template <int CINP, int COUTP, int INMODE, int OUTMODE>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(ConvArgs a) {
   constexpr int U = CINP / 8;               // 16-byte units per voxel
-  constexpr int TPK = 32 / CINP;            // taps per k-step
-  constexpr int NKS = (27 + TPK - 1) / TPK;
+  constexpr int KS = conv_split(CINP);      // phases per tile
+  constexpr int CE = CINP / KS;             // channels of a phase
+  constexpr int UE = CE / 8;                // units of a phase (in LDS)
+  constexpr int TPK = 32 / CE;              // taps per k-step
+  constexpr int NCG = (9 + TPK - 1) / TPK;  // column groups of (dz, dx) combinations
+  constexpr int NKS = 3 * NCG;              // k-steps of a phase: (column group, dy)
   constexpr int NCT = COUTP / 16;
-  constexpr int RPW = TZ * TY / 4;          // 16-voxel rows per wave
+  static_assert(TZ == 4, "one output plane per wave");
   // halo tile, unit-major: sX[unit * HALO_P + voxel], so that the 16 lanes of
   // a lane group read 16 consecutive 16-byte units; the unit stride is padded
   // so that the units start on different banks
-  // DIRECT (two-unit inputs, 32 output channels): two halo buffers; the next
-  // tile's halo is read straight from global memory into the other buffer
+  // DIRECT (two-unit phases: 16-channel inputs with 32 output channels, and
+  // both halves of 32-channel inputs): two halo buffers; the next phase's
+  // halo is read straight from global memory into the other buffer
   // (global_load_lds, 64 voxels of one unit per wave instruction) while the
-  // current one is used.  (With 16 output channels the second buffer would cost
-  // a wave per SIMD: there the registers take part of the halo instead.)
-  constexpr bool DIRECT = INMODE == 0 && U == 2 && COUTP == 32;
+  // current one is used.  (16 -> 16 channels: the second buffer would cost a
+  // wave per SIMD; there the registers take part of the halo instead.)
+  constexpr bool DIRECT = INMODE == 0 && UE == 2 && (COUTP == 32 || KS == 2);
+  static_assert(KS == 1 || DIRECT, "split phases are double-buffered");
   constexpr int NCH = (HALO + 63) / 64;     // 64-voxel chunks per unit
   constexpr int HALO_P = (DIRECT ? NCH * 64 : HALO) + 2;
-  __shared__ u32x4 sXbuf[(DIRECT ? 2 : 1) * HALO_P * U];
+  __shared__ u32x4 sXbuf[(DIRECT ? 2 : 1) * HALO_P * UE];
   u32x4* sX = sXbuf;
 
   // Persistent work-groups walk the output tiles t = blockIdx.x, + gridDim.x,
@@ -177,11 +190,26 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   const int ntile = nbx * nby * ((a.Z + TZ - 1) / TZ);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-  bf16x8 wr[NKS][NCT];
+  bf16x8 wr[KS][NKS][NCT];
 #pragma unroll
-  for (int s = 0; s < NKS; ++s)
+  for (int p = 0; p < KS; ++p)
 #pragma unroll
-    for (int j = 0; j < NCT; ++j) wr[s][j] = __builtin_bit_cast(bf16x8, a.wp[(s * NCT + j) * 64 + lane]);
+    for (int s = 0; s < NKS; ++s)
+#pragma unroll
+      for (int j = 0; j < NCT; ++j)
+        wr[p][s][j] = __builtin_bit_cast(bf16x8, a.wp[((p * NKS + s) * NCT + j) * 64 + lane]);
+
+  // biases in registers: loaded from global memory in the epilogue, they
+  // would be reloaded after every output store (the pointers may alias) and
+  // each reload would wait for all outstanding stores and loads
+  float bias_r[NCT][4];
+#pragma unroll
+  for (int j = 0; j < NCT; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = 16 * j + 4 * g + i;
+      bias_r[j][i] = OUTMODE == 0 ? a.bias[co] : OUTMODE == 1 && j == 0 && i < 3 ? a.bias[i] : 0.0f;
+    }
 
   constexpr int PU = U >= 4 ? 2 : 1;        // units prefetched into registers (register budget)
   // staging of channel units [U0, U0 + UW): one halo row (HX voxels x UW
@@ -275,13 +303,14 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     input_vox(t, [&](int k, int hv, bool, int64_t) { sX[hv] = pack_in(pin[3 * k], pin[3 * k + 1], pin[3 * k + 2]); });
   };
 
-  auto direct_load = [&](int t, u32x4* dst) {
+  // units p UE .. p UE + UE - 1 of tile t's halo into dst
+  auto direct_load = [&](int t, int p, u32x4* dst) {
     int b = t;
     const int bx = b % nbx;
     b /= nbx;
     const int by = b % nby, bz = b / nby;
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-    for (int c = wave; c < U * NCH; c += 4) {
+    for (int c = wave; c < UE * NCH; c += 4) {
       const int u = c / NCH, ch = c - u * NCH;
       const int hv = ch * 64 + lane;
       const u32x4* src = &g_zero16;
@@ -290,7 +319,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         const int gz = z0 + hz - 1;
         if (gz >= 0 && gz < a.Z) {
           const int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
-          src = a.in + ((((int64_t)gz * a.Y + gy) * a.X + gx) * U + u);
+          src = a.in + ((((int64_t)gz * a.Y + gy) * a.X + gx) * U + p * UE + u);
         }
       }
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
@@ -303,7 +332,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   if (t >= ntile) return;
   int buf = 0;
   if (DIRECT) {
-    direct_load(t, sXbuf);
+    direct_load(t, 0, sXbuf);
     __builtin_amdgcn_s_waitcnt(0);
   } else if (INMODE == 0) {
     stage_direct_all(t);
@@ -313,67 +342,72 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
   __syncthreads();
 
   for (; t < ntile; t += gridDim.x) {
-  const int tn = t + (int)gridDim.x;
-  sX = sXbuf + buf * (HALO_P * U);
-  if (tn < ntile) {
-    if (DIRECT) direct_load(tn, sXbuf + (buf ^ 1) * (HALO_P * U));
-    else if (INMODE == 0) prefetch(tn);
-    else prefetch_input(tn);
-  }
   int b = t;
   const int bx = b % nbx;
   b /= nbx;
   const int by = b % nby, bz = b / nby;
   const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+  f32x4 acc[TY][NCT];
+#pragma unroll
+  for (int r = 0; r < TY; ++r)
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) acc[r][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int p = 0; p < KS; ++p) {
+  // the phase after this one: the next half of this tile, or the next tile
+  const bool last = p == KS - 1;
+  const int tn = last ? t + (int)gridDim.x : t;
+  sX = sXbuf + buf * (HALO_P * UE);
+  if (tn < ntile) {
+    if (DIRECT) direct_load(tn, last ? 0 : p + 1, sXbuf + (buf ^ 1) * (HALO_P * UE));
+    else if (INMODE == 0) prefetch(tn);
+    else prefetch_input(tn);
+  }
 
-  // RR rows of 16 voxels at a time: RR independent accumulator chains and RR
-  // LDS reads in flight per k-step
-  constexpr int RR = 4;
-  for (int it = 0; it < RPW; it += RR) {
-    f32x4 acc[RR][NCT];
-    int base[RR];
+  // Each wave computes the TY rows (16 x voxels each) of output plane
+  // z0 + wave.  The k-steps are ordered (column group cg, dy): column group
+  // cg holds the (dz, dx) combinations cg * TPK .. cg * TPK + TPK - 1, one per
+  // lane-group slot, so that the activation fragment read at halo row h serves
+  // the output rows h - 1 - dy for the three dy: NCG * (TY + 2) LDS reads per
+  // wave instead of one per k-step and row.
+  {
+    const int slot = (g * 8) / CE;          // this lane group's slot within a k-step
+    const int c0u = ((g * 8) % CE) / 8;     // and its 16-byte channel unit
+    const int lb = c0u * HALO_P + (wave + 1) * HY * HX + n + 1;
 #pragma unroll
-    for (int r = 0; r < RR; ++r) {
-      int rg = wave * RPW + it + r;
-      int zz = rg / TY, yy = rg - zz * TY;
-      base[r] = ((zz + 1) * HY + (yy + 1)) * HX + (n + 1);
+    for (int cg = 0; cg < NCG; ++cg) {
+      int q;
+      if (TPK == 1) q = cg;
+      else if (TPK == 2) q = slot ? 2 * cg + 1 : 2 * cg;
+      else q = slot == 0 ? 4 * cg : slot == 1 ? 4 * cg + 1 : slot == 2 ? 4 * cg + 2 : 4 * cg + 3;
+      q = q > 8 ? 8 : q;                    // padding slots (zero weights)
+      const int off = lb + (q / 3 - 1) * HY * HX + (q % 3 - 1);
 #pragma unroll
-      for (int j = 0; j < NCT; ++j) acc[r][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int h = 0; h < TY + 2; ++h) {
+        const bf16x8 f = __builtin_bit_cast(bf16x8, sX[off + h * HX]);
+#pragma unroll
+        for (int dyi = 0; dyi < 3; ++dyi) {
+          const int r = h - dyi;
+          if (r >= 0 && r < TY) {
+#pragma unroll
+            for (int j = 0; j < NCT; ++j)
+              acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[p][3 * cg + dyi][j], f, acc[r][j], 0, 0, 0);
+          }
+        }
+      }
     }
-    const int dt = (g * 8) / CINP;          // this lane group's tap within a k-step
-    const int c0u = ((g * 8) % CINP) / 8;   // and its 16-byte channel unit
-    int bb[RR];
+  }
+  if (last) {
+    const int z = z0 + wave;
 #pragma unroll
-    for (int r = 0; r < RR; ++r) bb[r] = c0u * HALO_P + base[r];
-#pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-      int toff;
-      if (TPK == 1) toff = tap_off(s);
-      else if (TPK == 2) toff = dt ? tap_off(2 * s + 1) : tap_off(2 * s);
-      else toff = dt == 0 ? tap_off(4 * s) : dt == 1 ? tap_off(4 * s + 1)
-                : dt == 2 ? tap_off(4 * s + 2) : tap_off(4 * s + 3);
-      const int off = toff;
-      bf16x8 bv[RR];
-#pragma unroll
-      for (int r = 0; r < RR; ++r) bv[r] = __builtin_bit_cast(bf16x8, sX[bb[r] + off]);
-#pragma unroll
-      for (int r = 0; r < RR; ++r)
-#pragma unroll
-        for (int j = 0; j < NCT; ++j)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[s][j], bv[r], acc[r][j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < RR; ++r) {
-      int rg = wave * RPW + it + r;
-      int zz = rg / TY, yy = rg - zz * TY;
-      int z = z0 + zz;
-      if (z >= a.Z) continue;
-      int64_t vox = ((int64_t)z * a.Y + (y0 + yy)) * a.X + (x0 + n);
+    for (int r = 0; r < TY; ++r) {
+      if (z >= a.Z) break;
+      int64_t vox = ((int64_t)z * a.Y + (y0 + r)) * a.X + (x0 + n);
       if (OUTMODE == 1) {
         if (g == 0) {
-          a.outf[0][vox] = acc[r][0][0] + a.bias[0];
-          a.outf[1][vox] = acc[r][0][1] + a.bias[1];
-          a.outf[2][vox] = acc[r][0][2] + a.bias[2];
+          a.outf[0][vox] = acc[r][0][0] + bias_r[0][0];
+          a.outf[1][vox] = acc[r][0][1] + bias_r[0][1];
+          a.outf[2][vox] = acc[r][0][2] + bias_r[0][2];
         }
       } else {
 #pragma unroll
@@ -382,7 +416,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
           float v[4];
           if (OUTMODE == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[r][j][i] + a.bias[co0 + i], 0.0f);
+            for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[r][j][i] + bias_r[j][i], 0.0f);
           } else {
             u32x2 m = *(const u32x2*)(a.mask + vox * COUTP + co0);
 #pragma unroll
@@ -416,6 +450,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
       __syncthreads();
     }
   }
+  }  // phases
   }  // tiles of this work-group
 }
 
@@ -575,30 +610,55 @@ struct Box {
 struct P3 { const float* p[3]; };
 struct W3 { float* p[3]; };
 
-// one 1-2-1 pass along x, y (periodic) and zeta (zero outside)
-__global__ void k_filter(Box B, P3 in, W3 out) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t nv = (int64_t)B.Z * B.Y * B.X;
-  if (v >= nv) return;
-  int x = (int)(v % B.X);
-  int64_t r = v / B.X;
-  int y = (int)(r % B.Y), z = (int)(r / B.Y);
-  const float w[3] = {0.25f, 0.5f, 0.25f};
-  for (int c = 0; c < 3; ++c) {
-    float acc = 0.0f;
-    for (int dz = -1; dz <= 1; ++dz) {
-      int zz = z + dz;
-      if (zz < 0 || zz >= B.Z) continue;
-      float sy = 0.0f;
-      for (int dy = -1; dy <= 1; ++dy) {
-        int yy = wrapi(y + dy, B.Y);
-        const float* row = in.p[c] + B.at(zz, yy, 0);
-        float sx = 0.25f * row[wrapi(x - 1, B.X)] + 0.5f * row[x] + 0.25f * row[wrapi(x + 1, B.X)];
-        sy += w[dy + 1] * sx;
+// one 1-2-1 pass along x, y (periodic) and zeta (zero beyond the planes).
+// A thread takes an FY-row y strip of one x column of one component
+// (blockIdx.z) through FZ planes: the x- then y-filtered rows of the planes
+// z - 1 and z stay in registers, so that every input row is read once per
+// plane (plus the two halo rows).
+constexpr int FY = 4, FZ = 8;
+
+__global__ __launch_bounds__(256) void k_filter(Box B, P3 in, W3 out) {
+  const int ncol = B.X * (B.Y / FY);
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= ncol) return;
+  const int x = w % B.X, y0 = (w / B.X) * FY;
+  const int z0 = blockIdx.y * FZ;
+  const int c = blockIdx.z;
+  const int xl = wrapi(x - 1, B.X), xr = wrapi(x + 1, B.X);
+  const int64_t plane = (int64_t)B.Y * B.X;
+  {
+    float a[FY], b[FY];
+#pragma unroll
+    for (int j = 0; j < FY; ++j) a[j] = b[j] = 0.0f;
+#pragma unroll
+    for (int k = -1; k <= FZ; ++k) {
+      const int z = z0 + k;
+      float s[FY];
+      if (z >= 0 && z < B.Z) {
+        const float* p = in.p[c] + z * plane;
+        float r[FY + 2];
+#pragma unroll
+        for (int j = 0; j < FY + 2; ++j) {
+          const float* row = p + wrapi(y0 + j - 1, B.Y) * B.X;
+          r[j] = 0.25f * row[xl] + 0.5f * row[x] + 0.25f * row[xr];
+        }
+#pragma unroll
+        for (int j = 0; j < FY; ++j) s[j] = 0.25f * r[j] + 0.5f * r[j + 1] + 0.25f * r[j + 2];
+      } else {
+#pragma unroll
+        for (int j = 0; j < FY; ++j) s[j] = 0.0f;
       }
-      acc += w[dz + 1] * sy;
+      if (k >= 1 && z - 1 < B.Z) {
+        float* q = out.p[c] + (z - 1) * plane + (int64_t)y0 * B.X + x;
+#pragma unroll
+        for (int j = 0; j < FY; ++j) q[j * B.X] = 0.25f * a[j] + 0.5f * b[j] + 0.25f * s[j];
+      }
+#pragma unroll
+      for (int j = 0; j < FY; ++j) {
+        a[j] = b[j];
+        b[j] = s[j];
+      }
     }
-    out.p[c][v] = acc;
   }
 }
 
@@ -635,32 +695,63 @@ GP_DEV double block_sum_d(double v, double* sh) {
 
 // Jd = Jf + s curl(A); per-block partial sums of |D.(s curl A)|^2 and
 // |D.Jf|^2 into part[2 * block + {0, 1}] (a fixed grid of COMB_BLOCKS
-// blocks strides over the box, so that the sums need no global atomics)
+// blocks strides over the work, so that the sums need no global atomics).
+// A work item is one (x, y) column through CZ planes: the values of plane
+// z - 1 that the curl and the divergences need are carried in registers.
 constexpr int COMB_BLOCKS = 2048;
+constexpr int CZ = 8;
 
 __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd, double* part) {
   __shared__ double sh[4];
   const Box& B = a.B;
-  int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  const int ncol = B.X * B.Y;
+  const int nwork = ncol * ((B.Z + CZ - 1) / CZ);
+  const int64_t plane = ncol;
   double num = 0.0, den = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    int x = (int)(v % B.X);
-    int64_t r = v / B.X;
-    int y = (int)(r % B.Y), z = (int)(r / B.Y);
-    float c[3], cx[3], cy[3], cz[3];
-    curl_at(a, A, z, y, x, c);
-    curl_at(a, A, z, y, wrapi(x - 1, B.X), cx);
-    curl_at(a, A, z, wrapi(y - 1, B.Y), x, cy);
-    curl_at(a, A, z - 1, y, x, cz);
-    for (int q = 0; q < 3; ++q) Jd.p[q][v] = Jf.p[q][v] + c[q];
-    double dc = (double)(c[0] - cx[0]) * a.ihx + (double)(c[1] - cy[1]) * a.ihy + (double)(c[2] - cz[2]) * a.ih;
-    int64_t vx = B.at(z, y, wrapi(x - 1, B.X)), vy = B.at(z, wrapi(y - 1, B.Y), x);
-    float fz = z > 0 ? Jf.p[2][B.at(z - 1, y, x)] : 0.0f;
-    double df = (double)(Jf.p[0][v] - Jf.p[0][vx]) * a.ihx + (double)(Jf.p[1][v] - Jf.p[1][vy]) * a.ihy +
-                (double)(Jf.p[2][v] - fz) * a.ih;
-    num += dc * dc;
-    den += df * df;
+  for (int w = blockIdx.x * 256 + threadIdx.x; w < nwork; w += gridDim.x * 256) {
+    const int col = w % ncol, z0 = (w / ncol) * CZ;
+    const int x = col % B.X, y = col / B.X;
+    const int xm = wrapi(x - 1, B.X), ym = wrapi(y - 1, B.Y);
+    const int cx = y * B.X + xm, cy = ym * B.X + x, cxy = ym * B.X + xm;
+    // plane z0 - 1 (zero below the box): A_x at (y, x) and (y - 1, x),
+    // A_y at (y, x) and (y, x - 1), z-component of the curl and Jf_z
+    float pax = 0.0f, paxy = 0.0f, pay = 0.0f, payx = 0.0f, pc2 = 0.0f, pj2 = 0.0f;
+    if (z0 > 0) {
+      const int64_t o = (z0 - 1) * plane;
+      pax = A.p[0][o + col];
+      paxy = A.p[0][o + cy];
+      pay = A.p[1][o + col];
+      payx = A.p[1][o + cx];
+      pc2 = a.s * ((pay - payx) * a.ihx - (pax - paxy) * a.ihy);
+      pj2 = Jf.p[2][o + col];
+    }
+    const int zend = min(z0 + CZ, B.Z);
+    for (int z = z0; z < zend; ++z) {
+      const int64_t o = z * plane;
+      const float ax = A.p[0][o + col], ay = A.p[1][o + col], az = A.p[2][o + col];
+      const float axy = A.p[0][o + cy], ayx = A.p[1][o + cx];
+      const float azx = A.p[2][o + cx], azy = A.p[2][o + cy], azxy = A.p[2][o + cxy];
+      const float c0 = a.s * ((az - azy) * a.ihy - (ay - pay) * a.ih);
+      const float c1 = a.s * ((ax - pax) * a.ih - (az - azx) * a.ihx);
+      const float c2 = a.s * ((ay - ayx) * a.ihx - (ax - axy) * a.ihy);
+      const float c0x = a.s * ((azx - azxy) * a.ihy - (ayx - payx) * a.ih);   // c0 at x - 1
+      const float c1y = a.s * ((axy - paxy) * a.ih - (azy - azxy) * a.ihx);   // c1 at y - 1
+      const float j0 = Jf.p[0][o + col], j1 = Jf.p[1][o + col], j2 = Jf.p[2][o + col];
+      Jd.p[0][o + col] = j0 + c0;
+      Jd.p[1][o + col] = j1 + c1;
+      Jd.p[2][o + col] = j2 + c2;
+      const double dc = (double)(c0 - c0x) * a.ihx + (double)(c1 - c1y) * a.ihy + (double)(c2 - pc2) * a.ih;
+      const double df = (double)(j0 - Jf.p[0][o + cx]) * a.ihx + (double)(j1 - Jf.p[1][o + cy]) * a.ihy +
+                        (double)(j2 - pj2) * a.ih;
+      num += dc * dc;
+      den += df * df;
+      pax = ax;
+      paxy = axy;
+      pay = ay;
+      payx = ayx;
+      pc2 = c2;
+      pj2 = j2;
+    }
   }
   double tn = block_sum_d(num, sh);
   __syncthreads();
@@ -824,6 +915,8 @@ static int dn_fail(gempic_dn* d, int code, const std::string& m) {
 static int check_box(gempic_dn* d, int Z, int Y, int X) {
   if (Z < 1 || Y < TY || X < TX || Y % TY || X % TX)
     return dn_fail(d, GEMPIC_EINVAL, "box must have Z >= 1, Y a multiple of 8 and X a multiple of 16");
+  if ((int64_t)X * Y * ((Z + CZ - 1) / CZ) >= (int64_t(1) << 31) - (int64_t(COMB_BLOCKS) << 8))
+    return dn_fail(d, GEMPIC_EINVAL, "box too large for the denoiser: X * Y * ceil(Z / 8) must stay below 2^31");
   return GEMPIC_OK;
 }
 
@@ -901,12 +994,13 @@ static void filter(hipStream_t s, int Z, int Y, int X, const float* const in[3],
     for (int q = 0; q < 3; ++q) (void)hipMemcpyAsync(out[q], in[q], nv * 4, hipMemcpyDeviceToDevice, s);
     return;
   }
+  dim3 grid(nblk((int64_t)X * (Y / FY), 256), (unsigned)((Z + FZ - 1) / FZ), 3);
   if (passes == 1) {
-    k_filter<<<nblk(nv, 256), 256, 0, s>>>(B, pi, W3{{out[0], out[1], out[2]}});
+    k_filter<<<grid, 256, 0, s>>>(B, pi, W3{{out[0], out[1], out[2]}});
     return;
   }
-  k_filter<<<nblk(nv, 256), 256, 0, s>>>(B, pi, W3{{tmp[0], tmp[1], tmp[2]}});
-  k_filter<<<nblk(nv, 256), 256, 0, s>>>(B, P3{{tmp[0], tmp[1], tmp[2]}}, W3{{out[0], out[1], out[2]}});
+  k_filter<<<grid, 256, 0, s>>>(B, pi, W3{{tmp[0], tmp[1], tmp[2]}});
+  k_filter<<<grid, 256, 0, s>>>(B, P3{{tmp[0], tmp[1], tmp[2]}}, W3{{out[0], out[1], out[2]}});
 }
 
 int dn_reserve(gempic_dn* d, int64_t nv) {

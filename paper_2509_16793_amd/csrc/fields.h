@@ -200,7 +200,7 @@ __global__ void k_interleave(T* rec, const T* in, int q, int64_t n) {
 // Transform along y (columns), in place: data[planes][Ny][Nxh]; a work-group
 // takes ncol consecutive kx columns of one plane.  Inverse scales by 1/Ny.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_y(cplx<T>* data, int Ny, int Nxh, int ncol,
+__global__ __launch_bounds__(512) void k_fft_y(cplx<T>* data, int Ny, int Nxh, int ncol,
                                                const cplx<T>* tw, int inverse) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs<T> a) {
   // Node n uses its old state and the raw current plane n + 1 - P, both
   // loaded PD nodes ahead into ring slot (Nz - 1 - n) mod PD (the loop is
   // unrolled by PD so that every slot index is static).
-  constexpr int PD = 4;
+  constexpr int PD = sizeof(T) == 4 ? 8 : 4;
   cplx<T> S[PD][4], Pl[PD][3];
 #pragma unroll
   for (int i = 0; i < PD; ++i) {

@@ -233,13 +233,13 @@ struct Impl {
     const Geom& G = g->g;
     int64_t rows = planes * G.Ny;
     int64_t pairs = (rows + 1) / 2;
-    int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / G.Nx));
+    int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 1024 / G.Nx));
     size_t sh = (2 * (size_t)nseq + 1) * G.Nx * sizeof(C);
     k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
     if (G.Ny > 1) {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
       size_t sh2 = (2 * (size_t)ncol + 1) * G.Ny * sizeof(C);
-      k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 256, sh2, g->s>>>(out, G.Ny, G.Nxh, ncol,
+      k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 512, sh2, g->s>>>(out, G.Ny, G.Nxh, ncol,
                                                                        (const C*)g->twy, 0);
     }
   }
@@ -250,7 +250,7 @@ struct Impl {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
       size_t sh2 = (2 * (size_t)ncol + 1) * G.Ny * sizeof(C);
       for (int q = 0; q < 6; ++q)
-        k_fft_y<T><<<(unsigned)((int64_t)G.Nz * (G.Nxh / ncol)), 256, sh2, g->s>>>(
+        k_fft_y<T><<<(unsigned)((int64_t)G.Nz * (G.Nxh / ncol)), 512, sh2, g->s>>>(
             (C*)g->outs[q], G.Ny, G.Nxh, ncol, (const C*)g->twy, 1);
     }
     int64_t rows = (int64_t)G.Nz * G.Ny;

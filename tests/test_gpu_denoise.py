@@ -65,13 +65,17 @@ def test_forward_matches_oracle(shape):
     assert _rel(Jq, Jf) > 1e-2
 
 
-def test_fallback_returns_filtered_current():
+# shapes: one plane; planes and rows that fill the filter's 8-plane chunks and
+# 8-row strips exactly; a ragged last chunk with x wider than a wavefront
+@pytest.mark.parametrize("shape,passes", [((6, 8, 16), 2), ((1, 8, 16), 1), ((16, 16, 32), 1),
+                                          ((19, 24, 80), 2), ((19, 24, 80), 0)])
+def test_fallback_returns_filtered_current(shape, passes):
     theta = workloads.denoiser_init(seed=12, last_scale=1.0, bias_scale=0.05)
-    J = _current((6, 8, 16), 2)
+    J = _current(shape, 2)
     d = Denoiser(theta)
-    Jout, used, rel = d.apply(_dev(J), N_E, H, passes=2, threshold=-1.0)
+    Jout, used, rel = d.apply(_dev(J), N_E, H, passes=passes, threshold=-1.0)
     assert not used
-    assert _rel(Jout.cpu().numpy(), dn.binomial(J.astype(np.float64), 2)) < 1e-6
+    assert _rel(Jout.cpu().numpy(), dn.binomial(J.astype(np.float64), passes)) < 1e-6
 
 
 def test_gradient_matches_oracle():
