@@ -81,7 +81,9 @@ typedef enum {
 typedef struct {
   int32_t abi_version;      /* must equal GEMPIC_ABI_VERSION                            */
   int32_t dims;             /* 2 = (x, zeta), 3 = (x, y, zeta)                          */
-  int32_t n[3];             /* Nx, Ny (ignored in 2-D), Nzeta: powers of two, >= 2      */
+  int32_t n[3];             /* Nx, Ny (ignored in 2-D), Nzeta: powers of two, >= 2;
+                               Nx <= 512 in FP64 and <= 1024 in FP32, Ny <= 2048 (the
+                               transverse transforms hold whole rows in LDS)            */
   double  d[3];             /* hx, hy (ignored in 2-D), h (zeta step), config units     */
   double  length_unit;      /* > 0                                                      */
   double  dtau;             /* slow step, config units; 0 selects h / 2.  2 dtau > h or

@@ -104,44 +104,6 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const T* in, cplx<T>* out, in
   }
 }
 
-// Inverse of k_fft_x_r2c (scaled by 1/Nx): in[rows][Nxh] -> out[rows][Nx].
-template <typename T>
-__global__ __launch_bounds__(256) void k_fft_x_c2r(const cplx<T>* in, T* out, int64_t rows, int Nx,
-                                                   int nseq, const cplx<T>* tw) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* y = x + nseq * Nx;
-  cplx<T>* tl = y + nseq * Nx;
-  int64_t pair0 = (int64_t)blockIdx.x * nseq;
-  int Nxh = Nx >> 1;
-  for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
-    int sq = idx / Nx, n = idx - sq * Nx;
-    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
-    cplx<T> z = mk((T)0, (T)0);
-    if (n < Nxh) {
-      cplx<T> A = r0 < rows ? in[r0 * Nxh + n] : mk((T)0, (T)0);
-      cplx<T> B = r1 < rows ? in[r1 * Nxh + n] : mk((T)0, (T)0);
-      z = A + mul_i(B);
-    } else if (n > Nxh) {
-      int k = Nx - n;
-      cplx<T> A = r0 < rows ? in[r0 * Nxh + k] : mk((T)0, (T)0);
-      cplx<T> B = r1 < rows ? in[r1 * Nxh + k] : mk((T)0, (T)0);
-      z = conj(A) + mul_i(conj(B));
-    }
-    x[idx] = z;
-  }
-  __syncthreads();
-  cplx<T>* Z = lds_fft(x, y, tl, Nx, nseq, tw, true);
-  T sc = (T)1 / (T)Nx;
-  for (int idx = threadIdx.x; idx < nseq * Nx; idx += blockDim.x) {
-    int sq = idx / Nx, n = idx - sq * Nx;
-    int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
-    cplx<T> z = Z[idx];
-    if (r0 < rows) out[r0 * Nx + n] = sc * z.x;
-    if (r1 < rows) out[r1 * Nx + n] = sc * z.y;
-  }
-}
-
 // Inverse of the x transform for the six field components at once, written
 // as interleaved node records out[row][Nx][6] (scaled by 1/Nx).
 template <typename T>

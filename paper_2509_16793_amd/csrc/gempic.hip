@@ -790,6 +790,11 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->NT = G->nTx * G->nTy * G->nTz;
   G->Nxh = G->Nx / 2;
   if ((int64_t)G->Nzp * G->Ny * G->Nx >= (1ll << 30)) { *why = "grid too large: cells must stay below 2^30"; return GEMPIC_EINVAL; }
+  // the transverse transforms hold whole rows of six components in LDS
+  if (G->Nx > (c->precision == GEMPIC_FP64 ? 512 : 1024) || G->Ny > 2048) {
+    *why = "transverse grid too large: Nx <= 512 (FP64) or 1024 (FP32), Ny <= 2048";
+    return GEMPIC_EINVAL;
+  }
   if (c->beam_np < 0) { *why = "beam_np must be >= 0"; return GEMPIC_EINVAL; }
   if (c->beam_np > 0) {
     if (c->dims != 3) { *why = "a driver beam needs dims = 3"; return GEMPIC_EINVAL; }

@@ -78,3 +78,21 @@ def test_quiet_plasma_interior_current_vanishes():
     F = g.fields()
     assert max(np.abs(v[3:]).max() for v in F.values()) < 1e-14
     _check(cfg, 6)
+
+
+# configurations the library rejects at creation, each with the reason it
+# names: a grid size that is not a power of two, a tile shape it does not
+# support, a slow step beyond h / 2, and a transverse grid wider than the LDS
+# transforms hold (FP64 rows of 1024 nodes)
+@pytest.mark.parametrize("n,change,why", [
+    ((24, 32, 64), {}, "powers of two"),
+    ((16, 16, 32), {"tile": [4, 4, 8]}, "tile must be"),
+    ((16, 16, 32), {"dtau": 0.8 * 0.05}, "slow step too large"),
+    ((1024, 8, 32), {}, "transverse grid too large"),
+])
+def test_invalid_configurations_are_rejected(n, change, why):
+    from paper_2509_16793_amd.gempic import GempicError
+    cfg = workloads.small3d(precision="fp64", n=n, steps=1)
+    cfg.update(change)
+    with pytest.raises(GempicError, match=why):
+        Sim(cfg)
