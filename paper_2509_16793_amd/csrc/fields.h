@@ -15,10 +15,13 @@
 // input, y is the ping-pong buffer; the pointer to the result is returned.
 // tl (LDS, N entries) receives the full circle of twiddles exp(-2 pi i t / N)
 // from tw (global, t < N/2); the inverse uses their conjugates (no scaling).
+// Sequence sq starts at element sq * S of x and y (S >= N; a padded stride
+// spreads column-wise accesses over the LDS banks).
 // Every thread of the block must call it (it synchronises).
 template <typename T>
 GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, cplx<T>* tl, int N, int nseq, const cplx<T>* tw,
-                        bool inverse) {
+                        bool inverse, int S = 0) {
+  if (S < N) S = N;
   const int half = N >> 1;
   for (int t = threadIdx.x; t < N; t += blockDim.x) {
     cplx<T> w = tw[t < half ? t : t - half];
@@ -34,7 +37,7 @@ GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, cplx<T>* tl, int N, int nseq, co
     for (int idx = threadIdx.x; idx < nseq * q4; idx += blockDim.x) {
       int sq = idx / q4, j = idx - sq * q4;
       int k = j & (Ns - 1);
-      const cplx<T>* xs = x + sq * N;
+      const cplx<T>* xs = x + sq * S;
       int ts = k * step;
       cplx<T> a0 = xs[j];
       cplx<T> a1 = tl[ts] * xs[j + q4];
@@ -42,7 +45,7 @@ GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, cplx<T>* tl, int N, int nseq, co
       cplx<T> a3 = tl[3 * ts] * xs[j + 3 * q4];
       cplx<T> b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3, b3 = a1 - a3;
       cplx<T> ib3 = mul_i(b3);
-      cplx<T>* ys = y + sq * N;
+      cplx<T>* ys = y + sq * S;
       int d = ((j - k) << 2) + k;
       ys[d] = b0 + b2;
       ys[d + Ns] = inverse ? b1 + ib3 : b1 - ib3;
@@ -57,10 +60,10 @@ GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, cplx<T>* tl, int N, int nseq, co
     for (int idx = threadIdx.x; idx < nseq * half; idx += blockDim.x) {
       int sq = idx / half, j = idx - sq * half;
       int k = j & (Ns - 1);
-      const cplx<T>* xs = x + sq * N;
+      const cplx<T>* xs = x + sq * S;
       cplx<T> a = xs[j];
       cplx<T> b = tl[k * (half / Ns)] * xs[j + half];
-      cplx<T>* ys = y + sq * N;
+      cplx<T>* ys = y + sq * S;
       int d = ((j - k) << 1) + k;
       ys[d] = a + b;
       ys[d + Ns] = a - b;
@@ -117,33 +120,43 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r6(const cplx<T>* i0, const cpl
   cplx<T>* tl = y + 6 * nseq * Nx;
   int64_t pair0 = (int64_t)blockIdx.x * nseq;
   int Nxh = Nx >> 1;
-  for (int idx = threadIdx.x; idx < 6 * nseq * Nx; idx += blockDim.x) {
-    int sq6 = idx / Nx, n = idx - sq6 * Nx;
+  // spectrum k of both rows gives the Hermitian pair n = k and n = Nx - k
+  // (each input read once); the Nyquist entry n = Nxh is zero
+  for (int idx = threadIdx.x; idx < 6 * nseq * Nxh; idx += blockDim.x) {
+    int sq6 = idx / Nxh, k = idx - sq6 * Nxh;
     int q = sq6 / nseq, sq = sq6 - q * nseq;
     int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
-    cplx<T> z = mk((T)0, (T)0);
-    if (n < Nxh) {
-      cplx<T> A = r0 < rows ? in[q][r0 * Nxh + n] : mk((T)0, (T)0);
-      cplx<T> B = r1 < rows ? in[q][r1 * Nxh + n] : mk((T)0, (T)0);
-      z = A + mul_i(B);
-    } else if (n > Nxh) {
-      int k = Nx - n;
-      cplx<T> A = r0 < rows ? in[q][r0 * Nxh + k] : mk((T)0, (T)0);
-      cplx<T> B = r1 < rows ? in[q][r1 * Nxh + k] : mk((T)0, (T)0);
-      z = conj(A) + mul_i(conj(B));
-    }
-    x[idx] = z;
+    cplx<T> A = r0 < rows ? in[q][r0 * Nxh + k] : mk((T)0, (T)0);
+    cplx<T> B = r1 < rows ? in[q][r1 * Nxh + k] : mk((T)0, (T)0);
+    cplx<T>* xs = x + sq6 * Nx;
+    xs[k] = A + mul_i(B);
+    if (k > 0) xs[Nx - k] = conj(A) + mul_i(conj(B));
+    else xs[Nxh] = mk((T)0, (T)0);
   }
   __syncthreads();
   cplx<T>* Z = lds_fft(x, y, tl, Nx, 6 * nseq, tw, true);
   T sc = (T)1 / (T)Nx;
-  for (int idx = threadIdx.x; idx < 6 * nseq * Nx; idx += blockDim.x) {
-    int q = idx % 6, r = idx / 6;
+  // one node per thread: its six components are consecutive in the record
+  for (int r = threadIdx.x; r < nseq * Nx; r += blockDim.x) {
     int sq = r / Nx, n = r - sq * Nx;
     int64_t r0 = 2 * (pair0 + sq), r1 = r0 + 1;
-    cplx<T> z = Z[(q * nseq + sq) * Nx + n];
-    if (r0 < rows) out[(r0 * Nx + n) * 6 + q] = sc * z.x;
-    if (r1 < rows) out[(r1 * Nx + n) * 6 + q] = sc * z.y;
+    T a[6], b[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      cplx<T> z = Z[(q * nseq + sq) * Nx + n];
+      a[q] = sc * z.x;
+      b[q] = sc * z.y;
+    }
+    if (r0 < rows) {
+      T* o = out + (r0 * Nx + n) * 6;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) o[q] = a[q];
+    }
+    if (r1 < rows) {
+      T* o = out + (r1 * Nx + n) * 6;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) o[q] = b[q];
+    }
   }
 }
 
@@ -159,29 +172,33 @@ __global__ void k_interleave(T* rec, const T* in, int q, int64_t n) {
   if (i < n) rec[6 * i + q] = in[i];
 }
 
+// padding of the column stride of k_fft_y in LDS (complex elements)
+constexpr int FFTY_PAD = 2;
+
 // Transform along y (columns), in place: data[planes][Ny][Nxh]; a work-group
 // takes ncol consecutive kx columns of one plane.  Inverse scales by 1/Ny.
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_y(cplx<T>* data, int Ny, int Nxh, int ncol,
                                                const cplx<T>* tw, int inverse) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int S = Ny + FFTY_PAD;                // column stride in LDS
   cplx<T>* x = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* y = x + ncol * Ny;
-  cplx<T>* tl = y + ncol * Ny;
+  cplx<T>* y = x + ncol * S;
+  cplx<T>* tl = y + ncol * S;
   int cpp = Nxh / ncol;                       // column groups per plane
   int64_t plane = blockIdx.x / cpp;
   int c0 = (blockIdx.x % cpp) * ncol;
   cplx<T>* base = data + plane * Ny * Nxh + c0;
   for (int idx = threadIdx.x; idx < ncol * Ny; idx += blockDim.x) {
     int row = idx / ncol, c = idx - row * ncol;
-    x[c * Ny + row] = base[(int64_t)row * Nxh + c];
+    x[c * S + row] = base[(int64_t)row * Nxh + c];
   }
   __syncthreads();
-  cplx<T>* Z = lds_fft(x, y, tl, Ny, ncol, tw, inverse != 0);
+  cplx<T>* Z = lds_fft(x, y, tl, Ny, ncol, tw, inverse != 0, S);
   T sc = inverse ? (T)1 / (T)Ny : (T)1;
   for (int idx = threadIdx.x; idx < ncol * Ny; idx += blockDim.x) {
     int row = idx / ncol, c = idx - row * ncol;
-    base[(int64_t)row * Nxh + c] = sc * Z[c * Ny + row];
+    base[(int64_t)row * Nxh + c] = sc * Z[c * S + row];
   }
 }
 

@@ -238,7 +238,7 @@ struct Impl {
     k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
     if (G.Ny > 1) {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
-      size_t sh2 = (2 * (size_t)ncol + 1) * G.Ny * sizeof(C);
+      size_t sh2 = (2 * (size_t)ncol * (G.Ny + FFTY_PAD) + G.Ny) * sizeof(C);
       k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 512, sh2, g->s>>>(out, G.Ny, G.Nxh, ncol,
                                                                        (const C*)g->twy, 0);
     }
@@ -248,7 +248,7 @@ struct Impl {
     const Geom& G = g->g;
     if (G.Ny > 1) {
       int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
-      size_t sh2 = (2 * (size_t)ncol + 1) * G.Ny * sizeof(C);
+      size_t sh2 = (2 * (size_t)ncol * (G.Ny + FFTY_PAD) + G.Ny) * sizeof(C);
       for (int q = 0; q < 6; ++q)
         k_fft_y<T><<<(unsigned)((int64_t)G.Nz * (G.Nxh / ncol)), 512, sh2, g->s>>>(
             (C*)g->outs[q], G.Ny, G.Nxh, ncol, (const C*)g->twy, 1);
