@@ -303,7 +303,7 @@ struct Impl {
     sa.code = g->code;
     sa.counts = g->counts;
     sa.err = g->err_dev;
-    k_sort_rank<<<g->max_chunks, 256, 0, g->s>>>(sa);
+    k_sort_rank<<<g->max_chunks, 64, 0, g->s>>>(sa);
 
     k_fill<int32_t><<<nblk(G.NT, 256), 256, 0, g->s>>>(g->inj_count, G.NT, 0);
     InjArgs ia;
@@ -730,7 +730,7 @@ static int check_errors(gempic* g) {
   if (e & ERR_CFL) return fail(g, GEMPIC_ECFL, "a particle crossed more than one cell in a step");
   if (e & ERR_NUMERIC) return fail(g, GEMPIC_ENUMERIC, "non-finite particle momentum");
   if (e & ERR_CAPACITY) return fail(g, GEMPIC_ECAPACITY, "particle buffer capacity exceeded");
-  if (e & ERR_TILE) return fail(g, GEMPIC_EDEVICE, "internal: particle outside its tile");
+  if (e & ERR_TILE) return fail(g, GEMPIC_EDEVICE, "internal: particle outside its tile or chunk too long");
   return GEMPIC_OK;
 }
 

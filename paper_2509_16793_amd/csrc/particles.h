@@ -324,24 +324,29 @@ struct SortArgs {
   int* err;
 };
 
-__global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
+// One wavefront per chunk, no barriers: the codes of all rows of 64
+// particles first (their loads in flight together), then the rows in order.
+// Lane k < NCODE keeps the number of earlier particles with code k, so a
+// particle's rank is that count plus the same-code lanes below it.
+__global__ __launch_bounds__(64) void k_sort_rank(SortArgs a) {
   const Geom& g = a.g;
-  __shared__ int wcnt[4][NCODE];
-  __shared__ int run[NCODE];
   int c = blockIdx.x;
   if (c >= *a.ct.n) return;
   int t = a.ct.tile[c];
   int p0 = a.ct.start[c], p1 = a.ct.end[c];
   int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (threadIdx.x < NCODE) {
-    run[threadIdx.x] = 0;
-    for (int w = 0; w < 4; ++w) wcnt[w][threadIdx.x] = 0;
+  const int lane = threadIdx.x;
+  constexpr int NR = GP_CHUNK / 64;
+  static_assert(GP_CHUNK % 64 == 0, "chunks are whole rows of 64");
+  if (p1 - p0 > GP_CHUNK) {                 // the chunk table never builds these
+    if (lane == 0) atomicOr(a.err, ERR_TILE);
+    return;
   }
-  __syncthreads();
-  for (int row = p0; row < p1; row += blockDim.x) {
-    int p = row + threadIdx.x;
-    int code = -1;
+  int code[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int p = p0 + r * 64 + lane;
+    code[r] = -1;
     if (p < p1) {
       int cell;
       if (a.cell) {
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
         cell = iz < 0 ? -1 : (iz * g.Ny + iy) * g.Nx + ix;
       }
       if (cell < 0) {
-        code = CODE_REMOVED;
+        code[r] = CODE_REMOVED;
       } else {
         cell &= ~GEMPIC_BEAM_BIT;
         // power-of-two grid and tile sizes: shifts and masks
@@ -368,39 +373,34 @@ __global__ __launch_bounds__(256) void k_sort_rank(SortArgs a) {
         int sz = (iz >> (__ffs(g.Tz) - 1)) - tz;
         if (sx == 99 || sy == 99 || sz < -1 || sz > 0) {
           atomicOr(a.err, ERR_TILE);
-          code = CODE_REMOVED;
+          code[r] = CODE_REMOVED;
         } else {
-          code = (sz + 1) * 9 + (sy + 1) * 3 + (sx + 1);
+          code[r] = (sz + 1) * 9 + (sy + 1) * 3 + (sx + 1);
         }
       }
     }
-    // rank among equal codes within the wave
-    int myrank = 0;
-    uint64_t active = __ballot(code >= 0);
-    uint64_t lt = (1ull << lane) - 1ull;
+  }
+  const uint64_t lt = (1ull << lane) - 1ull;
+  int run = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (p0 + r * 64 >= p1) break;
+    const int cd = code[r];
+    int myrank = 0, add = 0;
+    uint64_t active = __ballot(cd >= 0);
     while (active) {
       int leader = __ffsll((unsigned long long)active) - 1;
-      int lc = __shfl(code, leader);
-      uint64_t m = __ballot(code == lc);
-      if (code == lc) myrank = __popcll(m & lt);
-      if (lane == 0) wcnt[wid][lc] = __popcll(m);
+      int lc = __shfl(cd, leader);
+      uint64_t m = __ballot(cd == lc);
+      if (cd == lc) myrank = __popcll(m & lt);
+      if (lane == lc) add = __popcll(m);
       active &= ~m;
     }
-    __syncthreads();
-    if (code >= 0) {
-      int rk = run[code] + myrank;
-      for (int w = 0; w < wid; ++w) rk += wcnt[w][code];
-      a.code[p] = (code << 24) | rk;
-    }
-    __syncthreads();
-    if (threadIdx.x < NCODE) {
-      int s = 0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { s += wcnt[w][threadIdx.x]; wcnt[w][threadIdx.x] = 0; }
-      run[threadIdx.x] += s;
-    }
-    __syncthreads();
+    const int base = __shfl(run, cd < 0 ? 0 : cd);
+    if (cd >= 0) a.code[p0 + r * 64 + lane] = (cd << 24) | (base + myrank);
+    run += add;
   }
-  if (threadIdx.x < NCODE) a.counts[c * NCODE + threadIdx.x] = run[threadIdx.x];
+  if (lane < NCODE) a.counts[c * NCODE + lane] = run;
 }
 
 // Step 2: per destination tile, offsets of every (source chunk, code) group in
@@ -593,25 +593,62 @@ __global__ __launch_bounds__(256) void k_scatter(ScatArgs<T> a, PartPtrs<T> A, P
   int t = a.ct.tile[c];
   int p0 = a.ct.start[c], p1 = a.ct.end[c];
   int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-    int cr = a.code[p];
-    int code = cr >> 24, rank = cr & 0xFFFFFF;
-    if (code == CODE_REMOVED) continue;
-    int sz = code / 9 - 1, sy = (code / 3) % 3 - 1, sx = code % 3 - 1;
-    int dx = tx + sx; if (dx < 0) dx += g.nTx; if (dx >= g.nTx) dx -= g.nTx;
-    int dy = ty + sy; if (dy < 0) dy += g.nTy; if (dy >= g.nTy) dy -= g.nTy;
-    int dz = tz + sz;
-    int dt = (dz * g.nTy + dy) * g.nTx + dx;
-    int64_t o = a.tile_base[dt] + a.offs[c * NCODE + code] + rank;
-    if (o >= a.capacity) { atomicOr(a.err, ERR_CAPACITY); continue; }
-    if (B.cell) B.cell[o] = A.cell[p];
-    B.ox[o] = A.ox[p];
-    if (DIM == 3) B.oy[o] = A.oy[p];
-    B.oz[o] = A.oz[p];
-    B.ux[o] = A.ux[p];
-    B.uy[o] = A.uy[p];
-    B.uz[o] = A.uz[p];
-    if (B.id) B.id[o] = A.id[p];
+  // the chunk's rows of 256 in phases (codes, destinations, loads, stores),
+  // so that each phase's memory operations are in flight together
+  constexpr int R = GP_CHUNK / 256;
+  static_assert(GP_CHUNK % 256 == 0, "chunks are whole rows of 256");
+  int64_t o[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = p0 + r * 256 + (int)threadIdx.x;
+    o[r] = -1;
+    if (p < p1) {
+      const int cr = a.code[p];
+      const int code = cr >> 24, rank = cr & 0xFFFFFF;
+      if (code != CODE_REMOVED) {
+        int sz = code / 9 - 1, sy = (code / 3) % 3 - 1, sx = code % 3 - 1;
+        int dx = tx + sx; if (dx < 0) dx += g.nTx; if (dx >= g.nTx) dx -= g.nTx;
+        int dy = ty + sy; if (dy < 0) dy += g.nTy; if (dy >= g.nTy) dy -= g.nTy;
+        int dz = tz + sz;
+        int dt = (dz * g.nTy + dy) * g.nTx + dx;
+        o[r] = a.tile_base[dt] + a.offs[c * NCODE + code] + rank;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (o[r] >= a.capacity) {
+      atomicOr(a.err, ERR_CAPACITY);
+      o[r] = -1;
+    }
+  int32_t cell[R];
+  T ox[R], oy[R], oz[R], ux[R], uy[R], uz[R];
+  int64_t id[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (o[r] < 0) continue;
+    const int p = p0 + r * 256 + (int)threadIdx.x;
+    if (B.cell) cell[r] = A.cell[p];
+    ox[r] = A.ox[p];
+    if (DIM == 3) oy[r] = A.oy[p];
+    oz[r] = A.oz[p];
+    ux[r] = A.ux[p];
+    uy[r] = A.uy[p];
+    uz[r] = A.uz[p];
+    if (B.id) id[r] = A.id[p];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (o[r] < 0) continue;
+    const int64_t q = o[r];
+    if (B.cell) B.cell[q] = cell[r];
+    B.ox[q] = ox[r];
+    if (DIM == 3) B.oy[q] = oy[r];
+    B.oz[q] = oz[r];
+    B.ux[q] = ux[r];
+    B.uy[q] = uy[r];
+    B.uz[q] = uz[r];
+    if (B.id) B.id[q] = id[r];
   }
 }
 
