@@ -342,7 +342,7 @@ struct Impl {
     oa.inj_count = g->inj_count;
     oa.inj_off = g->inj_off;
     oa.tile_count = g->tile_count;
-    k_tile_offsets<<<nblk(G.NT, 128), 128, 0, g->s>>>(oa);
+    k_tile_offsets<<<(unsigned)((G.NT + 4 * OFF_TPW - 1) / (4 * OFF_TPW)), 256, 0, g->s>>>(oa);
     scan_tiles(g, newt);
     k_build_chunks<<<nblk(G.NT, 128), 128, 0, g->s>>>(G.NT, g->tile_base, g->tile_count, newt,
                                                        g->max_chunks);

@@ -416,48 +416,64 @@ struct OffArgs {
   int64_t* tile_count;      // [NT]
 };
 
-__global__ void k_tile_offsets(OffArgs a) {
+// Three destination tiles per wavefront, 18 lanes each (lanes 54 .. 63
+// idle): lane i of tile t's group takes the step (sz, sy, sx) =
+// (-(i / 9), (i % 9) / 3 - 1, i % 3 - 1) from source tile t - step; a step is
+// kept only if it is the canonical step between the two tiles (small
+// periodic grids reach one source by several steps).  The sources'
+// particles follow each other in increasing source index.
+constexpr int OFF_TPW = 3;                    // tiles per wavefront
+
+__global__ __launch_bounds__(256) void k_tile_offsets(OffArgs a) {
   const Geom& g = a.g;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.NT) return;
-  int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
-  int src[18], cod[18];
-  int ns = 0;
-  for (int sz = 0; sz >= -1; --sz) {          // source row tz - sz  (dest = source + sz)
-    int szr = tz - sz;
-    if (szr >= g.nTz) continue;
-    for (int sy = -1; sy <= 1; ++sy) {
-      for (int sx = -1; sx <= 1; ++sx) {
-        int sxt = tx - sx; sxt = ((sxt % g.nTx) + g.nTx) % g.nTx;
-        int syt = ty - sy; syt = ((syt % g.nTy) + g.nTy) % g.nTy;
-        // canonical step from this source to t
-        int cx = tile_step(sxt, tx, g.nTx), cy = tile_step(syt, ty, g.nTy);
-        if (cx != sx || cy != sy) continue;     // duplicate of another step
-        int s = (szr * g.nTy + syt) * g.nTx + sxt;
-        src[ns] = s;
-        cod[ns] = (sz + 1) * 9 + (sy + 1) * 3 + (sx + 1);
-        ++ns;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / 18, i = lane - grp * 18, g0 = grp * 18;
+  const int t = (blockIdx.x * 4 + (threadIdx.x >> 6)) * OFF_TPW + grp;
+  const bool own = grp < OFF_TPW && t < g.NT;
+  const int tx = t % g.nTx, ty = (t / g.nTx) % g.nTy, tz = t / (g.nTx * g.nTy);
+  int valid = 0, src = 0, cod = 0;
+  if (own) {
+    const int sz = -(i / 9), sy = (i % 9) / 3 - 1, sx = i % 3 - 1;
+    const int szr = tz - sz;
+    if (szr < g.nTz) {
+      int sxt = tx - sx; sxt = ((sxt % g.nTx) + g.nTx) % g.nTx;
+      int syt = ty - sy; syt = ((syt % g.nTy) + g.nTy) % g.nTy;
+      if (tile_step(sxt, tx, g.nTx) == sx && tile_step(syt, ty, g.nTy) == sy) {
+        valid = 1;
+        src = (szr * g.nTy + syt) * g.nTx + sxt;
+        cod = (sz + 1) * 9 + (sy + 1) * 3 + (sx + 1);
       }
     }
   }
-  // sort sources by index (insertion sort)
-  for (int i = 1; i < ns; ++i) {
-    int s = src[i], c = cod[i], j = i - 1;
-    while (j >= 0 && src[j] > s) { src[j + 1] = src[j]; cod[j + 1] = cod[j]; --j; }
-    src[j + 1] = s; cod[j + 1] = c;
+  int f = 0, n = 0;
+  if (valid) {
+    f = a.ct.first[src];
+    n = a.ct.count[src];
   }
-  int64_t run = 0;
-  for (int i = 0; i < ns; ++i) {
-    int f = a.ct.first[src[i]], n = a.ct.count[src[i]];
+  long long tot = 0;                          // this source's particles for t
+  for (int k = 0; k < n; ++k) tot += a.counts[(f + k) * NCODE + cod];
+  long long pre = 0, all = 0;                 // sources below this one; all sources
+  for (int j = 0; j < 18; ++j) {
+    const int vj = __shfl(valid, g0 + j);
+    const int sj = __shfl(src, g0 + j);
+    const long long tj = __shfl(tot, g0 + j);
+    if (vj) {
+      all += tj;
+      if (sj < src) pre += tj;
+    }
+  }
+  if (valid) {
+    long long run = pre;
     for (int k = 0; k < n; ++k) {
-      int ci = (f + k) * NCODE + cod[i];
+      const int ci = (f + k) * NCODE + cod;
       a.offs[ci] = (int32_t)run;
       run += a.counts[ci];
     }
   }
-  a.inj_off[t] = (int32_t)run;
-  run += a.inj_count[t];
-  a.tile_count[t] = run;
+  if (own && i == 0) {
+    a.inj_off[t] = (int32_t)all;
+    a.tile_count[t] = all + a.inj_count[t];
+  }
 }
 
 // Step 3: exclusive scans of the tile counts (-> tile_base, total) and of the chunk
