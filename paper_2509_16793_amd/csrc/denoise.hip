@@ -782,12 +782,14 @@ __global__ __launch_bounds__(256) void k_decide(const double* part, int nparts, 
   if (!ok && fallbacks) *fallbacks += 1;
 }
 
-__global__ void k_select(Box B, const int* use_net, P3 Jf, W3 Jd) {
+// a fixed grid strides over the box: when the network's current is kept
+// (the usual case) every work-group returns at once
+constexpr int SEL_BLOCKS = 1024;
+__global__ __launch_bounds__(256) void k_select(Box B, const int* use_net, P3 Jf, W3 Jd) {
   if (*use_net) return;
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t nv = (int64_t)B.Z * B.Y * B.X;
-  if (v >= nv) return;
-  for (int q = 0; q < 3; ++q) Jd.p[q][v] = Jf.p[q][v];
+  const int64_t nv = (int64_t)B.Z * B.Y * B.X;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x)
+    for (int q = 0; q < 3; ++q) Jd.p[q][v] = Jf.p[q][v];
 }
 
 // training loss on planes [lo, hi): r = (Jf + s curl A - Jt) / n_e,
@@ -1070,7 +1072,7 @@ int dn_step(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const
                                         W3{{Jd[0], Jd[1], Jd[2]}}, d->part);
   k_decide<<<1, 256, 0, s>>>(d->part, COMB_BLOCKS, thr, d->use_net, rel ? rel : d->rel,
                              fallbacks ? fallbacks : d->fallbacks);
-  k_select<<<nblk(nv, 256), 256, 0, s>>>(c.B, d->use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
+  k_select<<<SEL_BLOCKS, 256, 0, s>>>(c.B, d->use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("denoiser launch: ") + hipGetErrorString(e));
   return GEMPIC_OK;
