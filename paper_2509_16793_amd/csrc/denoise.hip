@@ -15,9 +15,12 @@
 // B = activations, one 16-byte LDS read per lane from a halo tile).  The
 // reduction index k = (tap, input channel) is split in steps of 32; a lane
 // group g (lanes 16g .. 16g+15) supplies the 8 values k = 32 s + 8 g + e of
-// both operands, so operands A and B agree element by element.  The data
-// gradient is the same kernel with flipped taps and transposed channels;
-// weight gradients are MFMAs with the voxels as the reduction index.
+// both operands, so operands A and B agree element by element.  The k-steps
+// are ordered by (group of (dz, dx) taps, dy), so that one LDS read serves
+// three output rows; 32-channel inputs are reduced in two 16-channel phases,
+// each with its half of the halo in its own LDS buffer.  The data gradient is
+// the same kernel with flipped taps and transposed channels; weight
+// gradients are MFMAs with the voxels as the reduction index.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
