@@ -82,6 +82,19 @@ def test_rejects_non_power_of_two_and_bad_tile():
     assert _create(cfg)[0] == -1
 
 
+def test_rejects_transverse_grid_beyond_lds_transforms():
+    # FP64 rows of 1024 nodes (and FP32 rows of 2048) exceed what the
+    # transverse transforms hold in LDS; FP32 rows of 1024 are accepted
+    cfg = workloads.lwfa2d_fp64()
+    cfg["n"] = [1024, 1, 256]
+    rc, _ = _create(cfg)
+    assert rc == -1
+    assert b"transverse grid too large" in gp.lib().gempic_last_error(None)
+    cfg["precision"] = "fp32"
+    cfg["n"] = [2048, 1, 256]
+    assert _create(cfg)[0] == -1
+
+
 def test_strerror():
     for code in range(0, -9, -1):
         assert gp.lib().gempic_strerror(code)
