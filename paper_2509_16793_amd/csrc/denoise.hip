@@ -400,6 +400,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
     }
   }
+  if (tn < ntile) {
+    if (DIRECT) {
+      // own loads done, then every wave's loads and every read of this buffer
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      buf ^= 1;
+    } else {
+      __syncthreads();
+      if (INMODE == 0) {
+        place(tn);
+        if (PU < U) stage_rest(tn);
+      } else {
+        place_input(tn);
+      }
+      __syncthreads();
+    }
+  }
+  // epilogue after the barrier: the output stores drain while the next tile
+  // is computed instead of holding up the wait above
   if (last) {
     const int z = z0 + wave;
 #pragma unroll
@@ -434,23 +453,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           *(u32x2*)(a.out + vox * COUTP + co0) = o;
         }
       }
-    }
-  }
-  if (tn < ntile) {
-    if (DIRECT) {
-      // own loads done, then every wave's loads and every read of this buffer
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      buf ^= 1;
-    } else {
-      __syncthreads();
-      if (INMODE == 0) {
-        place(tn);
-        if (PU < U) stage_rest(tn);
-      } else {
-        place_input(tn);
-      }
-      __syncthreads();
     }
   }
   }  // phases
