@@ -202,6 +202,77 @@ __global__ __launch_bounds__(512) void k_fft_y(cplx<T>* data, int Ny, int Nxh, i
   }
 }
 
+// Transform along y for Ny = 256 as 16 x 16 (four-step): with row
+// n = 16 n1 + n2 and mode k = k1 + 16 k2,
+//   X[k1 + 16 k2] = sum_n2 W16^(n2 k2) W256^(n2 k1) sum_n1 W16^(n1 k1) x[16 n1 + n2].
+// Thread (column c, n2) takes the 16 rows n2 + 16 n1 into registers, does the
+// inner 16-point DFT there and applies W256^(n2 k1); after one LDS transpose
+// thread (c, k1) does the outer DFT and writes the rows k1 + 16 k2.  Eight
+// columns per 128-thread work-group; the inverse conjugates the twiddles and
+// scales by 1/256.  tw holds exp(-2 pi i t / 256) for t < 128.
+template <typename T>
+GP_DEV cplx<T> twid256(const cplx<T>* tw, int e, bool inverse) {   // exp(-+2 pi i e / 256), 0 <= e < 256
+  cplx<T> w = e < 128 ? tw[e] : mk(-tw[e - 128].x, -tw[e - 128].y);
+  if (inverse) w.y = -w.y;
+  return w;
+}
+// 4-point DFT in place
+template <typename T>
+GP_DEV void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3, bool inverse) {
+  const cplx<T> b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3, b3 = a1 - a3;
+  const cplx<T> ib3 = mul_i(b3);
+  a0 = b0 + b2;
+  a2 = b0 - b2;
+  a1 = inverse ? b1 + ib3 : b1 - ib3;
+  a3 = inverse ? b1 - ib3 : b1 + ib3;
+}
+// 16-point DFT of v[n] as 4 x 4 (n = 4 m1 + m2, k = l1 + 4 l2); the result
+// for k = l1 + 4 l2 is left in v[4 l1 + l2]
+template <typename T>
+GP_DEV void dft16(cplx<T> v[16], const cplx<T>* tw, bool inverse) {
+#pragma unroll
+  for (int m2 = 0; m2 < 4; ++m2) dft4(v[m2], v[4 + m2], v[8 + m2], v[12 + m2], inverse);
+#pragma unroll
+  for (int l1 = 1; l1 < 4; ++l1)
+#pragma unroll
+    for (int m2 = 1; m2 < 4; ++m2) v[4 * l1 + m2] = v[4 * l1 + m2] * twid256(tw, 16 * m2 * l1, inverse);
+#pragma unroll
+  for (int l1 = 0; l1 < 4; ++l1) dft4(v[4 * l1], v[4 * l1 + 1], v[4 * l1 + 2], v[4 * l1 + 3], inverse);
+}
+
+constexpr int FY256_NC = 8;                  // columns per work-group
+constexpr int FY256_KS = 16 * FY256_NC + 4;  // LDS stride of one k1 (padded)
+
+template <typename T>
+__global__ __launch_bounds__(128) void k_fft_y256(cplx<T>* data, int Nxh, const cplx<T>* tw, int inverse) {
+  __shared__ cplx<T> sY[16 * FY256_KS];      // [k1][n2][c]
+  const int cpp = Nxh / FY256_NC;
+  const int64_t plane = blockIdx.x / cpp;
+  const int c0 = (int)(blockIdx.x % cpp) * FY256_NC;
+  const int c = threadIdx.x % FY256_NC, q = threadIdx.x / FY256_NC;   // q: n2, then k1
+  cplx<T>* col = data + plane * 256 * Nxh + c0 + c;
+  const bool inv = inverse != 0;
+  cplx<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = col[(int64_t)(16 * n1 + q) * Nxh];
+  dft16(v, tw, inv);
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = (p >> 2) + 4 * (p & 3);
+    sY[k1 * FY256_KS + q * FY256_NC + c] = k1 == 0 || q == 0 ? v[p] : v[p] * twid256(tw, q * k1, inv);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = sY[q * FY256_KS + m * FY256_NC + c];
+  dft16(v, tw, inv);
+  const T sc = inv ? (T)1 / (T)256 : (T)1;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k2 = (p >> 2) + 4 * (p & 3);
+    col[(int64_t)(q + 16 * k2) * Nxh] = sc * v[p];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The march.  One thread per transverse mode (ky, kx); zeta nodes n = Nz-1 .. 0.
 // Node "1" (n + 1, new level) is known; node 0 (n) is solved with App. B:

@@ -229,6 +229,19 @@ struct Impl {
   }
 
   // ---- FFT helpers --------------------------------------------------------
+  // transform along y of data[planes][Ny][Nxh] in place
+  static void fft_y(gempic* g, C* data, int64_t planes, int inverse) {
+    const Geom& G = g->g;
+    if (G.Ny == 256 && G.Nxh % FY256_NC == 0) {
+      k_fft_y256<T><<<(unsigned)(planes * (G.Nxh / FY256_NC)), 128, 0, g->s>>>(data, G.Nxh, (const C*)g->twy,
+                                                                               inverse);
+      return;
+    }
+    int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
+    size_t sh = (2 * (size_t)ncol * (G.Ny + FFTY_PAD) + G.Ny) * sizeof(C);
+    k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 512, sh, g->s>>>(data, G.Ny, G.Nxh, ncol, (const C*)g->twy,
+                                                                      inverse);
+  }
   static void fft_fwd(gempic* g, const T* in, C* out, int64_t planes) {
     const Geom& G = g->g;
     int64_t rows = planes * G.Ny;
@@ -236,23 +249,13 @@ struct Impl {
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 1024 / G.Nx));
     size_t sh = (2 * (size_t)nseq + 1) * G.Nx * sizeof(C);
     k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
-    if (G.Ny > 1) {
-      int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
-      size_t sh2 = (2 * (size_t)ncol * (G.Ny + FFTY_PAD) + G.Ny) * sizeof(C);
-      k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 512, sh2, g->s>>>(out, G.Ny, G.Nxh, ncol,
-                                                                       (const C*)g->twy, 0);
-    }
+    if (G.Ny > 1) fft_y(g, out, planes, 0);
   }
   // six field spectra (outs) -> interleaved real node records F6
   static void fft_inv6(gempic* g) {
     const Geom& G = g->g;
-    if (G.Ny > 1) {
-      int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
-      size_t sh2 = (2 * (size_t)ncol * (G.Ny + FFTY_PAD) + G.Ny) * sizeof(C);
-      for (int q = 0; q < 6; ++q)
-        k_fft_y<T><<<(unsigned)((int64_t)G.Nz * (G.Nxh / ncol)), 512, sh2, g->s>>>(
-            (C*)g->outs[q], G.Ny, G.Nxh, ncol, (const C*)g->twy, 1);
-    }
+    if (G.Ny > 1)
+      for (int q = 0; q < 6; ++q) fft_y(g, (C*)g->outs[q], G.Nz, 1);
     int64_t rows = (int64_t)G.Nz * G.Ny;
     int64_t pairs = (rows + 1) / 2;
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / (6 * G.Nx)));
