@@ -210,9 +210,11 @@ __global__ __launch_bounds__(512) void k_fft_y(cplx<T>* data, int Ny, int Nxh, i
 // thread (c, k1) does the outer DFT and writes the rows k1 + 16 k2.  Eight
 // columns per 128-thread work-group; the inverse conjugates the twiddles and
 // scales by 1/256.  tw holds exp(-2 pi i t / 256) for t < 128.
+// exp(-+2 pi i e / 256), 0 <= e < 256, from a table tw[t] = exp(-2 pi i t / N)
+// (t < N / 2) of N = 256 S
 template <typename T>
-GP_DEV cplx<T> twid256(const cplx<T>* tw, int e, bool inverse) {   // exp(-+2 pi i e / 256), 0 <= e < 256
-  cplx<T> w = e < 128 ? tw[e] : mk(-tw[e - 128].x, -tw[e - 128].y);
+GP_DEV cplx<T> twid256(const cplx<T>* tw, int e, bool inverse, int S = 1) {
+  cplx<T> w = e < 128 ? tw[e * S] : mk(-tw[(e - 128) * S].x, -tw[(e - 128) * S].y);
   if (inverse) w.y = -w.y;
   return w;
 }
@@ -229,13 +231,13 @@ GP_DEV void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3, bool invers
 // 16-point DFT of v[n] as 4 x 4 (n = 4 m1 + m2, k = l1 + 4 l2); the result
 // for k = l1 + 4 l2 is left in v[4 l1 + l2]
 template <typename T>
-GP_DEV void dft16(cplx<T> v[16], const cplx<T>* tw, bool inverse) {
+GP_DEV void dft16(cplx<T> v[16], const cplx<T>* tw, bool inverse, int S = 1) {
 #pragma unroll
   for (int m2 = 0; m2 < 4; ++m2) dft4(v[m2], v[4 + m2], v[8 + m2], v[12 + m2], inverse);
 #pragma unroll
   for (int l1 = 1; l1 < 4; ++l1)
 #pragma unroll
-    for (int m2 = 1; m2 < 4; ++m2) v[4 * l1 + m2] = v[4 * l1 + m2] * twid256(tw, 16 * m2 * l1, inverse);
+    for (int m2 = 1; m2 < 4; ++m2) v[4 * l1 + m2] = v[4 * l1 + m2] * twid256(tw, 16 * m2 * l1, inverse, S);
 #pragma unroll
   for (int l1 = 0; l1 < 4; ++l1) dft4(v[4 * l1], v[4 * l1 + 1], v[4 * l1 + 2], v[4 * l1 + 3], inverse);
 }
@@ -270,6 +272,54 @@ __global__ __launch_bounds__(128) void k_fft_y256(cplx<T>* data, int Nxh, const 
   for (int p = 0; p < 16; ++p) {
     const int k2 = (p >> 2) + 4 * (p & 3);
     col[(int64_t)(q + 16 * k2) * Nxh] = sc * v[p];
+  }
+}
+
+// Transform along y for Ny = 512: the even rows (threads 0 .. 127) and the
+// odd rows (128 .. 255) each take the 256-point four-step transform above,
+// then X[k] = E[k] + W512^k O[k] and X[k + 256] = E[k] - W512^k O[k].  tw
+// holds exp(-2 pi i t / 512) for t < 256.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_y512(cplx<T>* data, int Nxh, const cplx<T>* tw, int inverse) {
+  __shared__ cplx<T> sY[2 * 16 * FY256_KS];  // per half [k1][n2][c]; then the halves' results [h][k][c]
+  const int cpp = Nxh / FY256_NC;
+  const int64_t plane = blockIdx.x / cpp;
+  const int c0 = (int)(blockIdx.x % cpp) * FY256_NC;
+  const int h = threadIdx.x >> 7, t = threadIdx.x & 127;
+  const int c = t % FY256_NC, q = t / FY256_NC;   // q: n2, then k1
+  cplx<T>* const base = data + plane * 512 * Nxh + c0;
+  cplx<T>* col = base + c;
+  cplx<T>* sh = sY + h * 16 * FY256_KS;
+  const bool inv = inverse != 0;
+  cplx<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = col[(int64_t)(2 * (16 * n1 + q) + h) * Nxh];
+  dft16(v, tw, inv, 2);
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = (p >> 2) + 4 * (p & 3);
+    sh[k1 * FY256_KS + q * FY256_NC + c] = k1 == 0 || q == 0 ? v[p] : v[p] * twid256(tw, q * k1, inv, 2);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = sh[q * FY256_KS + m * FY256_NC + c];
+  dft16(v, tw, inv, 2);
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k = q + 16 * ((p >> 2) + 4 * (p & 3));
+    sY[(h * 256 + k) * FY256_NC + c] = v[p];
+  }
+  __syncthreads();
+  const T sc = inv ? (T)1 / (T)512 : (T)1;
+  for (int idx = threadIdx.x; idx < 256 * FY256_NC; idx += 256) {
+    const int cc = idx % FY256_NC, k = idx / FY256_NC;
+    const cplx<T> E = sY[k * FY256_NC + cc], O = sY[(256 + k) * FY256_NC + cc];
+    cplx<T> w = tw[k];
+    if (inv) w.y = -w.y;
+    const cplx<T> wO = w * O;
+    base[(int64_t)k * Nxh + cc] = sc * (E + wO);
+    base[(int64_t)(k + 256) * Nxh + cc] = sc * (E - wO);
   }
 }
 

@@ -237,6 +237,11 @@ struct Impl {
                                                                                inverse);
       return;
     }
+    if (G.Ny == 512 && G.Nxh % FY256_NC == 0) {
+      k_fft_y512<T><<<(unsigned)(planes * (G.Nxh / FY256_NC)), 256, 0, g->s>>>(data, G.Nxh, (const C*)g->twy,
+                                                                               inverse);
+      return;
+    }
     int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
     size_t sh = (2 * (size_t)ncol * (G.Ny + FFTY_PAD) + G.Ny) * sizeof(C);
     k_fft_y<T><<<(unsigned)(planes * (G.Nxh / ncol)), 512, sh, g->s>>>(data, G.Ny, G.Nxh, ncol, (const C*)g->twy,

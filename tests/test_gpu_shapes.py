@@ -90,6 +90,15 @@ def test_ny256_four_step_transform_fp32():
     _check(workloads.small3d(precision="fp32", n=(16, 256, 32), steps=2), 2, bar=2e-4, particles=False)
 
 
+# Ny = 512: one radix-2 step over two 256-point four-step transforms
+def test_ny512_transform_fp64():
+    _check(workloads.small3d(precision="fp64", n=(16, 512, 32), steps=2), 2)
+
+
+def test_ny512_transform_fp32():
+    _check(workloads.small3d(precision="fp32", n=(16, 512, 32), steps=2), 2, bar=2e-4, particles=False)
+
+
 # configurations the library rejects at creation, each with the reason it
 # names: a grid size that is not a power of two, a tile shape it does not
 # support, a slow step beyond h / 2, and a transverse grid wider than the LDS
