@@ -99,6 +99,16 @@ def test_ny512_transform_fp32():
     _check(workloads.small3d(precision="fp32", n=(16, 512, 32), steps=2), 2, bar=2e-4, particles=False)
 
 
+# Nx = 256 rows: the x transforms at the benchmark's row length, FP64 and FP32
+# fields against the oracle
+def test_nx256_transforms_fp64():
+    _check(workloads.small3d(precision="fp64", n=(256, 16, 32), steps=2), 2)
+
+
+def test_nx256_transforms_fp32():
+    _check(workloads.small3d(precision="fp32", n=(256, 16, 32), steps=2), 2, bar=2e-4, particles=False)
+
+
 # configurations the library rejects at creation, each with the reason it
 # names: a grid size that is not a power of two, a tile shape it does not
 # support, a slow step beyond h / 2, and a transverse grid wider than the LDS
