@@ -342,24 +342,46 @@ __global__ __launch_bounds__(64) void k_sort_rank(SortArgs a) {
     if (lane == 0) atomicOr(a.err, ERR_TILE);
     return;
   }
+  if (p1 <= p0) {
+    if (lane < NCODE) a.counts[c * NCODE + lane] = 0;
+    return;
+  }
+  // cells of every row first: unconditional loads (lanes past the chunk
+  // read its first particle), so that all of them are in flight together
+  int cellv[NR];
+  if (a.cell) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int p = p0 + r * 64 + lane;
+      cellv[r] = a.cell[p < p1 ? p : p0];
+    }
+  } else {
+    float xs[NR], ys[NR], zs[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int p = p0 + r * 64 + lane, q = p < p1 ? p : p0;
+      xs[r] = a.px[q];
+      ys[r] = g.dims == 3 ? a.py[q] : 0.0f;
+      zs[r] = a.pz[q];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      float o;
+      int ix = abs_cell(xs[r], g.ihx, &o);
+      if (ix >= g.Nx) ix -= g.Nx;
+      int iy = g.dims == 3 ? abs_cell(ys[r], g.ihy, &o) : 0;
+      if (iy >= g.Ny) iy -= g.Ny;
+      int iz = min(abs_cell(zs[r], g.ih, &o), g.Nzp - 1);
+      cellv[r] = iz < 0 ? -1 : (iz * g.Ny + iy) * g.Nx + ix;
+    }
+  }
   int code[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int p = p0 + r * 64 + lane;
     code[r] = -1;
     if (p < p1) {
-      int cell;
-      if (a.cell) {
-        cell = a.cell[p];
-      } else {
-        float o;
-        int ix = abs_cell(a.px[p], g.ihx, &o);
-        if (ix >= g.Nx) ix -= g.Nx;
-        int iy = g.dims == 3 ? abs_cell(a.py[p], g.ihy, &o) : 0;
-        if (iy >= g.Ny) iy -= g.Ny;
-        int iz = min(abs_cell(a.pz[p], g.ih, &o), g.Nzp - 1);
-        cell = iz < 0 ? -1 : (iz * g.Ny + iy) * g.Nx + ix;
-      }
+      int cell = cellv[r];
       if (cell < 0) {
         code[r] = CODE_REMOVED;
       } else {
@@ -614,44 +636,62 @@ __global__ __launch_bounds__(256) void k_scatter(ScatArgs<T> a, PartPtrs<T> A, P
   constexpr int R = GP_CHUNK / 256;
   static_assert(GP_CHUNK % 256 == 0, "chunks are whole rows of 256");
   int64_t o[R];
+  if (p1 <= p0) return;
+  // rows that hold particles (uniform): no loads for the empty ones
+  const int nrow = (p1 - p0 + 255) / 256;
+  int crv[R];                               // codes of every row, loads in flight together
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int p = p0 + r * 256 + (int)threadIdx.x;
-    o[r] = -1;
-    if (p < p1) {
-      const int cr = a.code[p];
-      const int code = cr >> 24, rank = cr & 0xFFFFFF;
-      if (code != CODE_REMOVED) {
-        int sz = code / 9 - 1, sy = (code / 3) % 3 - 1, sx = code % 3 - 1;
-        int dx = tx + sx; if (dx < 0) dx += g.nTx; if (dx >= g.nTx) dx -= g.nTx;
-        int dy = ty + sy; if (dy < 0) dy += g.nTy; if (dy >= g.nTy) dy -= g.nTy;
-        int dz = tz + sz;
-        int dt = (dz * g.nTy + dy) * g.nTx + dx;
-        o[r] = a.tile_base[dt] + a.offs[c * NCODE + code] + rank;
-      }
-    }
+    crv[r] = r < nrow ? a.code[p < p1 ? p : p0] : (CODE_REMOVED << 24);
   }
+  // destinations: the tile base and chunk offset loads of every row in flight
+  // together (rows without a destination read those of the staying code)
+  int64_t tbv[R];
+  int ofv[R], rkv[R];
+  bool okv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = p0 + r * 256 + (int)threadIdx.x;
+    const int cr = crv[r];
+    const int code0 = cr >> 24;
+    okv[r] = p < p1 && code0 != CODE_REMOVED;
+    const int code = okv[r] ? code0 : 13;   // 13: the staying code
+    rkv[r] = cr & 0xFFFFFF;
+    int sz = code / 9 - 1, sy = (code / 3) % 3 - 1, sx = code % 3 - 1;
+    int dx = tx + sx; if (dx < 0) dx += g.nTx; if (dx >= g.nTx) dx -= g.nTx;
+    int dy = ty + sy; if (dy < 0) dy += g.nTy; if (dy >= g.nTy) dy -= g.nTy;
+    int dz = tz + sz;
+    int dt = (dz * g.nTy + dy) * g.nTx + dx;
+    tbv[r] = r < nrow ? a.tile_base[dt] : 0;
+    ofv[r] = r < nrow ? a.offs[c * NCODE + code] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) o[r] = okv[r] ? tbv[r] + ofv[r] + rkv[r] : -1;
 #pragma unroll
   for (int r = 0; r < R; ++r)
     if (o[r] >= a.capacity) {
       atomicOr(a.err, ERR_CAPACITY);
       o[r] = -1;
     }
+  // particle rows: unconditional loads (rows without a destination read the
+  // chunk's first particle), stores only where there is a destination
   int32_t cell[R];
   T ox[R], oy[R], oz[R], ux[R], uy[R], uz[R];
   int64_t id[R];
+  const bool hasc = B.cell != nullptr, hasid = B.id != nullptr;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (o[r] < 0) continue;
-    const int p = p0 + r * 256 + (int)threadIdx.x;
-    if (B.cell) cell[r] = A.cell[p];
+    if (r >= nrow) break;
+    const int p = o[r] >= 0 ? p0 + r * 256 + (int)threadIdx.x : p0;
+    cell[r] = hasc ? A.cell[p] : 0;
     ox[r] = A.ox[p];
-    if (DIM == 3) oy[r] = A.oy[p];
+    oy[r] = DIM == 3 ? A.oy[p] : (T)0;
     oz[r] = A.oz[p];
     ux[r] = A.ux[p];
     uy[r] = A.uy[p];
     uz[r] = A.uz[p];
-    if (B.id) id[r] = A.id[p];
+    id[r] = hasid ? A.id[p] : 0;
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
