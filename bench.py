@@ -113,8 +113,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU decomposition is a design only)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

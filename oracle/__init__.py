@@ -27,5 +27,5 @@ Every step is written for a reader to check against the paper by eye:
 * ``conv3d``   -- plain conv3d forward/backward for the learned denoiser.
 
 Readings where the paper is silent, garbled or inconsistent are named where
-they are used (e.g. "reading: ...") and collected in the design doc.
+they are used (e.g. "reading: ...").
 """
