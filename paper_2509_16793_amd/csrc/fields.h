@@ -74,6 +74,87 @@ GP_DEV cplx<T>* lds_fft(cplx<T>* x, cplx<T>* y, cplx<T>* tl, int N, int nseq, co
   return x;
 }
 
+// exp(-+2 pi i e / 256), 0 <= e < 256, from a table tw[t] = exp(-2 pi i t / N)
+// (t < N / 2) of N = 256 S
+template <typename T>
+GP_DEV cplx<T> twid256(const cplx<T>* tw, int e, bool inverse, int S = 1) {
+  cplx<T> w = e < 128 ? tw[e * S] : mk(-tw[(e - 128) * S].x, -tw[(e - 128) * S].y);
+  if (inverse) w.y = -w.y;
+  return w;
+}
+// 4-point DFT in place
+template <typename T>
+GP_DEV void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3, bool inverse) {
+  const cplx<T> b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3, b3 = a1 - a3;
+  const cplx<T> ib3 = mul_i(b3);
+  a0 = b0 + b2;
+  a2 = b0 - b2;
+  a1 = inverse ? b1 + ib3 : b1 - ib3;
+  a3 = inverse ? b1 - ib3 : b1 + ib3;
+}
+// 16-point DFT of v[n] as 4 x 4 (n = 4 m1 + m2, k = l1 + 4 l2); the result
+// for k = l1 + 4 l2 is left in v[4 l1 + l2]
+template <typename T>
+GP_DEV void dft16(cplx<T> v[16], const cplx<T>* tw, bool inverse, int S = 1) {
+#pragma unroll
+  for (int m2 = 0; m2 < 4; ++m2) dft4(v[m2], v[4 + m2], v[8 + m2], v[12 + m2], inverse);
+#pragma unroll
+  for (int l1 = 1; l1 < 4; ++l1)
+#pragma unroll
+    for (int m2 = 1; m2 < 4; ++m2) v[4 * l1 + m2] = v[4 * l1 + m2] * twid256(tw, 16 * m2 * l1, inverse, S);
+#pragma unroll
+  for (int l1 = 0; l1 < 4; ++l1) dft4(v[4 * l1], v[4 * l1 + 1], v[4 * l1 + 2], v[4 * l1 + 3], inverse);
+}
+
+// Forward x transform of row pairs for Nx = 256 (two-for-one, as
+// k_fft_x_r2c), as the four-step 16 x 16 DFT: 16 threads per row pair read
+// the pair's rows 16 n1 + l straight into registers, the inner DFT, twiddles
+// and one LDS transpose precede the outer DFT, and the spectra of both rows
+// are split from the pair's transform in LDS.  8 pairs per 128-thread
+// work-group; rows past the end read row 0 and are not written.
+constexpr int R2C256_P = 8;
+template <typename T>
+__global__ __launch_bounds__(128) void k_fft_x_r2c_256(const T* in, cplx<T>* out, int64_t rows, const cplx<T>* tw) {
+  constexpr int P = R2C256_P;
+  __shared__ cplx<T> sT[P * 272];
+  __shared__ cplx<T> sZ[P * 256];
+  const int q = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int64_t r0 = 2 * ((int64_t)blockIdx.x * P + q), r1 = r0 + 1;
+  const int64_t a0 = r0 < rows ? r0 : 0, a1 = r1 < rows ? r1 : 0;
+  cplx<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const T x0 = in[a0 * 256 + 16 * n1 + l], x1 = in[a1 * 256 + 16 * n1 + l];
+    v[n1] = mk(r0 < rows ? x0 : (T)0, r1 < rows ? x1 : (T)0);
+  }
+  dft16(v, tw, false);
+  cplx<T>* st = sT + q * 272;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = (p >> 2) + 4 * (p & 3);
+    st[k1 * 17 + l] = k1 == 0 || l == 0 ? v[p] : v[p] * twid256(tw, l * k1, false);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = st[l * 17 + m];
+  dft16(v, tw, false);
+  cplx<T>* sz = sZ + q * 256;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) sz[l + 16 * ((p >> 2) + 4 * (p & 3))] = v[p];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < P * 128; idx += 128) {
+    const int qq = idx >> 7, k = idx & 127;
+    const int64_t b0 = 2 * ((int64_t)blockIdx.x * P + qq), b1 = b0 + 1;
+    const cplx<T> zk = sZ[qq * 256 + k];
+    const cplx<T> zc = conj(sZ[qq * 256 + ((256 - k) & 255)]);
+    const cplx<T> A = (T)0.5 * (zk + zc);
+    const cplx<T> D = zk - zc;
+    const cplx<T> B = mk((T)0.5 * D.y, (T)-0.5 * D.x);
+    if (b0 < rows) out[b0 * 128 + k] = A;
+    if (b1 < rows) out[b1 * 128 + k] = B;
+  }
+}
+
 // Forward transform along x of pairs of real rows (two-for-one): rows 2r and
 // 2r+1 of in[rows][Nx] -> out[rows][Nxh].  nseq pairs per work-group.
 template <typename T>
@@ -210,38 +291,6 @@ __global__ __launch_bounds__(512) void k_fft_y(cplx<T>* data, int Ny, int Nxh, i
 // thread (c, k1) does the outer DFT and writes the rows k1 + 16 k2.  Eight
 // columns per 128-thread work-group; the inverse conjugates the twiddles and
 // scales by 1/256.  tw holds exp(-2 pi i t / 256) for t < 128.
-// exp(-+2 pi i e / 256), 0 <= e < 256, from a table tw[t] = exp(-2 pi i t / N)
-// (t < N / 2) of N = 256 S
-template <typename T>
-GP_DEV cplx<T> twid256(const cplx<T>* tw, int e, bool inverse, int S = 1) {
-  cplx<T> w = e < 128 ? tw[e * S] : mk(-tw[(e - 128) * S].x, -tw[(e - 128) * S].y);
-  if (inverse) w.y = -w.y;
-  return w;
-}
-// 4-point DFT in place
-template <typename T>
-GP_DEV void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3, bool inverse) {
-  const cplx<T> b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3, b3 = a1 - a3;
-  const cplx<T> ib3 = mul_i(b3);
-  a0 = b0 + b2;
-  a2 = b0 - b2;
-  a1 = inverse ? b1 + ib3 : b1 - ib3;
-  a3 = inverse ? b1 - ib3 : b1 + ib3;
-}
-// 16-point DFT of v[n] as 4 x 4 (n = 4 m1 + m2, k = l1 + 4 l2); the result
-// for k = l1 + 4 l2 is left in v[4 l1 + l2]
-template <typename T>
-GP_DEV void dft16(cplx<T> v[16], const cplx<T>* tw, bool inverse, int S = 1) {
-#pragma unroll
-  for (int m2 = 0; m2 < 4; ++m2) dft4(v[m2], v[4 + m2], v[8 + m2], v[12 + m2], inverse);
-#pragma unroll
-  for (int l1 = 1; l1 < 4; ++l1)
-#pragma unroll
-    for (int m2 = 1; m2 < 4; ++m2) v[4 * l1 + m2] = v[4 * l1 + m2] * twid256(tw, 16 * m2 * l1, inverse, S);
-#pragma unroll
-  for (int l1 = 0; l1 < 4; ++l1) dft4(v[4 * l1], v[4 * l1 + 1], v[4 * l1 + 2], v[4 * l1 + 3], inverse);
-}
-
 constexpr int FY256_NC = 8;                  // columns per work-group
 constexpr int FY256_KS = 16 * FY256_NC + 4;  // LDS stride of one k1 (padded)
 

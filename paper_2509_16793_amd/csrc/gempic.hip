@@ -253,7 +253,10 @@ struct Impl {
     int64_t pairs = (rows + 1) / 2;
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 1024 / G.Nx));
     size_t sh = (2 * (size_t)nseq + 1) * G.Nx * sizeof(C);
-    k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
+    if (G.Nx == 256)
+      k_fft_x_r2c_256<T><<<(unsigned)((pairs + R2C256_P - 1) / R2C256_P), 128, 0, g->s>>>(in, out, rows, (const C*)g->twx);
+    else
+      k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
     if (G.Ny > 1) fft_y(g, out, planes, 0);
   }
   // six field spectra (outs) -> interleaved real node records F6
