@@ -288,19 +288,21 @@ __global__ __launch_bounds__(512) void k_fft_y(cplx<T>* data, int Ny, int Nxh, i
 //   X[k1 + 16 k2] = sum_n2 W16^(n2 k2) W256^(n2 k1) sum_n1 W16^(n1 k1) x[16 n1 + n2].
 // Thread (column c, n2) takes the 16 rows n2 + 16 n1 into registers, does the
 // inner 16-point DFT there and applies W256^(n2 k1); after one LDS transpose
-// thread (c, k1) does the outer DFT and writes the rows k1 + 16 k2.  Eight
-// columns per 128-thread work-group; the inverse conjugates the twiddles and
-// scales by 1/256.  tw holds exp(-2 pi i t / 256) for t < 128.
-constexpr int FY256_NC = 8;                  // columns per work-group
-constexpr int FY256_KS = 16 * FY256_NC + 4;  // LDS stride of one k1 (padded)
-
+// thread (c, k1) does the outer DFT and writes the rows k1 + 16 k2.  A
+// work-group takes the columns of one 128-byte segment of every row (16 FP32
+// or 8 FP64 complex values), 16 threads per column; the inverse conjugates
+// the twiddles and scales by 1/256.  tw holds exp(-2 pi i t / 256) for
+// t < 128.
+// columns per work-group (one 128-byte row segment)
+template <typename T> constexpr int fy_nc() { return 128 / (int)sizeof(cplx<T>); }
 template <typename T>
-__global__ __launch_bounds__(128) void k_fft_y256(cplx<T>* data, int Nxh, const cplx<T>* tw, int inverse) {
-  __shared__ cplx<T> sY[16 * FY256_KS];      // [k1][n2][c]
-  const int cpp = Nxh / FY256_NC;
+__global__ __launch_bounds__(256) void k_fft_y256(cplx<T>* data, int Nxh, const cplx<T>* tw, int inverse) {
+  constexpr int NC = fy_nc<T>(), KS = 16 * NC + 4;
+  __shared__ cplx<T> sY[16 * KS];      // [k1][n2][c]
+  const int cpp = Nxh / NC;
   const int64_t plane = blockIdx.x / cpp;
-  const int c0 = (int)(blockIdx.x % cpp) * FY256_NC;
-  const int c = threadIdx.x % FY256_NC, q = threadIdx.x / FY256_NC;   // q: n2, then k1
+  const int c0 = (int)(blockIdx.x % cpp) * NC;
+  const int c = threadIdx.x % NC, q = threadIdx.x / NC;   // q: n2, then k1
   cplx<T>* col = data + plane * 256 * Nxh + c0 + c;
   const bool inv = inverse != 0;
   cplx<T> v[16];
@@ -310,11 +312,11 @@ __global__ __launch_bounds__(128) void k_fft_y256(cplx<T>* data, int Nxh, const 
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int k1 = (p >> 2) + 4 * (p & 3);
-    sY[k1 * FY256_KS + q * FY256_NC + c] = k1 == 0 || q == 0 ? v[p] : v[p] * twid256(tw, q * k1, inv);
+    sY[k1 * KS + q * NC + c] = k1 == 0 || q == 0 ? v[p] : v[p] * twid256(tw, q * k1, inv);
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = sY[q * FY256_KS + m * FY256_NC + c];
+  for (int m = 0; m < 16; ++m) v[m] = sY[q * KS + m * NC + c];
   dft16(v, tw, inv);
   const T sc = inv ? (T)1 / (T)256 : (T)1;
 #pragma unroll
@@ -324,21 +326,22 @@ __global__ __launch_bounds__(128) void k_fft_y256(cplx<T>* data, int Nxh, const 
   }
 }
 
-// Transform along y for Ny = 512: the even rows (threads 0 .. 127) and the
-// odd rows (128 .. 255) each take the 256-point four-step transform above,
-// then X[k] = E[k] + W512^k O[k] and X[k + 256] = E[k] - W512^k O[k].  tw
-// holds exp(-2 pi i t / 512) for t < 256.
+// Transform along y for Ny = 512: with NC columns per work-group, the even
+// rows (the first 16 NC threads) and the odd rows (the other 16 NC) each take
+// the 256-point four-step transform above, then X[k] = E[k] + W512^k O[k] and
+// X[k + 256] = E[k] - W512^k O[k].  tw holds exp(-2 pi i t / 512) for t < 256.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_y512(cplx<T>* data, int Nxh, const cplx<T>* tw, int inverse) {
-  __shared__ cplx<T> sY[2 * 16 * FY256_KS];  // per half [k1][n2][c]; then the halves' results [h][k][c]
-  const int cpp = Nxh / FY256_NC;
+__global__ __launch_bounds__(512) void k_fft_y512(cplx<T>* data, int Nxh, const cplx<T>* tw, int inverse) {
+  constexpr int NC = fy_nc<T>(), KS = 16 * NC + 4, TH = 16 * NC;
+  __shared__ cplx<T> sY[2 * 16 * KS];  // per half [k1][n2][c]; then the halves' results [h][k][c]
+  const int cpp = Nxh / NC;
   const int64_t plane = blockIdx.x / cpp;
-  const int c0 = (int)(blockIdx.x % cpp) * FY256_NC;
-  const int h = threadIdx.x >> 7, t = threadIdx.x & 127;
-  const int c = t % FY256_NC, q = t / FY256_NC;   // q: n2, then k1
+  const int c0 = (int)(blockIdx.x % cpp) * NC;
+  const int h = threadIdx.x / TH, t = threadIdx.x % TH;
+  const int c = t % NC, q = t / NC;   // q: n2, then k1
   cplx<T>* const base = data + plane * 512 * Nxh + c0;
   cplx<T>* col = base + c;
-  cplx<T>* sh = sY + h * 16 * FY256_KS;
+  cplx<T>* sh = sY + h * 16 * KS;
   const bool inv = inverse != 0;
   cplx<T> v[16];
 #pragma unroll
@@ -347,23 +350,23 @@ __global__ __launch_bounds__(256) void k_fft_y512(cplx<T>* data, int Nxh, const 
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int k1 = (p >> 2) + 4 * (p & 3);
-    sh[k1 * FY256_KS + q * FY256_NC + c] = k1 == 0 || q == 0 ? v[p] : v[p] * twid256(tw, q * k1, inv, 2);
+    sh[k1 * KS + q * NC + c] = k1 == 0 || q == 0 ? v[p] : v[p] * twid256(tw, q * k1, inv, 2);
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = sh[q * FY256_KS + m * FY256_NC + c];
+  for (int m = 0; m < 16; ++m) v[m] = sh[q * KS + m * NC + c];
   dft16(v, tw, inv, 2);
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int k = q + 16 * ((p >> 2) + 4 * (p & 3));
-    sY[(h * 256 + k) * FY256_NC + c] = v[p];
+    sY[(h * 256 + k) * NC + c] = v[p];
   }
   __syncthreads();
   const T sc = inv ? (T)1 / (T)512 : (T)1;
-  for (int idx = threadIdx.x; idx < 256 * FY256_NC; idx += 256) {
-    const int cc = idx % FY256_NC, k = idx / FY256_NC;
-    const cplx<T> E = sY[k * FY256_NC + cc], O = sY[(256 + k) * FY256_NC + cc];
+  for (int idx = threadIdx.x; idx < 256 * NC; idx += 2 * TH) {
+    const int cc = idx % NC, k = idx / NC;
+    const cplx<T> E = sY[k * NC + cc], O = sY[(256 + k) * NC + cc];
     cplx<T> w = tw[k];
     if (inv) w.y = -w.y;
     const cplx<T> wO = w * O;

@@ -232,14 +232,14 @@ struct Impl {
   // transform along y of data[planes][Ny][Nxh] in place
   static void fft_y(gempic* g, C* data, int64_t planes, int inverse) {
     const Geom& G = g->g;
-    if (G.Ny == 256 && G.Nxh % FY256_NC == 0) {
-      k_fft_y256<T><<<(unsigned)(planes * (G.Nxh / FY256_NC)), 128, 0, g->s>>>(data, G.Nxh, (const C*)g->twy,
-                                                                               inverse);
+    if (G.Ny == 256 && G.Nxh % fy_nc<T>() == 0) {
+      k_fft_y256<T><<<(unsigned)(planes * (G.Nxh / fy_nc<T>())), 16 * fy_nc<T>(), 0, g->s>>>(
+          data, G.Nxh, (const C*)g->twy, inverse);
       return;
     }
-    if (G.Ny == 512 && G.Nxh % FY256_NC == 0) {
-      k_fft_y512<T><<<(unsigned)(planes * (G.Nxh / FY256_NC)), 256, 0, g->s>>>(data, G.Nxh, (const C*)g->twy,
-                                                                               inverse);
+    if (G.Ny == 512 && G.Nxh % fy_nc<T>() == 0) {
+      k_fft_y512<T><<<(unsigned)(planes * (G.Nxh / fy_nc<T>())), 32 * fy_nc<T>(), 0, g->s>>>(
+          data, G.Nxh, (const C*)g->twy, inverse);
       return;
     }
     int ncol = std::min(G.Nxh, std::max(1, 2048 / G.Ny));
