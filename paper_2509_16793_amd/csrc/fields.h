@@ -110,14 +110,15 @@ GP_DEV void dft16(cplx<T> v[16], const cplx<T>* tw, bool inverse, int S = 1) {
 // k_fft_x_r2c), as the four-step 16 x 16 DFT: 16 threads per row pair read
 // the pair's rows 16 n1 + l straight into registers, the inner DFT, twiddles
 // and one LDS transpose precede the outer DFT, and the spectra of both rows
-// are split from the pair's transform in LDS.  8 pairs per 128-thread
-// work-group; rows past the end read row 0 and are not written.
+// are split from the pair's transform in LDS, which reuses the transpose
+// buffer (17 KB in FP32: up to 9 work-groups fit in a CU's LDS).  8 pairs per
+// 128-thread work-group; rows past the end read row 0 and are not written.
 constexpr int R2C256_P = 8;
 template <typename T>
 __global__ __launch_bounds__(128) void k_fft_x_r2c_256(const T* in, cplx<T>* out, int64_t rows, const cplx<T>* tw) {
   constexpr int P = R2C256_P;
   __shared__ cplx<T> sT[P * 272];
-  __shared__ cplx<T> sZ[P * 256];
+  cplx<T>* const sZ = sT;                    // the pair's transform, after the transpose
   const int q = threadIdx.x >> 4, l = threadIdx.x & 15;
   const int64_t r0 = 2 * ((int64_t)blockIdx.x * P + q), r1 = r0 + 1;
   const int64_t a0 = r0 < rows ? r0 : 0, a1 = r1 < rows ? r1 : 0;
@@ -138,6 +139,7 @@ __global__ __launch_bounds__(128) void k_fft_x_r2c_256(const T* in, cplx<T>* out
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = st[l * 17 + m];
   dft16(v, tw, false);
+  __syncthreads();
   cplx<T>* sz = sZ + q * 256;
 #pragma unroll
   for (int p = 0; p < 16; ++p) sz[l + 16 * ((p >> 2) + 4 * (p & 3))] = v[p];
@@ -152,6 +154,64 @@ __global__ __launch_bounds__(128) void k_fft_x_r2c_256(const T* in, cplx<T>* out
     const cplx<T> B = mk((T)0.5 * D.y, (T)-0.5 * D.x);
     if (b0 < rows) out[b0 * 128 + k] = A;
     if (b1 < rows) out[b1 * 128 + k] = B;
+  }
+}
+
+// Forward x transform of row pairs for Nx = 512 (two-for-one, as
+// k_fft_x_r2c): the even and the odd nodes of a pair's rows each take the
+// 256-point four-step transform of k_fft_x_r2c_256 (16 threads each), then
+// Z[k] = E[k] + W512^k O[k] and Z[k + 256] = E[k] - W512^k O[k] give the
+// pair's transform, and the spectra of both rows are split from it; E and O
+// reuse the transpose buffer.  4 pairs per 128-thread work-group; rows past
+// the end read row 0 and are not written.  tw holds exp(-2 pi i t / 512) for
+// t < 256.
+constexpr int R2C512_P = 4;
+template <typename T>
+__global__ __launch_bounds__(128) void k_fft_x_r2c_512(const T* in, cplx<T>* out, int64_t rows, const cplx<T>* tw) {
+  constexpr int P = R2C512_P;
+  __shared__ cplx<T> sT[P * 2 * 272];
+  cplx<T>* const sH = sT;                    // per pair: E[0..255], O[0..255], after the transpose
+  const int q = threadIdx.x >> 5, h = (threadIdx.x >> 4) & 1, l = threadIdx.x & 15;
+  const int64_t r0 = 2 * ((int64_t)blockIdx.x * P + q), r1 = r0 + 1;
+  const int64_t a0 = r0 < rows ? r0 : 0, a1 = r1 < rows ? r1 : 0;
+  cplx<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int n = 2 * (16 * n1 + l) + h;
+    const T x0 = in[a0 * 512 + n], x1 = in[a1 * 512 + n];
+    v[n1] = mk(r0 < rows ? x0 : (T)0, r1 < rows ? x1 : (T)0);
+  }
+  dft16(v, tw, false, 2);
+  cplx<T>* st = sT + (2 * q + h) * 272;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = (p >> 2) + 4 * (p & 3);
+    st[k1 * 17 + l] = k1 == 0 || l == 0 ? v[p] : v[p] * twid256(tw, l * k1, false, 2);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = st[l * 17 + m];
+  dft16(v, tw, false, 2);
+  __syncthreads();
+  cplx<T>* sh = sH + q * 512 + h * 256;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) sh[l + 16 * ((p >> 2) + 4 * (p & 3))] = v[p];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < P * 256; idx += 128) {
+    const int qq = idx >> 8, k = idx & 255;
+    const cplx<T>* E = sH + qq * 512;
+    const cplx<T>* O = E + 256;
+    const cplx<T> zk = E[k] + tw[k] * O[k];
+    // Z[512 - k] = E[256 - k] - W512^(256 - k) O[256 - k] for k > 0; Z[0] for k = 0
+    const int j = (256 - k) & 255;
+    const cplx<T> zm = k == 0 ? zk : E[j] - tw[j] * O[j];
+    const cplx<T> zc = conj(zm);
+    const int64_t b0 = 2 * ((int64_t)blockIdx.x * P + qq), b1 = b0 + 1;
+    const cplx<T> A = (T)0.5 * (zk + zc);
+    const cplx<T> D = zk - zc;
+    const cplx<T> B = mk((T)0.5 * D.y, (T)-0.5 * D.x);
+    if (b0 < rows) out[b0 * 256 + k] = A;
+    if (b1 < rows) out[b1 * 256 + k] = B;
   }
 }
 

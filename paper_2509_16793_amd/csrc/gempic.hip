@@ -255,6 +255,8 @@ struct Impl {
     size_t sh = (2 * (size_t)nseq + 1) * G.Nx * sizeof(C);
     if (G.Nx == 256)
       k_fft_x_r2c_256<T><<<(unsigned)((pairs + R2C256_P - 1) / R2C256_P), 128, 0, g->s>>>(in, out, rows, (const C*)g->twx);
+    else if (G.Nx == 512)
+      k_fft_x_r2c_512<T><<<(unsigned)((pairs + R2C512_P - 1) / R2C512_P), 128, 0, g->s>>>(in, out, rows, (const C*)g->twx);
     else
       k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
     if (G.Ny > 1) fft_y(g, out, planes, 0);

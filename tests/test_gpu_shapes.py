@@ -109,6 +109,16 @@ def test_nx256_transforms_fp32():
     _check(workloads.small3d(precision="fp32", n=(256, 16, 32), steps=2), 2, bar=2e-4, particles=False)
 
 
+# Nx = 512 rows (the PWFA row length): the radix-2 step over two 256-point
+# four-step x transforms
+def test_nx512_transforms_fp64():
+    _check(workloads.small3d(precision="fp64", n=(512, 8, 32), steps=2), 2)
+
+
+def test_nx512_transforms_fp32():
+    _check(workloads.small3d(precision="fp32", n=(512, 8, 32), steps=2), 2, bar=2e-4, particles=False)
+
+
 # configurations the library rejects at creation, each with the reason it
 # names: a grid size that is not a power of two, a tile shape it does not
 # support, a slow step beyond h / 2, and a transverse grid wider than the LDS
