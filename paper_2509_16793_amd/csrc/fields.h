@@ -758,3 +758,20 @@ __global__ void k_fill(T* p, int64_t n, T v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+// The same fill with one 16-byte store per thread over a 16-byte aligned p;
+// threads past the nv = n / W vectors write the n % W tail elements.
+template <typename T>
+__global__ void k_fill16(T* p, int64_t n, T v) {
+  constexpr int W = 16 / (int)sizeof(T);
+  struct alignas(16) V { T e[W]; };
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = n / W;
+  if (i < nv) {
+    V x;
+#pragma unroll
+    for (int k = 0; k < W; ++k) x.e[k] = v;
+    reinterpret_cast<V*>(p)[i] = x;
+  } else if (i - nv < n - nv * W) {
+    p[nv * W + (i - nv)] = v;
+  }
+}

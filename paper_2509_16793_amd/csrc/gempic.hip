@@ -225,7 +225,12 @@ struct Impl {
 
   static void fill(gempic* g, void* p, int64_t n) {
     if (n <= 0) return;
-    k_fill<T><<<nblk(n, 256), 256, 0, g->s>>>((T*)p, n, (T)0);
+    if (((uintptr_t)p & 15) == 0) {
+      const int64_t w = 16 / (int64_t)sizeof(T);
+      k_fill16<T><<<nblk(n / w + n % w, 256), 256, 0, g->s>>>((T*)p, n, (T)0);
+    } else {
+      k_fill<T><<<nblk(n, 256), 256, 0, g->s>>>((T*)p, n, (T)0);
+    }
   }
 
   // ---- FFT helpers --------------------------------------------------------
