@@ -248,6 +248,73 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const T* in, cplx<T>* out, in
   }
 }
 
+// Inverse x transform of the six field components for Nx = 256, four-step:
+// 16 threads per (row pair, component) assemble the pair's Hermitian
+// sequence x[j] = A[j] + i B[j] (x[256 - j] = conj(A[j]) + i conj(B[j]),
+// x[128] = 0) straight into registers, run the inverse 16 x 16 DFT with one
+// LDS transpose, and leave z[n] in the same LDS buffer; the node records of
+// both rows are then written as in k_fft_x_c2r6.  2 row pairs per 192-thread
+// work-group; rows past the end read row 0 and are not written.
+constexpr int C2R256_P = 2;
+template <typename T>
+__global__ __launch_bounds__(192) void k_fft_x_c2r6_256(const cplx<T>* i0, const cplx<T>* i1, const cplx<T>* i2,
+                                                        const cplx<T>* i3, const cplx<T>* i4, const cplx<T>* i5,
+                                                        T* out, int64_t rows, const cplx<T>* tw) {
+  constexpr int P = C2R256_P;
+  __shared__ cplx<T> sT[P * 6 * 272];
+  const int pr = threadIdx.x / 96, rest = threadIdx.x - 96 * pr;
+  const int q = rest >> 4, l = rest & 15;
+  const cplx<T>* in = q == 0 ? i0 : q == 1 ? i1 : q == 2 ? i2 : q == 3 ? i3 : q == 4 ? i4 : i5;
+  const int64_t r0 = 2 * ((int64_t)blockIdx.x * P + pr), r1 = r0 + 1;
+  const int64_t a0 = r0 < rows ? r0 : 0, a1 = r1 < rows ? r1 : 0;
+  cplx<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int j = 16 * n1 + l;
+    const int jj = n1 < 8 ? j : (256 - j) & 127;
+    const cplx<T> A = in[a0 * 128 + jj], B = in[a1 * 128 + jj];
+    if (n1 < 8) v[n1] = A + mul_i(B);
+    else v[n1] = j == 128 ? mk((T)0, (T)0) : conj(A) + mul_i(conj(B));
+  }
+  dft16(v, tw, true);
+  cplx<T>* st = sT + (pr * 6 + q) * 272;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = (p >> 2) + 4 * (p & 3);
+    st[k1 * 17 + l] = k1 == 0 || l == 0 ? v[p] : v[p] * twid256(tw, l * k1, true);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = st[l * 17 + m];
+  dft16(v, tw, true);
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 16; ++p) st[l + 16 * ((p >> 2) + 4 * (p & 3))] = v[p];
+  __syncthreads();
+  const T sc = (T)1 / (T)256;
+  for (int idx = threadIdx.x; idx < P * 256; idx += 192) {
+    const int pp = idx >> 8, n = idx & 255;
+    const int64_t b0 = 2 * ((int64_t)blockIdx.x * P + pp), b1 = b0 + 1;
+    T a[6], b[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const cplx<T> z = sT[(pp * 6 + c) * 272 + n];
+      a[c] = sc * z.x;
+      b[c] = sc * z.y;
+    }
+    if (b0 < rows) {
+      T* o = out + (b0 * 256 + n) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = a[c];
+    }
+    if (b1 < rows) {
+      T* o = out + (b1 * 256 + n) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = b[c];
+    }
+  }
+}
+
 // Inverse of the x transform for the six field components at once, written
 // as interleaved node records out[row][Nx][6] (scaled by 1/Nx).
 template <typename T>

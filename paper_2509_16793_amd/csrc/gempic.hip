@@ -275,6 +275,12 @@ struct Impl {
     int64_t pairs = (rows + 1) / 2;
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / (6 * G.Nx)));
     size_t sh = (2 * (size_t)6 * nseq + 1) * G.Nx * sizeof(C);
+    if (G.Nx == 256) {
+      k_fft_x_c2r6_256<T><<<(unsigned)((pairs + C2R256_P - 1) / C2R256_P), 192, 0, g->s>>>(
+          (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
+          (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, (const C*)g->twx);
+      return;
+    }
     k_fft_x_c2r6<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(
         (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
         (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, G.Nx, nseq, (const C*)g->twx);
