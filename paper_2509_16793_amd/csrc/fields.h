@@ -315,6 +315,74 @@ __global__ __launch_bounds__(192) void k_fft_x_c2r6_256(const cplx<T>* i0, const
   }
 }
 
+// Inverse x transform of the six field components for Nx = 512: per
+// (row pair, component) the even and the odd nodes of the Hermitian sequence
+// each take the inverse 256-point four-step transform of k_fft_x_c2r6_256
+// (16 threads each), and z[m] = E[m] + W512^-m O[m], z[m + 256] = E[m] -
+// W512^-m O[m] are formed as the node records are written.  One row pair per
+// 192-thread work-group; E and O reuse the transpose buffer.  tw holds
+// exp(-2 pi i t / 512) for t < 256.
+template <typename T>
+__global__ __launch_bounds__(192) void k_fft_x_c2r6_512(const cplx<T>* i0, const cplx<T>* i1, const cplx<T>* i2,
+                                                        const cplx<T>* i3, const cplx<T>* i4, const cplx<T>* i5,
+                                                        T* out, int64_t rows, const cplx<T>* tw) {
+  __shared__ cplx<T> sT[12 * 272];           // per (component, half); then E, O per component
+  const int q = threadIdx.x >> 5, h = (threadIdx.x >> 4) & 1, l = threadIdx.x & 15;
+  const cplx<T>* in = q == 0 ? i0 : q == 1 ? i1 : q == 2 ? i2 : q == 3 ? i3 : q == 4 ? i4 : i5;
+  const int64_t r0 = 2 * (int64_t)blockIdx.x, r1 = r0 + 1;
+  const int64_t a0 = r0 < rows ? r0 : 0, a1 = r1 < rows ? r1 : 0;
+  cplx<T> v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int j = 2 * (16 * n1 + l) + h;
+    const int jj = n1 < 8 ? j : (512 - j) & 255;
+    const cplx<T> A = in[a0 * 256 + jj], B = in[a1 * 256 + jj];
+    if (n1 < 8) v[n1] = A + mul_i(B);
+    else v[n1] = j == 256 ? mk((T)0, (T)0) : conj(A) + mul_i(conj(B));
+  }
+  dft16(v, tw, true, 2);
+  cplx<T>* st = sT + (2 * q + h) * 272;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = (p >> 2) + 4 * (p & 3);
+    st[k1 * 17 + l] = k1 == 0 || l == 0 ? v[p] : v[p] * twid256(tw, l * k1, true, 2);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = st[l * 17 + m];
+  dft16(v, tw, true, 2);
+  __syncthreads();
+  cplx<T>* sh = sT + q * 512 + h * 256;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) sh[l + 16 * ((p >> 2) + 4 * (p & 3))] = v[p];
+  __syncthreads();
+  const T sc = (T)1 / (T)512;
+  for (int n = threadIdx.x; n < 512; n += 192) {
+    const int m = n & 255;
+    cplx<T> w = tw[m];
+    w.y = -w.y;
+    T a[6], b[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const cplx<T> wO = w * sT[c * 512 + 256 + m];
+      const cplx<T> E = sT[c * 512 + m];
+      const cplx<T> z = n < 256 ? E + wO : E - wO;
+      a[c] = sc * z.x;
+      b[c] = sc * z.y;
+    }
+    if (r0 < rows) {
+      T* o = out + (r0 * 512 + n) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = a[c];
+    }
+    if (r1 < rows) {
+      T* o = out + (r1 * 512 + n) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = b[c];
+    }
+  }
+}
+
 // Inverse of the x transform for the six field components at once, written
 // as interleaved node records out[row][Nx][6] (scaled by 1/Nx).
 template <typename T>

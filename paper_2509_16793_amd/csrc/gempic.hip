@@ -281,6 +281,12 @@ struct Impl {
           (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, (const C*)g->twx);
       return;
     }
+    if (G.Nx == 512) {
+      k_fft_x_c2r6_512<T><<<(unsigned)pairs, 192, 0, g->s>>>(
+          (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
+          (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, (const C*)g->twx);
+      return;
+    }
     k_fft_x_c2r6<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(
         (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
         (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, G.Nx, nseq, (const C*)g->twx);
