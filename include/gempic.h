@@ -30,8 +30,10 @@
  *   - Thread-compatible, not thread-safe: one handle per host thread.
  *   - After GEMPIC_EDEVICE, GEMPIC_ECFL, GEMPIC_ENUMERIC or GEMPIC_ECAPACITY the
  *     handle is "failed": the particle/field state is undefined (a step may
- *     have been applied partially) and only getters, gempic_last_error and
- *     gempic_destroy are accepted.
+ *     have been applied partially; the step keeps no copy of the pre-step
+ *     state, which would double the particle memory) and only getters,
+ *     gempic_last_error and gempic_destroy are accepted.  The flags are read
+ *     once per gempic_step call, after its last step.
  */
 #ifndef GEMPIC_H
 #define GEMPIC_H
@@ -60,7 +62,8 @@ typedef enum {
   GEMPIC_ENUMERIC = -5,   /* NaN or Inf in the state                               */
   GEMPIC_ESTATE = -6,     /* call not allowed in the handle's state                */
   GEMPIC_EABI = -7,       /* abi_version mismatch                                  */
-  GEMPIC_ECAPACITY = -8   /* particle buffer capacity exceeded                     */
+  GEMPIC_ECAPACITY = -8   /* particle buffer capacity exceeded, or (FP64) a tile
+                             denser than the deposit's fixed-point range          */
 } gempic_status;
 
 typedef enum {
@@ -82,8 +85,8 @@ typedef struct {
   int32_t abi_version;      /* must equal GEMPIC_ABI_VERSION                            */
   int32_t dims;             /* 2 = (x, zeta), 3 = (x, y, zeta)                          */
   int32_t n[3];             /* Nx, Ny (ignored in 2-D), Nzeta: powers of two, >= 2;
-                               Nx <= 512 in FP64 and <= 1024 in FP32, Ny <= 2048 (the
-                               transverse transforms hold whole rows in LDS)            */
+                               Nx, Ny <= 512 (the transverse transforms hold whole
+                               rows in LDS)                                             */
   double  d[3];             /* hx, hy (ignored in 2-D), h (zeta step), config units     */
   double  length_unit;      /* > 0                                                      */
   double  dtau;             /* slow step, config units; 0 selects h / 2.  2 dtau > h or
@@ -159,12 +162,24 @@ typedef struct {
  * gempic_last_error(NULL) until the next call). */
 int gempic_create(const gempic_config* cfg, gempic_t** out);
 
-/* Advance nsteps slow steps.  diag (nullable) receives the FP64 diagnostics
- * of the last step; computing them adds reductions to that step only. */
+/* Advance nsteps slow steps (Sec. 4.1: the slow coordinate s = tau advances by
+ * Delta = dtau per step).  Each step gathers the level-k node fields, pushes
+ * every particle along the characteristics of eq:Vlasov1 (Sec. 5), deposits
+ * the beam-particle current j = q n v of Sec. 5.1 in charge-conserving form,
+ * injects the fresh plasma the window sweeps over, and marches the node
+ * system RxN .. eqall right to left with the App. B solution.
+ * diag (nullable) receives the FP64 diagnostics of the last step; computing
+ * them adds reductions to that step only.  Errors: GEMPIC_ESTATE on a failed
+ * handle, GEMPIC_ECFL (a particle crossed more than one cell), GEMPIC_ENUMERIC
+ * (a non-finite momentum), GEMPIC_ECAPACITY, GEMPIC_EDEVICE; each fails the
+ * handle. */
 int gempic_step(gempic_t* g, int32_t nsteps, gempic_diag* diag);
 
 /* Copy the selected real-space fields, in bit order, each as one array of the
- * handle's precision (double for GEMPIC_FP64, float otherwise):
+ * handle's precision (double for GEMPIC_FP64, float otherwise).  E and B are
+ * the node fields of the current slow level, E_x = (R_x + L_x)/2,
+ * B_y = (R_x - L_x)/2, E_y = (R_y + L_y)/2, B_x = (L_y - R_y)/2 (Sec. 3.1,
+ * eq:Rx .. eq:Ly), transformed back from the transverse spectrum:
  *   E, B:   [Nzeta][Ny][Nx]            node (i, j, n) at (i hx, j hy, n h)
  *   J, rho: [Nzeta + filter_passes + 7][Ny][Nx]; plane p holds node n = p - 2
  *           (J_x at x index i is J_x(i + 1/2); J_y at y index j is J_y(j + 1/2)
@@ -176,7 +191,9 @@ int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size
 /* Number of bytes gempic_fields needs for mask. */
 size_t gempic_fields_bytes(const gempic_t* g, uint32_t mask);
 
-/* Copy the particles (structure of arrays, in the handle's sorted order):
+/* Copy the particles (structure of arrays, in the handle's sorted order) --
+ * the macro-particles of Sec. 5.1 (plasma electrons of weight Q_b / ppc and
+ * driver-beam electrons), at the current slow level:
  * cell[i] = (iz * Ny + iy) * Nx + ix (int32), with GEMPIC_BEAM_BIT set for
  * driver-beam electrons; off = 3 planes of
  * capacity entries (offset in [0,1) along x, y, zeta); u = 3 planes of

@@ -213,6 +213,21 @@ def continuity_rel(J, Jf, hx, hy, h):
     return num / den if den > 0 else (0.0 if num == 0 else np.inf)
 
 
+def correction_ratio(J, Jf):
+    """Size test of the denoised current: ||J - F(J_raw)|| over ||F(J_raw)||,
+    the correction relative to the filtered current it corrects."""
+    num = np.sqrt(np.sum((J - Jf) ** 2))
+    den = np.sqrt(np.sum(Jf ** 2))
+    return num / den if den > 0 else (0.0 if num == 0 else np.inf)
+
+
+def keep_network(J, Jf, hx, hy, h, threshold, corr_max=1.0):
+    """The step keeps the denoised current J when its continuity ratio is at
+    most threshold and its correction is at most corr_max times the filtered
+    current; otherwise it falls back to F(J_raw)."""
+    return bool(continuity_rel(J, Jf, hx, hy, h) <= threshold and correction_ratio(J, Jf) <= corr_max)
+
+
 def adam(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     """Adam step t (1-based) with bias correction; returns new (theta, m, v)."""
     m = b1 * m + (1.0 - b1) * g

@@ -698,9 +698,10 @@ GP_DEV double block_sum_d(double v, double* sh) {
   return t;
 }
 
-// Jd = Jf + s curl(A); per-block partial sums of |D.(s curl A)|^2 and
-// |D.Jf|^2 into part[2 * block + {0, 1}] (a fixed grid of COMB_BLOCKS
-// blocks strides over the work, so that the sums need no global atomics).
+// Jd = Jf + s curl(A); per-block partial sums of |D.(s curl A)|^2, |D.Jf|^2,
+// |s curl A|^2 and |Jf|^2 into part[4 * block + {0, 1, 2, 3}] (a fixed grid
+// of COMB_BLOCKS blocks strides over the work, so that the sums need no
+// global atomics).
 // A work item is one (x, y) column through CZ planes: the values of plane
 // z - 1 that the curl and the divergences need are carried in registers.
 constexpr int COMB_BLOCKS = 2048;
@@ -712,7 +713,7 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
   const int ncol = B.X * B.Y;
   const int nwork = ncol * ((B.Z + CZ - 1) / CZ);
   const int64_t plane = ncol;
-  double num = 0.0, den = 0.0;
+  double num = 0.0, den = 0.0, cc = 0.0, jj = 0.0;
   for (int w = blockIdx.x * 256 + threadIdx.x; w < nwork; w += gridDim.x * 256) {
     const int col = w % ncol, z0 = (w / ncol) * CZ;
     const int x = col % B.X, y = col / B.X;
@@ -750,6 +751,8 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
                         (double)(j2 - pj2) * a.ih;
       num += dc * dc;
       den += df * df;
+      cc += (double)c0 * c0 + (double)c1 * c1 + (double)c2 * c2;
+      jj += (double)j0 * j0 + (double)j1 * j1 + (double)j2 * j2;
       pax = ax;
       paxy = axy;
       pay = ay;
@@ -761,27 +764,48 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
   double tn = block_sum_d(num, sh);
   __syncthreads();
   double td = block_sum_d(den, sh);
+  __syncthreads();
+  double tc = block_sum_d(cc, sh);
+  __syncthreads();
+  double tj = block_sum_d(jj, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = tn;
-    part[2 * blockIdx.x + 1] = td;
+    part[4 * blockIdx.x] = tn;
+    part[4 * blockIdx.x + 1] = td;
+    part[4 * blockIdx.x + 2] = tc;
+    part[4 * blockIdx.x + 3] = tj;
   }
 }
 
-// sum the partials and decide between the corrected and the filtered current
+// sum the partials and decide between the corrected and the filtered current.
+// Two criteria, both needed to keep the network's current:
+//  - continuity: ||D.(s curl A)|| / ||D.Jf|| <= thr.  D.curl vanishes
+//    identically, so for a finite A this ratio is FP32 rounding; it rejects a
+//    non-finite output (a finiteness guard), not a wrong one;
+//  - size: ||s curl A|| <= DN_CORR_MAX ||Jf||.  The filtered current judges
+//    the network: a correction larger than the current it corrects is taken
+//    as the network's failure (a finite but wrong output).
+constexpr double DN_CORR_MAX = 1.0;
 __global__ __launch_bounds__(256) void k_decide(const double* part, int nparts, double thr, int* use_net,
                                                 double* rel, int64_t* fallbacks) {
   __shared__ double sh[4];
-  double num = 0.0, den = 0.0;
+  double num = 0.0, den = 0.0, cc = 0.0, jj = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    num += part[2 * i];
-    den += part[2 * i + 1];
+    num += part[4 * i];
+    den += part[4 * i + 1];
+    cc += part[4 * i + 2];
+    jj += part[4 * i + 3];
   }
   num = block_sum_d(num, sh);
   __syncthreads();
   den = block_sum_d(den, sh);
+  __syncthreads();
+  cc = block_sum_d(cc, sh);
+  __syncthreads();
+  jj = block_sum_d(jj, sh);
   if (threadIdx.x != 0) return;
   double q = den > 0.0 ? sqrt(num / den) : (num > 0.0 ? INFINITY : 0.0);
-  int ok = q <= thr;                         // false for NaN
+  double m = jj > 0.0 ? sqrt(cc / jj) : (cc > 0.0 ? INFINITY : 0.0);
+  int ok = q <= thr && m <= DN_CORR_MAX;     // false for NaN
   *use_net = ok;
   if (rel) *rel = q;
   if (!ok && fallbacks) *fallbacks += 1;
@@ -1183,7 +1207,7 @@ int gempic_dn_create(const float* theta, size_t n, void* stream, gempic_dn_t** o
     }
   }
   d->red = (double*)d->alloc(4 * 8);
-  d->part = (double*)d->alloc(2 * COMB_BLOCKS * 8);
+  d->part = (double*)d->alloc(4 * COMB_BLOCKS * 8);
   d->use_net = (int*)d->alloc(sizeof(int));
   d->rel = (double*)d->alloc(8);
   d->fallbacks = (int64_t*)d->alloc(8);

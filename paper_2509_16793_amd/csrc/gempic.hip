@@ -125,6 +125,14 @@ static int fail(gempic* g, int code, const std::string& msg) {
 
 static bool pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
 
+// a kernel launch that failed (bad configuration, too much LDS) leaves a
+// sticky error that hipGetLastError reports; map it to GEMPIC_EDEVICE
+static int launch_check(gempic* g, const char* phase) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(g, GEMPIC_EDEVICE, std::string(phase) + ": " + hipGetErrorString(e));
+  return GEMPIC_OK;
+}
+
 // tile_base / total and the chunk table heads of t from g->tile_count
 static void scan_tiles(gempic* g, ChunkTab& t) {
   const Geom& G = g->g;
@@ -444,9 +452,10 @@ struct Impl {
     a.crho = (T)(qw / G.V);
     // fixed-point scale: every single contribution is bounded by
     // max(|cx|, |cy|, |cz| + |crho|, |cjy|) and a node of the LDS tile receives
-    // at most one contribution per particle of the chunk.  FP32: a single
-    // contribution below 2^30 (converted through int32); FP64: the worst-case
-    // node sum below 2^61.
+    // at most one contribution per particle of the (at most two) tiles of the
+    // column that reach it.  FP32: a single contribution below 2^30 (converted
+    // through int32); FP64: the worst-case node sum of 2 FIX64_TILE_MAX
+    // particles below 2^61 (the push flags denser tiles).
     double cmax = std::max(std::max(std::fabs((double)a.cx), std::fabs((double)a.cy)),
                            std::max(std::fabs((double)a.cz) + std::fabs((double)a.crho),
                                     std::fabs((double)a.cjy)));
@@ -455,7 +464,7 @@ struct Impl {
     a.rb = (T)(g->wb > 0 ? g->wb / g->w : 1.0);
     a.dtau = (T)G.dtau;
     if (g->wb > 0) cmax *= std::max(1.0, g->wb / g->w);
-    double lim = sizeof(T) == 4 ? std::ldexp(1.0, 30) : std::ldexp(1.0, 61) / (double)GP_CHUNK;
+    double lim = sizeof(T) == 4 ? std::ldexp(1.0, 30) : std::ldexp(1.0, 61) / (2.0 * FIX64_TILE_MAX);
     double sc = cmax > 0 ? lim / (cmax * 1.01) : 1.0;
     int e2 = (int)std::floor(std::log2(sc));
     a.fscale = (T)std::ldexp(1.0, e2);
@@ -550,12 +559,15 @@ struct Impl {
     if (rc) return rc;
     for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
     if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
+    if ((rc = launch_check(g, "clearing the current"))) return rc;
     if ((rc = mark(g, 1))) return rc;
     launch_push(g);
+    if ((rc = launch_check(g, "push and deposit"))) return rc;
     if ((rc = mark(g, 2))) return rc;
     (void)hipMemcpyAsync(g->pushed, g->total, 8, hipMemcpyDeviceToDevice, g->s);
     rc = sort_and_inject(g, g->step + 1);
     if (rc) return rc;
+    if ((rc = launch_check(g, "sort and window"))) return rc;
     if ((rc = mark(g, 3))) return rc;
     if (g->dn) {
       if (sizeof(T) != 4) return fail(g, GEMPIC_EINVAL, "denoiser needs FP32");
@@ -569,6 +581,7 @@ struct Impl {
       if (rc) return fail(g, rc, std::string("denoiser: ") + dn_error(g->dn));
     }
     field_update(g, true, (T)G.dtau);
+    if ((rc = launch_check(g, "field update"))) return rc;
     if ((rc = mark(g, 4))) return rc;
     if (g->timing) g->tsteps += 1;
     g->step += 1;
@@ -612,6 +625,9 @@ struct Impl {
       for (int t = 0; t < G.NT; ++t) cnt[t] += bcnt[t];
     }
     if (tot > g->capacity) return fail(g, GEMPIC_EINVAL, "capacity too small for the initial load");
+    if (g->prec == 0 && *std::max_element(cnt.begin(), cnt.end()) > FIX64_TILE_MAX / 2)
+      return fail(g, GEMPIC_EINVAL, "a tile holds more particles than the FP64 deposit's fixed-point range "
+                                    "allows with room for compression (FIX64_TILE_MAX / 2)");
     HIPCHK(g, hipMemcpyAsync(g->tile_count, cnt.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
     HIPCHK(g, hipMemcpyAsync(g->tile_base, base.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
     if (tot > 0) {
@@ -700,6 +716,8 @@ struct Impl {
     int64_t nJ = (int64_t)G.NPJ * nxy;
     for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
     if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
+    int rc2 = launch_check(g, "initial state");
+    if (rc2) return rc2;
     HIPCHK(g, hipStreamSynchronize(g->s));
     return GEMPIC_OK;
   }
@@ -761,6 +779,8 @@ static int check_errors(gempic* g) {
   if (e & ERR_NUMERIC) return fail(g, GEMPIC_ENUMERIC, "non-finite particle momentum");
   if (e & ERR_CAPACITY) return fail(g, GEMPIC_ECAPACITY, "particle buffer capacity exceeded");
   if (e & ERR_TILE) return fail(g, GEMPIC_EDEVICE, "internal: particle outside its tile or chunk too long");
+  if (e & ERR_DENSE)
+    return fail(g, GEMPIC_ECAPACITY, "a tile holds more particles than the FP64 deposit's fixed-point range");
   return GEMPIC_OK;
 }
 
@@ -820,9 +840,10 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->NT = G->nTx * G->nTy * G->nTz;
   G->Nxh = G->Nx / 2;
   if ((int64_t)G->Nzp * G->Ny * G->Nx >= (1ll << 30)) { *why = "grid too large: cells must stay below 2^30"; return GEMPIC_EINVAL; }
-  // the transverse transforms hold whole rows of six components in LDS
-  if (G->Nx > (c->precision == GEMPIC_FP64 ? 512 : 1024) || G->Ny > 2048) {
-    *why = "transverse grid too large: Nx <= 512 (FP64) or 1024 (FP32), Ny <= 2048";
+  // the transverse transforms hold whole rows of six components in LDS; sizes
+  // up to 512 are the ones the parity tests cover
+  if (G->Nx > 512 || G->Ny > 512) {
+    *why = "transverse grid too large: Nx, Ny <= 512";
     return GEMPIC_EINVAL;
   }
   if (c->beam_np < 0) { *why = "beam_np must be >= 0"; return GEMPIC_EINVAL; }
@@ -926,6 +947,12 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   g->capacity = n0 + n0 / 4 + 4096 + cfg->beam_np;
   g->max_nm = (int64_t)std::ceil(G.dtau * g->ppcz / G.h) + 5;
   g->stage_per_tile = g->max_nm * G.Ty * G.Tx * g->ppcx * g->ppcy;
+  // particle indices, chunk starts and the sort's ranks are int32
+  if (g->capacity > (int64_t)INT32_MAX || (int64_t)G.NT + g->capacity / GP_CHUNK + 1 > (int64_t)INT32_MAX) {
+    delete g;
+    g_create_error = "particle capacity beyond 2^31 - 1 (int32 particle indices)";
+    return GEMPIC_EINVAL;
+  }
   g->max_chunks = (int)(G.NT + g->capacity / GP_CHUNK + 1);
 
   Dev& d = g->dev;
@@ -1139,6 +1166,8 @@ int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void*
     cnt[t] += 1;
     if (id) maxid = std::max<int64_t>(maxid, id[i]);
   }
+  if (g->prec == 0 && count > 0 && *std::max_element(cnt.begin(), cnt.end()) > FIX64_TILE_MAX)
+    return fail(g, GEMPIC_EINVAL, "a tile holds more particles than the FP64 deposit's fixed-point range");
   int b = g->cur;
   if (G.abs_pos) {
     // the cells must be those the absolute positions decode to

@@ -10,8 +10,8 @@
 // interleaved); zeta nodes >= Nz carry zero.
 // Push: Higuera-Cary with eps = (q/m) dtau / 2.  Move: offsets advance by
 // v dtau / h_axis, zeta by (v_z - 1) dtau / h with the cancellation-free
-// v_z - 1; a cell step beyond one raises ERR_CFL and the particle is left
-// unchanged.  Gather, push and move follow a fixed operation order without
+// v_z - 1; a cell step beyond one raises ERR_CFL, a non-finite momentum
+// ERR_NUMERIC, and the particle is left unchanged.  Gather, push and move follow a fixed operation order without
 // contraction beyond the fused multiply-adds written out (FP32 only), so FP64
 // and FP32 results reproduce a reference bit for bit.
 // Deposit: Esirkepov frame current W on the staggered grid plus the time- and
@@ -23,8 +23,9 @@
 // exact and independent of the order of the atomics.  The scale is a power of
 // two chosen on the host: in FP32 a single contribution (bounded by the
 // largest coefficient) truncates to an int32 at 2^-30 of that bound; in FP64 a
-// chunk's worst-case node sum (chunk size x largest contribution) stays below
-// 2^61.  Neither can overflow the 64-bit sums.
+// node's worst-case sum (2 FIX64_TILE_MAX particles, each the largest
+// contribution) stays below 2^61, and a tile beyond FIX64_TILE_MAX particles
+// raises ERR_DENSE.  Neither can overflow the 64-bit sums.
 // A wave in which no particle crosses a transverse cell boundary takes a
 // reduced stencil (2 x 2 transverse nodes, 28 instead of 72 contributions);
 // the omitted terms are exactly zero.
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
 
   for (int tz = tz0; tz < tz1; ++tz) {
   const int z0 = tz * TZ;
+  if (sizeof(T) == 8 && threadIdx.x == 0 && p1 - p0 > FIX64_TILE_MAX) atomicOr(a.err, ERR_DENSE);
   int np0 = 0, np1 = 0;
   if (tz + 1 < tz1) range(tz + 1, &np0, &np1);
   // field node records: all planes for the first tile, planes 1 .. TZ after
@@ -400,10 +402,14 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           if (dz1 >= (T)1) { dz1 = (T)0; kz += 1; }
         }
     }
-    if (valid && !(ux == ux && uy == uy && uz == uz)) atomicOr(a.err, ERR_NUMERIC);
-    const bool cfl_bad = kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 0;
+    // a non-finite momentum (ERR_NUMERIC) or a step beyond one cell (ERR_CFL)
+    // leaves the particle unchanged; the cell steps of a non-finite move are
+    // never read
+    const bool nanu = !(ux == ux && uy == uy && uz == uz);
+    if (valid && nanu) atomicOr(a.err, ERR_NUMERIC);
+    const bool cfl_bad = !nanu && (kx < -1 || kx > 1 || ky < -1 || ky > 1 || kz < -1 || kz > 0);
     if (valid && cfl_bad) atomicOr(a.err, ERR_CFL);
-    valid = valid && !cfl_bad;
+    valid = valid && !cfl_bad && !nanu;
     if (!valid) kx = ky = kz = 0;
     if (valid) {
       int nix = (ix + kx) & mx;

@@ -83,16 +83,28 @@ def test_rejects_non_power_of_two_and_bad_tile():
 
 
 def test_rejects_transverse_grid_beyond_lds_transforms():
-    # FP64 rows of 1024 nodes (and FP32 rows of 2048) exceed what the
-    # transverse transforms hold in LDS; FP32 rows of 1024 are accepted
+    # rows longer than 512 nodes are beyond the sizes the transverse
+    # transforms are tested at; both precisions and both axes are rejected
     cfg = workloads.lwfa2d_fp64()
     cfg["n"] = [1024, 1, 256]
     rc, _ = _create(cfg)
     assert rc == -1
     assert b"transverse grid too large" in gp.lib().gempic_last_error(None)
     cfg["precision"] = "fp32"
-    cfg["n"] = [2048, 1, 256]
     assert _create(cfg)[0] == -1
+    cfg3 = workloads.small3d(precision="fp32", n=(16, 1024, 16))
+    assert _create(cfg3)[0] == -1
+
+
+def test_rejects_capacity_beyond_int32_indices():
+    # the PWFA grid at 8 ppc needs about 2.7e9 particle slots: rejected before
+    # any device allocation (particle indices are int32)
+    cfg = workloads.pwfa3d_fp32()
+    cfg["ppc"] = [2, 2, 2]
+    cfg["beam"] = None
+    rc, h = _create(cfg)
+    assert rc == -1 and not h.value
+    assert b"2^31" in gp.lib().gempic_last_error(None)
 
 
 def test_strerror():

@@ -49,14 +49,17 @@ def _dev(a):
 
 @pytest.mark.parametrize("shape", [(10, 16, 32), (4, 8, 16), (1, 8, 16)])
 def test_forward_matches_oracle(shape):
-    theta = workloads.denoiser_init(seed=11, last_scale=1.0, bias_scale=0.05)
+    # last layer scaled so that the correction stays below the filtered
+    # current (the size criterion of the fallback test keeps it)
+    theta = workloads.denoiser_init(seed=11, last_scale=0.3, bias_scale=0.05)
     J = _current(shape, 1)
     d = Denoiser(theta)
     A = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
     Jout, used, rel = d.apply(_dev(J), N_E, H, passes=1, threshold=1e9, aout=A)
-    assert used and rel < 1e-5
     th = theta.astype(np.float64)
     Jq, Aq, Jf, _ = dn.apply(th, J.astype(np.float64), N_E, *H, passes=1, quant=True)
+    assert dn.keep_network(Jq, Jf, *H, 1e9)
+    assert used and rel < 1e-5
     assert _rel(A.cpu().numpy(), Aq) < 1e-3
     assert _rel(Jout.cpu().numpy(), Jq) < 1e-3
     A64 = dn.forward(th, J.astype(np.float64) / N_E)[0]
@@ -208,3 +211,74 @@ def test_attached_network_matches_oracle_step():
     assert dg["fallbacks"] == 0 and dg["denoise_rel"] < 1e-4
     err = rel_errors(oracle_fields(o), g.fields())
     assert max(err.values()) < 5e-4, err
+
+
+def test_finite_bad_network_falls_back_at_production_threshold():
+    """A network with weights 100 times too large gives a finite correction
+    far larger than the current it corrects; the continuity ratio alone
+    (roundoff for any finite output) would keep it.  The size criterion
+    rejects it at the production threshold 1e-3, as the oracle's
+    keep_network decides, and the step then uses the filtered current."""
+    theta = workloads.denoiser_init(seed=11, last_scale=1.0, bias_scale=0.05) * 100.0
+    J = _current((10, 16, 32), 1)
+    d = Denoiser(theta)
+    Jout, used, rel = d.apply(_dev(J), N_E, H, passes=1, threshold=1e-3)
+    th = theta.astype(np.float64)
+    Jq, _, Jf, _ = dn.apply(th, J.astype(np.float64), N_E, *H, passes=1, quant=True)
+    assert dn.continuity_rel(Jq, Jf, *H) < 1e-3       # continuity alone would keep it
+    assert not dn.keep_network(Jq, Jf, *H, 1e-3)
+    assert not used
+    assert _rel(Jout.cpu().numpy(), dn.binomial(J.astype(np.float64), 1)) < 1e-6
+    # attached to a simulation: every step falls back and equals the plain path
+    cfg = _small()
+    plain = Sim(cfg)
+    plain.step(3)
+    g = Sim(cfg)
+    g.set_denoiser(d, 1e-3)
+    dg = g.step(3, diag=True)
+    assert dg["fallbacks"] == 3
+    err = rel_errors(plain.fields(), g.fields())
+    assert max(err.values()) < 1e-5, err
+
+
+def test_trained_network_beats_the_filter_on_held_out_runs():
+    """The committed weights (trained on seeds 0-63 of the 64 x 64 x 512
+    periodic LWFA box) against the filter alone on a held-out seed: paired
+    1-ppc and 16-ppc runs of seed 64 after 200 steps, four 64-plane crops
+    (plus the 5-plane halo the network and curl need), loss = mean of
+    ((J - F(J_16)) / n_e)^2 over the crop's central planes.  Training reached
+    a 31 % lower loss than the filter (7.96e-4 against 1.15e-3); the bar asks
+    for at least 15 % on data the network has not seen."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    theta = np.load(os.path.join(root, "paper_2509_16793_amd", "weights", "denoiser_lwfa.npy"))
+    lo = Sim(workloads.denoiser_train(ppc=(1, 1, 1), seed=64))
+    hi = Sim(workloads.denoiser_train(ppc=(2, 2, 4), seed=64))
+    lo.step(200)
+    hi.step(200)
+    shape = (3, lo.NPJ, lo.Ny, lo.Nx)
+    jl = torch.empty(shape, dtype=torch.float32, device="cuda")
+    jh = torch.empty(shape, dtype=torch.float32, device="cuda")
+    lo.fields_device(("Jx", "Jy", "Jz"), jl)
+    hi.fields_device(("Jx", "Jy", "Jz"), jh)
+    cfg = workloads.denoiser_train(seed=64)
+    n_e = cfg["n_e"]
+    h = tuple(float(v) * cfg["length_unit"] for v in cfg["d"])
+    d = Denoiser(theta)
+    rng = np.random.default_rng(64)
+    halo, crop = 5, 64
+    net_l, plain_l = 0.0, 0.0
+    for _ in range(4):
+        z0 = int(rng.integers(0, lo.NPJ - crop - 2 * halo + 1))
+        cl = jl[:, z0:z0 + crop + 2 * halo].contiguous()
+        ch = jh[:, z0:z0 + crop + 2 * halo].contiguous()
+        jnet, used, _ = d.apply(cl, n_e, h, passes=1, threshold=1e-3)
+        assert used
+        jfl, _, _ = d.apply(cl, n_e, h, passes=1, threshold=-1.0)
+        jfh, _, _ = d.apply(ch, n_e, h, passes=1, threshold=-1.0)
+        t = jfh.cpu().numpy()[:, halo:halo + crop].astype(np.float64)
+        a = jnet.cpu().numpy()[:, halo:halo + crop].astype(np.float64)
+        b = jfl.cpu().numpy()[:, halo:halo + crop].astype(np.float64)
+        net_l += np.mean(((a - t) / n_e) ** 2)
+        plain_l += np.mean(((b - t) / n_e) ** 2)
+    assert net_l < 0.85 * plain_l, (net_l / 4, plain_l / 4)
