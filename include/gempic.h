@@ -62,8 +62,7 @@ typedef enum {
   GEMPIC_ENUMERIC = -5,   /* NaN or Inf in the state                               */
   GEMPIC_ESTATE = -6,     /* call not allowed in the handle's state                */
   GEMPIC_EABI = -7,       /* abi_version mismatch                                  */
-  GEMPIC_ECAPACITY = -8   /* particle buffer capacity exceeded, or (FP64) a tile
-                             denser than the deposit's fixed-point range          */
+  GEMPIC_ECAPACITY = -8   /* particle buffer capacity exceeded                     */
 } gempic_status;
 
 typedef enum {

@@ -81,11 +81,5 @@ GP_DEV int abs_cell(float x, float ih, float* off) {
 #define ERR_TILE 2
 #define ERR_CAPACITY 4
 #define ERR_NUMERIC 8
-#define ERR_DENSE 16       // FP64: a tile holds more particles than FIX64_TILE_MAX
-
-// FP64 deposit: the LDS fixed-point scale is chosen so that a node's sum stays
-// below 2^61 when each of the (at most two) tiles of a column that reach the
-// node holds at most this many particles; the push raises ERR_DENSE beyond it
-#define FIX64_TILE_MAX (1 << 15)
 
 #define GP_CHUNK 1024      // max particles per work-group chunk

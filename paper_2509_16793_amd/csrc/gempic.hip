@@ -450,12 +450,10 @@ struct Impl {
       a.cjy = (T)(qw / (G.hx * G.h));
     }
     a.crho = (T)(qw / G.V);
-    // fixed-point scale: every single contribution is bounded by
-    // max(|cx|, |cy|, |cz| + |crho|, |cjy|) and a node of the LDS tile receives
-    // at most one contribution per particle of the (at most two) tiles of the
-    // column that reach it.  FP32: a single contribution below 2^30 (converted
-    // through int32); FP64: the worst-case node sum of 2 FIX64_TILE_MAX
-    // particles below 2^61 (the push flags denser tiles).
+    // FP32 fixed-point scale: every single contribution is bounded by
+    // max(|cx|, |cy|, |cz| + |crho|, |cjy|) and is converted through int32
+    // below 2^30; a node receives at most one contribution per particle, so
+    // the 64-bit sums hold 2^33 particles.  FP64 accumulates in FP64 (scale 1).
     double cmax = std::max(std::max(std::fabs((double)a.cx), std::fabs((double)a.cy)),
                            std::max(std::fabs((double)a.cz) + std::fabs((double)a.crho),
                                     std::fabs((double)a.cjy)));
@@ -464,9 +462,8 @@ struct Impl {
     a.rb = (T)(g->wb > 0 ? g->wb / g->w : 1.0);
     a.dtau = (T)G.dtau;
     if (g->wb > 0) cmax *= std::max(1.0, g->wb / g->w);
-    double lim = sizeof(T) == 4 ? std::ldexp(1.0, 30) : std::ldexp(1.0, 61) / (2.0 * FIX64_TILE_MAX);
-    double sc = cmax > 0 ? lim / (cmax * 1.01) : 1.0;
-    int e2 = (int)std::floor(std::log2(sc));
+    double sc = cmax > 0 ? std::ldexp(1.0, 30) / (cmax * 1.01) : 1.0;
+    int e2 = sizeof(T) == 4 ? (int)std::floor(std::log2(sc)) : 0;
     a.fscale = (T)std::ldexp(1.0, e2);
     a.finv = (T)std::ldexp(1.0, -e2);
     a.tile_base = g->tile_base;
@@ -625,9 +622,6 @@ struct Impl {
       for (int t = 0; t < G.NT; ++t) cnt[t] += bcnt[t];
     }
     if (tot > g->capacity) return fail(g, GEMPIC_EINVAL, "capacity too small for the initial load");
-    if (g->prec == 0 && *std::max_element(cnt.begin(), cnt.end()) > FIX64_TILE_MAX / 2)
-      return fail(g, GEMPIC_EINVAL, "a tile holds more particles than the FP64 deposit's fixed-point range "
-                                    "allows with room for compression (FIX64_TILE_MAX / 2)");
     HIPCHK(g, hipMemcpyAsync(g->tile_count, cnt.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
     HIPCHK(g, hipMemcpyAsync(g->tile_base, base.data(), G.NT * 8, hipMemcpyHostToDevice, g->s));
     if (tot > 0) {
@@ -779,8 +773,6 @@ static int check_errors(gempic* g) {
   if (e & ERR_NUMERIC) return fail(g, GEMPIC_ENUMERIC, "non-finite particle momentum");
   if (e & ERR_CAPACITY) return fail(g, GEMPIC_ECAPACITY, "particle buffer capacity exceeded");
   if (e & ERR_TILE) return fail(g, GEMPIC_EDEVICE, "internal: particle outside its tile or chunk too long");
-  if (e & ERR_DENSE)
-    return fail(g, GEMPIC_ECAPACITY, "a tile holds more particles than the FP64 deposit's fixed-point range");
   return GEMPIC_OK;
 }
 
@@ -1166,8 +1158,6 @@ int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void*
     cnt[t] += 1;
     if (id) maxid = std::max<int64_t>(maxid, id[i]);
   }
-  if (g->prec == 0 && count > 0 && *std::max_element(cnt.begin(), cnt.end()) > FIX64_TILE_MAX)
-    return fail(g, GEMPIC_EINVAL, "a tile holds more particles than the FP64 deposit's fixed-point range");
   int b = g->cur;
   if (G.abs_pos) {
     // the cells must be those the absolute positions decode to

@@ -21,11 +21,11 @@
 // tile holds 64-bit fixed-point integers: integer LDS atomics run tens of
 // times faster than floating-point ones on gfx950, and the tile sums become
 // exact and independent of the order of the atomics.  The scale is a power of
-// two chosen on the host: in FP32 a single contribution (bounded by the
-// largest coefficient) truncates to an int32 at 2^-30 of that bound; in FP64 a
-// node's worst-case sum (2 FIX64_TILE_MAX particles, each the largest
-// contribution) stays below 2^61, and a tile beyond FIX64_TILE_MAX particles
-// raises ERR_DENSE.  Neither can overflow the 64-bit sums.
+// two chosen on the host: a single contribution (bounded by the largest
+// coefficient) truncates to an int32 at 2^-30 of that bound, so the 64-bit
+// sums cannot overflow below 2^33 particles.  The FP64 mode (parity, not
+// throughput) accumulates in FP64 LDS atomics instead, at full precision and
+// without a range limit.
 // A wave in which no particle crosses a transverse cell boundary takes a
 // reduced stencil (2 x 2 transverse nodes, 28 instead of 72 contributions);
 // the omitted terms are exactly zero.
@@ -64,26 +64,27 @@ template <typename T> GP_DEV T madd(T a, T b, T c);
 template <> GP_DEV float madd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <> GP_DEV double madd<double>(double a, double b, double c) { return a * b + c; }
 
-// fixed-point accumulator of the LDS deposit tile
+// accumulator of the LDS deposit tile
 template <typename T> struct Fix;
 template <> struct Fix<float> {
-  // a single contribution fits in int32 at the FP32 scale; sums in 64 bits
+  // fixed point: a single contribution fits in int32 at the FP32 scale, the
+  // sums in 64-bit two's complement (no overflow below 2^33 contributions)
   using t = unsigned long long;
   // truncation: the bias is below 2^-30 of the largest single contribution
   static GP_DEV unsigned long long to(float v) { return (unsigned long long)(long long)(int)v; }
+  // sum -> value, within two ulp
+  static GP_DEV float value(unsigned long long v) {
+    float hi = (float)(int)(unsigned)(v >> 32);
+    float lo = (float)(unsigned)(v & 0xFFFFFFFFull);
+    return hi * 4294967296.0f + lo;
+  }
 };
 template <> struct Fix<double> {
-  // two's complement sums in unsigned 64-bit atomics
-  using t = unsigned long long;
-  static GP_DEV unsigned long long to(double v) { return (unsigned long long)__double2ll_rn(v); }
+  // FP64 (the parity mode): native FP64 LDS atomics, no range limit
+  using t = double;
+  static GP_DEV double to(double v) { return v; }
+  static GP_DEV double value(double v) { return v; }
 };
-// fixed-point sum -> value: exact rounding in FP64, within two ulp in FP32
-template <typename T>
-GP_DEV T fix_value(unsigned long long v) {
-  T hi = (T)(int)(unsigned)(v >> 32);
-  T lo = (T)(unsigned)(v & 0xFFFFFFFFull);
-  return hi * (T)4294967296.0 + lo;
-}
 
 // 3-node window starting at min(c0, c0 + k): old and new linear weights.
 template <typename T>
@@ -222,7 +223,6 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
 
   for (int tz = tz0; tz < tz1; ++tz) {
   const int z0 = tz * TZ;
-  if (sizeof(T) == 8 && threadIdx.x == 0 && p1 - p0 > FIX64_TILE_MAX) atomicOr(a.err, ERR_DENSE);
   int np0 = 0, np1 = 0;
   if (tz + 1 < tz1) range(tz + 1, &np0, &np1);
   // field node records: all planes for the first tile, planes 1 .. TZ after
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
           const int plane = z0 + jz;
           if (iv != (A)0 && plane < g.NPJ) {
             char* base = reinterpret_cast<char*>(dq + (int64_t)plane * plane_stride);
-            atomicAdd(reinterpret_cast<T*>(base + boff), fix_value<T>(iv) * a.finv);
+            atomicAdd(reinterpret_cast<T*>(base + boff), Fix<T>::value(iv) * a.finv);
           }
         };
         // a slab's planes below TZ + first are final: the next tile's deposits
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
         for (int rz = 0; rz < rflush; ++rz) {
           A iv = sc[rz * RY * RX];
           int plane = z0 + 1 + rz;
-          if (iv != (A)0 && plane < g.NPJ) atomicAdd(dst + plane * plane_stride, fix_value<T>(iv) * a.finv);
+          if (iv != (A)0 && plane < g.NPJ) atomicAdd(dst + plane * plane_stride, Fix<T>::value(iv) * a.finv);
         }
         if (!last) {
           for (int rz = TZ; rz < RZ; ++rz) {
