@@ -77,6 +77,21 @@ int gempic_dn_grad(gempic_dn_t* d, float* grad, size_t n);
 int gempic_dn_apply(gempic_dn_t* d, const int32_t box[3], const float* jraw, double n_e, const double h[3],
                     int32_t passes, double threshold, float* jout, float* aout, int32_t* used, double* rel);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as gempic_dn_apply, with every per-box buffer (activations, A,
+ * the filtered current, the filter's second pass, the test's partial sums)
+ * taken from a static device array of 43,057,664 bytes that each GPU the
+ * library runs on holds until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine.  Boxes beyond 2^18 voxels
+ * (Z * Y * X > 262144) give GEMPIC_EINVAL.  Every call on a GPU shares that
+ * GPU's array and the handle's stream: calls that overlap on one GPU (from
+ * several threads or streams) race.  Same arguments, results and
+ * synchronisation as gempic_dn_apply. */
+int gempic_dn_apply_noalloc(gempic_dn_t* d, const int32_t box[3], const float* jraw, double n_e,
+                            const double h[3], int32_t passes, double threshold, float* jout, float* aout,
+                            int32_t* used, double* rel);
+
 /* One training step over nbatch boxes: jraw and jtarget are device arrays
  * [nbatch][3][Z][Y][X] holding the raw deposits of a low- and a high-ppc run;
  * the loss is mean over the batch and over planes region[0] <= z < region[1]

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1084,6 +1085,35 @@ static CurlArgs curl_args(int Z, int Y, int X, double n_e, const double hs[3]) {
   return c;
 }
 
+// device workspace of one denoised box: activations, network output A
+// ([3][nv] planar), the continuity test's partial sums and its decision
+struct DnWork {
+  unsigned short* act[3];
+  float* A;
+  double* part;      // 4 * COMB_BLOCKS
+  int* use_net;
+  double* rel;
+};
+
+static int dn_step_ws(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const J[3],
+                      float* const Jf[3], float* const Jd[3], float* const tmp[3], double n_e, const double hs[3],
+                      int passes, double thr, int64_t* fallbacks, double* rel, const DnWork& w) {
+  int64_t nv = (int64_t)Z * Y * X;
+  if (!d->packed) repack(d, s);
+  filter(s, Z, Y, X, J, Jf, tmp, passes);
+  float* Ap[3] = {w.A, w.A + nv, w.A + 2 * nv};
+  net_forward(d, s, Z, Y, X, J, (float)(1.0 / n_e), w.act, Ap);
+  CurlArgs c = curl_args(Z, Y, X, n_e, hs);
+  k_combine<<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                        W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
+  k_decide<<<1, 256, 0, s>>>(w.part, COMB_BLOCKS, thr, w.use_net, rel ? rel : w.rel,
+                             fallbacks ? fallbacks : d->fallbacks);
+  k_select<<<SEL_BLOCKS, 256, 0, s>>>(c.B, w.use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("denoiser launch: ") + hipGetErrorString(e));
+  return GEMPIC_OK;
+}
+
 int dn_step(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const J[3], float* const Jf[3],
             float* const Jd[3], float* const tmp[3], double n_e, const double hs[3], int passes, double thr,
             int64_t* fallbacks, double* rel) {
@@ -1092,19 +1122,8 @@ int dn_step(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const float* const
   if (rc) return rc;
   if (!(n_e > 0)) return dn_fail(d, GEMPIC_EINVAL, "denoiser needs n_e > 0");
   if ((rc = dn_reserve(d, nv))) return rc;
-  if (!d->packed) repack(d, s);
-  filter(s, Z, Y, X, J, Jf, tmp, passes);
-  float* Ap[3] = {d->A, d->A + nv, d->A + 2 * nv};
-  net_forward(d, s, Z, Y, X, J, (float)(1.0 / n_e), d->act, Ap);
-  CurlArgs c = curl_args(Z, Y, X, n_e, hs);
-  k_combine<<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
-                                        W3{{Jd[0], Jd[1], Jd[2]}}, d->part);
-  k_decide<<<1, 256, 0, s>>>(d->part, COMB_BLOCKS, thr, d->use_net, rel ? rel : d->rel,
-                             fallbacks ? fallbacks : d->fallbacks);
-  k_select<<<SEL_BLOCKS, 256, 0, s>>>(c.B, d->use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("denoiser launch: ") + hipGetErrorString(e));
-  return GEMPIC_OK;
+  DnWork w{{d->act[0], d->act[1], d->act[2]}, d->A, d->part, d->use_net, d->rel};
+  return dn_step_ws(d, s, Z, Y, X, J, Jf, Jd, tmp, n_e, hs, passes, thr, fallbacks, rel, w);
 }
 
 const char* dn_error(const gempic_dn* d) { return d ? d->err.c_str() : ""; }
@@ -1270,6 +1289,98 @@ int gempic_dn_apply(gempic_dn_t* d, const int32_t box[3], const float* jraw, dou
   double rv = 0.0;
   DNCHK(d, hipMemcpyAsync(&un, d->use_net, sizeof(int), hipMemcpyDeviceToHost, d->s));
   DNCHK(d, hipMemcpyAsync(&rv, d->rel, 8, hipMemcpyDeviceToHost, d->s));
+  DNCHK(d, hipStreamSynchronize(d->s));
+  if (used) *used = un;
+  if (rel) *rel = rv;
+  return GEMPIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of gempic_dn_apply.  Every per-box buffer lives in
+// one file-scope device array: bf16 activations (16, 32, 16 channels), A,
+// the filtered current, the second filter pass and the continuity test's
+// partial sums and decision, each at a fixed offset sized for
+// DN_NOALLOC_MAX_VOXELS voxels.  Each device holds its own copy; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (kept in g_scratch_ptr).  Every buffer is fully written
+// before it is read, so nothing needs clearing between calls.
+}  // extern "C"
+
+constexpr int64_t DN_NOALLOC_MAX_VOXELS = int64_t(1) << 18;
+constexpr size_t dn_round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t SCR_ACT0 = 0;
+constexpr size_t SCR_ACT1 = SCR_ACT0 + dn_round256((size_t)DN_NOALLOC_MAX_VOXELS * 16 * 2);
+constexpr size_t SCR_ACT2 = SCR_ACT1 + dn_round256((size_t)DN_NOALLOC_MAX_VOXELS * 32 * 2);
+constexpr size_t SCR_A = SCR_ACT2 + dn_round256((size_t)DN_NOALLOC_MAX_VOXELS * 16 * 2);
+constexpr size_t SCR_JF = SCR_A + dn_round256((size_t)DN_NOALLOC_MAX_VOXELS * 3 * 4);
+constexpr size_t SCR_TMP = SCR_JF + dn_round256((size_t)DN_NOALLOC_MAX_VOXELS * 3 * 4);
+constexpr size_t SCR_PART = SCR_TMP + dn_round256((size_t)DN_NOALLOC_MAX_VOXELS * 3 * 4);
+constexpr size_t SCR_USE = SCR_PART + dn_round256((size_t)4 * COMB_BLOCKS * 8);
+constexpr size_t SCR_REL = SCR_USE + 256;
+constexpr size_t DN_SCRATCH_BYTES = SCR_REL + 256;   // 43,057,664 bytes (41.1 MiB)
+
+static __device__ __align__(256) unsigned char scratch[DN_SCRATCH_BYTES];
+
+constexpr int DN_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[DN_MAX_DEVICES];
+
+// device address of the current device's scratch array (looked up once per
+// device, with that device current)
+static int scratch_address(gempic_dn* d, unsigned char** out) {
+  int dev = 0;
+  DNCHK(d, hipGetDevice(&dev));
+  if (dev < 0 || dev >= DN_MAX_DEVICES) return dn_fail(d, GEMPIC_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return dn_fail(d, GEMPIC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return GEMPIC_OK;
+}
+
+extern "C" {
+
+int gempic_dn_apply_noalloc(gempic_dn_t* d, const int32_t box[3], const float* jraw, double n_e,
+                            const double h[3], int32_t passes, double threshold, float* jout, float* aout,
+                            int32_t* used, double* rel) {
+  if (!d || !box || !jraw || !h || !jout) return dn_fail(d, GEMPIC_EINVAL, "null argument");
+  if (passes < 0 || passes > 2) return dn_fail(d, GEMPIC_EINVAL, "passes must be 0, 1 or 2");
+  if (!(n_e > 0)) return dn_fail(d, GEMPIC_EINVAL, "denoiser needs n_e > 0");
+  int Z = box[0], Y = box[1], X = box[2];
+  int rc = check_box(d, Z, Y, X);
+  if (rc) return rc;
+  int64_t nv = (int64_t)Z * Y * X;
+  if (nv > DN_NOALLOC_MAX_VOXELS)
+    return dn_fail(d, GEMPIC_EINVAL, "box larger than the allocation-free limit of 2^18 voxels");
+  unsigned char* base = nullptr;
+  if ((rc = scratch_address(d, &base))) return rc;
+  DnWork w;
+  w.act[0] = (unsigned short*)(base + SCR_ACT0);
+  w.act[1] = (unsigned short*)(base + SCR_ACT1);
+  w.act[2] = (unsigned short*)(base + SCR_ACT2);
+  w.A = (float*)(base + SCR_A);
+  w.part = (double*)(base + SCR_PART);
+  w.use_net = (int*)(base + SCR_USE);
+  w.rel = (double*)(base + SCR_REL);
+  float* jf = (float*)(base + SCR_JF);
+  float* tp = (float*)(base + SCR_TMP);
+  const float* J[3] = {jraw, jraw + nv, jraw + 2 * nv};
+  float* Jf[3] = {jf, jf + nv, jf + 2 * nv};
+  float* tmp[3] = {tp, tp + nv, tp + 2 * nv};
+  float* Jd[3] = {jout, jout + nv, jout + 2 * nv};
+  // fallbacks are counted in the handle's counter, as gempic_dn_apply does
+  rc = dn_step_ws(d, d->s, Z, Y, X, J, Jf, Jd, tmp, n_e, h, passes, threshold, nullptr, nullptr, w);
+  if (rc) return rc;
+  if (aout) DNCHK(d, hipMemcpyAsync(aout, w.A, nv * 3 * 4, hipMemcpyDeviceToDevice, d->s));
+  int un = 0;
+  double rv = 0.0;
+  DNCHK(d, hipMemcpyAsync(&un, w.use_net, sizeof(int), hipMemcpyDeviceToHost, d->s));
+  DNCHK(d, hipMemcpyAsync(&rv, w.rel, 8, hipMemcpyDeviceToHost, d->s));
   DNCHK(d, hipStreamSynchronize(d->s));
   if (used) *used = un;
   if (rel) *rel = rv;

@@ -93,6 +93,10 @@ _SIGS = {
                                        ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "gempic_dn_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p,
+                                               ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                               ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "gempic_dn_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
@@ -385,6 +389,22 @@ class Denoiser:
                                         float(threshold), self._dptr(jout),
                                         None if aout is None else self._dptr(aout),
                                         ctypes.byref(used), ctypes.byref(rel)), self.h)
+        return jout, bool(used.value), rel.value
+
+    def apply_noalloc(self, jraw, n_e, h, passes=1, threshold=1e-3, jout=None, aout=None):
+        """As apply, through the allocation-free entry point (boxes of at most
+        2^18 voxels); jout must be given by callers that cannot allocate."""
+        import torch
+        box = (ctypes.c_int32 * 3)(*jraw.shape[1:])
+        if jout is None:
+            jout = torch.empty_like(jraw)
+        used = ctypes.c_int32()
+        rel = ctypes.c_double()
+        hs = (ctypes.c_double * 3)(*h)
+        _dn_check(lib().gempic_dn_apply_noalloc(self.h, box, self._dptr(jraw), float(n_e), hs, int(passes),
+                                                float(threshold), self._dptr(jout),
+                                                None if aout is None else self._dptr(aout),
+                                                ctypes.byref(used), ctypes.byref(rel)), self.h)
         return jout, bool(used.value), rel.value
 
     def train(self, jraw, jtarget, n_e, h, region, lr, passes=1):
