@@ -14,7 +14,14 @@
  *     RxN .. eqall marched from the right boundary (Sec. 4.1) with the analytic
  *     node solution of App. B;
  *   - moving-window injection of the fresh plasma the domain sweeps over
- *     (Sec. 5.1; here every particle carries Q_b and is pushed in tau).
+ *     (Sec. 5.1; here every particle carries Q_b and is pushed in tau);
+ *   - or, with scheme = 1 (GT1) or 2 (GT2), the paper's own slow step: the
+ *     particles are integrated along zeta (Sec. 5, stop rules eq:trap1 and
+ *     eq:trap2), fresh plasma of weight Q_f = q n h_x h_y Delta enters at the
+ *     right edge every step and deposits j = (Q / (h_x h_y h)) v ds / Delta
+ *     (Sec. 5.1), interleaved with the right-to-left node march (Sec. 4.1),
+ *     so that Delta may exceed h by far; Delta may change between steps and
+ *     h may vary along zeta (Sec. 7).
  * Units are the paper's normalised ones (Sec. 3): c = 1, lengths in c/omega_0,
  * fields in m c omega_0 / e, densities in units of the critical density.
  *
@@ -45,7 +52,7 @@
 extern "C" {
 #endif
 
-#define GEMPIC_ABI_VERSION 2
+#define GEMPIC_ABI_VERSION 3
 
 /* Bit of a particle's cell word that marks a driver-beam electron (gempic_particles,
  * gempic_set_state); the cell index itself is the word without this bit. */
@@ -125,6 +132,29 @@ typedef struct {
   double  beam_gamma;       /* mean Lorentz factor (> 1)                                */
   double  beam_dgamma;      /* rms spread of gamma                                      */
   int64_t beam_np;          /* macro-particles                                          */
+  /* Slow-step scheme.  0: every particle pushed in tau with slow step dtau
+   * (the fields above).  1, 2: the zeta march (GT1, GT2; Sec. 5): per slow
+   * step `delta` the particles of each zeta cell, right to left, take
+   * midpoint sub-steps along zeta (or, limited by the remaining slow budget
+   * or by half a transverse cell, in lab time) until they reach the node
+   * below, exhaust the budget (they are then parked in the box for the next
+   * step; GT1 counts the budget in time, GT2 in lab z) or leave at zeta = 0;
+   * each cell's currents are complete before its node is solved.  Fields
+   * inside a cell are linear in zeta between the new level above and the old
+   * level below.  One batch of fresh particles (ppc[0] x ppc[1] per
+   * transverse cell, u = 0, offsets as in `load`) enters at the right edge
+   * per step; GT1 also loads, at creation, batches every delta below the
+   * edge.  Needs n[2] <= 65536, no driver beam, precision FP64 or FP32_CELL;
+   * dtau, ppc[2], deposit_rho and the zeta passes of the filter are unused
+   * (the transverse filter factor cos^2(k h / 2) per pass remains). */
+  int32_t scheme;
+  double  delta;            /* slow step Delta of the zeta march, config units          */
+  const double* zeta_nodes; /* nullable: n[2] + 1 increasing zeta node positions from 0
+                               (config units; copied at creation): a variable fast step
+                               h_n = zeta_{n+1} - zeta_n; NULL = uniform d[2]           */
+  double  ch_ratio;         /* Gaussian plasma channel (Sec. 6, eq. n_plasma): density on
+                               the axis over n_e; 0 or 1 = uniform (zeta march only)      */
+  double  ch_radius;        /* channel radius R_ch, config units                        */
   void*   stream;           /* hipStream_t or NULL                                      */
 } gempic_config;
 
@@ -235,6 +265,18 @@ int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes);
  * accumulated.  gempic_get_timing synchronises the stream. */
 int gempic_timing(gempic_t* g, int32_t enable);
 int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps);
+
+/* Zeta march (scheme 1, 2): slow step Delta (config units) of the following
+ * steps (Sec. 7: Delta may change from one step to the next; the new step's
+ * fresh particles carry the new Q_f).  Delta h_max <= 4 / n_e is required
+ * (Sec. 4.2).  GEMPIC_EINVAL for the tau scheme or an invalid Delta. */
+int gempic_set_slow_step(gempic_t* g, double delta);
+
+/* Zeta march: weights w (electrons per macro-particle) and remaining slow
+ * budgets b (normalised time, <= 0 for a particle whose budget ran out,
+ * the rest carried into the next step) of the particles, in the order of
+ * gempic_particles, in the handle's precision.  Host or device memory. */
+int gempic_march_particles(gempic_t* g, int32_t on_device, void* w, void* b, size_t capacity, size_t* count);
 
 void gempic_destroy(gempic_t* g);
 

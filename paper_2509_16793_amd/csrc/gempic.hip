@@ -15,6 +15,7 @@
 #include "dn_internal.h"
 #include "fields.h"
 #include "particles.h"
+#include "march.h"
 
 namespace {
 
@@ -98,6 +99,24 @@ struct gempic {
   void* Jt[3];
   int64_t* dn_fallbacks;
   double* dn_rel;
+  // zeta march (scheme 1 = GT1, 2 = GT2)
+  int scheme;
+  double Delta;                 // slow step of the next step (normalised)
+  std::vector<double> zn;       // node positions zeta_0 .. zeta_Nz (normalised)
+  int64_t nperp;                // fresh particles per batch
+  int64_t mz_batches;           // batches loaded at creation
+  int mz_cap;                   // capacity of each march particle buffer
+  int mz_first;                 // no previous-step current yet
+  int mz_stage_blocks;
+  int mz_subcap;                // sub-step bound per particle and stage
+  void* mz_part[4][10];         // park, stop, active 0, active 1: cell ox oy oz ux uy uz w b id
+  int* mz_cnt;                  // active[2], stop, left, parked total
+  int *mz_pstart, *mz_pcount, *mz_cursor;
+  void *mz_dep, *mz_jhat, *mz_out6, *mz_zj;
+  void* mz_j0[2];
+  void* F6b;                    // new-level node records
+  double* mz_hnode;             // node volumes / (h_x h_y): (h_{n-1} + h_n) / 2
+  double s_total;               // slow coordinate reached (sum of the steps' Delta)
   // timing: five events per step while enabled
   bool timing;
   std::vector<hipEvent_t> ev;
@@ -274,30 +293,34 @@ struct Impl {
       k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
     if (G.Ny > 1) fft_y(g, out, planes, 0);
   }
-  // six field spectra (outs) -> interleaved real node records F6
-  static void fft_inv6(gempic* g) {
+  // inverse x transforms of `rows` rows of six field spectra (in[q] + row
+  // Nxh) -> interleaved real node records
+  static void c2r6(gempic* g, const C* const in[6], T* dst, int64_t rows) {
     const Geom& G = g->g;
-    if (G.Ny > 1)
-      for (int q = 0; q < 6; ++q) fft_y(g, (C*)g->outs[q], G.Nz, 1);
-    int64_t rows = (int64_t)G.Nz * G.Ny;
     int64_t pairs = (rows + 1) / 2;
     int nseq = std::max(1, std::min<int>((int)std::min<int64_t>(pairs, 1 << 20), 2048 / (6 * G.Nx)));
     size_t sh = (2 * (size_t)6 * nseq + 1) * G.Nx * sizeof(C);
     if (G.Nx == 256) {
       k_fft_x_c2r6_256<T><<<(unsigned)((pairs + C2R256_P - 1) / C2R256_P), 192, 0, g->s>>>(
-          (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
-          (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, (const C*)g->twx);
+          in[0], in[1], in[2], in[3], in[4], in[5], dst, rows, (const C*)g->twx);
       return;
     }
     if (G.Nx == 512) {
-      k_fft_x_c2r6_512<T><<<(unsigned)pairs, 192, 0, g->s>>>(
-          (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
-          (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, (const C*)g->twx);
+      k_fft_x_c2r6_512<T><<<(unsigned)pairs, 192, 0, g->s>>>(in[0], in[1], in[2], in[3], in[4], in[5], dst,
+                                                                rows, (const C*)g->twx);
       return;
     }
-    k_fft_x_c2r6<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(
-        (const C*)g->outs[0], (const C*)g->outs[1], (const C*)g->outs[2], (const C*)g->outs[3],
-        (const C*)g->outs[4], (const C*)g->outs[5], (T*)g->F6, rows, G.Nx, nseq, (const C*)g->twx);
+    k_fft_x_c2r6<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in[0], in[1], in[2], in[3], in[4], in[5], dst, rows,
+                                                            G.Nx, nseq, (const C*)g->twx);
+  }
+  // six field spectra (outs) -> interleaved real node records F6
+  static void fft_inv6(gempic* g) {
+    const Geom& G = g->g;
+    if (G.Ny > 1)
+      for (int q = 0; q < 6; ++q) fft_y(g, (C*)g->outs[q], G.Nz, 1);
+    const C* in[6];
+    for (int q = 0; q < 6; ++q) in[q] = (const C*)g->outs[q];
+    c2r6(g, in, (T*)g->F6, (int64_t)G.Nz * G.Ny);
   }
 
   // ---- field update: FFT(J) -> march -> iFFT ------------------------------
@@ -716,6 +739,253 @@ struct Impl {
     return GEMPIC_OK;
   }
 
+  // ---- zeta march ----------------------------------------------------------
+  static MzParts<T> mzp(gempic* g, int k) {
+    MzParts<T> P;
+    P.cell = (int32_t*)g->mz_part[k][0];
+    P.ox = (T*)g->mz_part[k][1];
+    P.oy = (T*)g->mz_part[k][2];
+    P.oz = (T*)g->mz_part[k][3];
+    P.ux = (T*)g->mz_part[k][4];
+    P.uy = (T*)g->mz_part[k][5];
+    P.uz = (T*)g->mz_part[k][6];
+    P.w = (T*)g->mz_part[k][7];
+    P.b = (T*)g->mz_part[k][8];
+    P.id = (int64_t*)g->mz_part[k][9];
+    return P;
+  }
+  enum { MZ_PARK = 0, MZ_STOP = 1, MZ_ACT = 2 };
+  enum { C_ACT = 0, C_STOP = 2, C_LEFT = 3, C_PARK = 4 };
+
+  // stopped particles -> parked store sorted by zeta cell
+  static void mz_sort(gempic* g) {
+    const Geom& G = g->g;
+    const int nxy = G.Nx * G.Ny;
+    k_fill<int32_t><<<nblk(G.Nz, 256), 256, 0, g->s>>>(g->mz_pcount, G.Nz, 0);
+    k_mz_count<<<256, 256, 0, g->s>>>((const int32_t*)g->mz_part[MZ_STOP][0], g->mz_cnt + C_STOP, g->mz_cap,
+                                       nxy, g->mz_pcount);
+    k_mz_scan<<<1, 1024, 0, g->s>>>(g->mz_pcount, G.Nz, g->mz_pstart, g->mz_cursor, g->mz_cnt + C_PARK);
+    k_mz_scatter<T><<<256, 256, 0, g->s>>>(mzp(g, MZ_STOP), g->mz_cnt + C_STOP, g->mz_cap, nxy, g->mz_cursor,
+                                            mzp(g, MZ_PARK));
+  }
+
+  static MzBatchArgs mz_batch_args(gempic* g, int64_t row, double zeta_abs, double b0, int base, int64_t id0) {
+    const Geom& G = g->g;
+    MzBatchArgs ba;
+    ba.g = G;
+    ba.ppcx = g->ppcx;
+    ba.ppcy = g->ppcy;
+    ba.quiet = g->quiet;
+    ba.key = sm_mix(g->cfg.seed ^ (2ull << 56));
+    ba.row = row;
+    // cell n with zeta_n < zeta <= zeta_{n+1}, offset in (0, 1]
+    int n = (int)(std::lower_bound(g->zn.begin(), g->zn.end(), zeta_abs) - g->zn.begin()) - 1;
+    n = std::max(0, std::min(n, G.Nz - 1));
+    ba.iz = n;
+    ba.oz = (zeta_abs - g->zn[n]) / (g->zn[n + 1] - g->zn[n]);
+    ba.n_e = g->cfg.n_e;
+    ba.ratio = g->cfg.ch_ratio;
+    ba.R = g->cfg.ch_radius * g->cfg.length_unit;
+    ba.Delta = g->Delta;
+    ba.b0 = b0;
+    ba.base = base;
+    ba.id0 = id0;
+    ba.capacity = g->mz_cap;
+    ba.err = g->err_dev;
+    return ba;
+  }
+
+  static MzNodeArgs<T> mz_node_args(gempic* g, int n, T D) {
+    const Geom& G = g->g;
+    MzNodeArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = G;
+    a.n = n;
+    a.h = (T)(g->zn[n + 1] - g->zn[n]);
+    a.D = D;
+    a.first = g->mz_first;
+    for (int q = 0; q < 2; ++q) a.j0[q] = (C*)g->mz_j0[q];
+    for (int q = 0; q < 4; ++q) a.st[q] = (C*)g->st[q];
+    a.L[0] = (C*)g->Lsp[0];
+    a.L[1] = (C*)g->Lsp[1];
+    return a;
+  }
+
+  // creation: laser (Sec. 6, eq. E_laser) on the nodes zeta_n as a forward
+  // wave, the consistency march with Delta = 0 node by node, real fields,
+  // and (GT1, Delta < L) the batches already in the box
+  static int mz_init(gempic* g) {
+    const Geom& G = g->g;
+    int64_t nxy = (int64_t)G.Ny * G.Nx;
+    int64_t M = (int64_t)G.Ny * G.Nxh;
+    int64_t nsp = (int64_t)G.Nz * M;
+    for (int q = 0; q < 4; ++q) fill(g, g->st[q], 2 * nsp);
+    for (int q = 0; q < 2; ++q) fill(g, g->Lsp[q], 2 * nsp);
+    for (int q = 0; q < 2; ++q) fill(g, g->mz_j0[q], 2 * (nsp + M));
+    fill(g, g->mz_dep, 3 * nxy);
+    if (g->cfg.a0 != 0.0) {
+      std::vector<double> lon(G.Nz), tra(nxy);
+      for (int n = 0; n < G.Nz; ++n) {
+        double phi = g->zn[n] - g->zeta_c;
+        lon[n] = g->cfg.a0 * std::cos(phi) * std::exp(-(phi * phi) / (g->Tlas * g->Tlas));
+      }
+      for (int j = 0; j < G.Ny; ++j)
+        for (int i = 0; i < G.Nx; ++i) {
+          double X = (double)i * G.hx - (double)(G.Nx / 2) * G.hx;
+          double Y = G.dims == 3 ? (double)j * G.hy - (double)(G.Ny / 2) * G.hy : 0.0;
+          tra[(int64_t)j * G.Nx + i] = g->waist > 0.0 ? std::exp(-(X * X + Y * Y) / (g->waist * g->waist)) : 1.0;
+        }
+      double* dl = (double*)g->dev.alloc(lon.size() * 8);
+      double* dt = (double*)g->dev.alloc(tra.size() * 8);
+      if (!dl || !dt) return fail(g, GEMPIC_ENOMEM, "laser buffers");
+      HIPCHK(g, hipMemcpyAsync(dl, lon.data(), lon.size() * 8, hipMemcpyHostToDevice, g->s));
+      HIPCHK(g, hipMemcpyAsync(dt, tra.data(), tra.size() * 8, hipMemcpyHostToDevice, g->s));
+      k_laser<T><<<nblk((int64_t)G.Nz * nxy, 256), 256, 0, g->s>>>((T*)g->J[0], dl, dt, G.Nz, nxy);
+      fft_fwd(g, (const T*)g->J[0], (C*)g->st[g->cfg.pol == 0 ? 0 : 1], G.Nz);
+      HIPCHK(g, hipStreamSynchronize(g->s));
+      g->dev.free(dl);
+      g->dev.free(dt);
+      fill(g, g->J[0], (int64_t)G.NPJ * nxy);
+    }
+    g->mz_first = 1;
+    for (int n = G.Nz - 1; n >= 0; --n) {
+      MzNodeArgs<T> a = mz_node_args(g, n, (T)0);
+      for (int q = 0; q < 6; ++q) a.out[q] = (C*)g->outs[q] + (int64_t)n * M;
+      k_mz_node<T><<<nblk(M, 256), 256, 0, g->s>>>(a);
+    }
+    fft_inv6(g);
+    // particles already in the box (GT1): batches at L - m Delta, budget 0
+    k_fill<int32_t><<<1, 64, 0, g->s>>>(g->mz_cnt, 8, 0);
+    const double L = g->zn[G.Nz];
+    int64_t nb = 0;
+    if (g->cfg.n_e > 0.0 && g->scheme == 1) {
+      for (int64_t m = 1; L - (double)m * g->Delta > 0.0; ++m) {
+        MzBatchArgs ba = mz_batch_args(g, -m, L - (double)m * g->Delta, 0.0, (int)((m - 1) * g->nperp),
+                                       (m - 1) * g->nperp);
+        k_mz_batch<T><<<nblk(g->nperp, 256), 256, 0, g->s>>>(ba, mzp(g, MZ_STOP));
+        nb = m;
+      }
+    }
+    g->mz_batches = nb;
+    int cnt = (int)(nb * g->nperp);
+    HIPCHK(g, hipMemcpyAsync(g->mz_cnt + C_STOP, &cnt, sizeof(int), hipMemcpyHostToDevice, g->s));
+    mz_sort(g);
+    int rc = launch_check(g, "zeta-march initial state");
+    if (rc) return rc;
+    HIPCHK(g, hipStreamSynchronize(g->s));
+    return GEMPIC_OK;
+  }
+
+  template <int DIM>
+  static void mz_stage(gempic* g, int n, T D) {
+    const Geom& G = g->g;
+    MzStageArgs<T> a;
+    a.g = G;
+    a.n = n;
+    a.hn = (T)(g->zn[n + 1] - g->zn[n]);
+    a.hx = (T)G.hx;
+    a.hy = (T)(G.dims == 3 ? G.hy : 1.0);
+    a.D = D;
+    a.ds_perp = (T)(0.5 * (G.dims == 3 ? std::min(G.hx, G.hy) : G.hx));
+    a.scheme = g->scheme;
+    a.cap = g->mz_subcap;
+    a.capacity = g->mz_cap;
+    a.F0 = (const T*)g->F6;
+    a.F1 = (const T*)g->F6b;
+    a.dep = (T*)g->mz_dep;
+    a.in = mzp(g, MZ_ACT + (n & 1));
+    a.in_count = g->mz_cnt + C_ACT + (n & 1);
+    a.park = mzp(g, MZ_PARK);
+    a.pstart = g->mz_pstart;
+    a.pcount = g->mz_pcount;
+    a.out = mzp(g, MZ_ACT + ((n + 1) & 1));
+    a.out_count = g->mz_cnt + C_ACT + ((n + 1) & 1);
+    a.stop = mzp(g, MZ_STOP);
+    a.stop_count = g->mz_cnt + C_STOP;
+    a.left_count = g->mz_cnt + C_LEFT;
+    a.err = g->err_dev;
+    k_mz_stage<T, DIM><<<g->mz_stage_blocks, 256, 0, g->s>>>(a);
+  }
+
+  // one slow step of the zeta march
+  static int mz_step(gempic* g) {
+    const Geom& G = g->g;
+    const int Nz = G.Nz;
+    const int64_t M = (int64_t)G.Ny * G.Nxh;
+    const int64_t nxy = (int64_t)G.Ny * G.Nx;
+    const T D = (T)g->Delta;
+    int rc = mark(g, 0);
+    if (rc) return rc;
+    const int fresh = g->cfg.n_e > 0.0 ? (int)g->nperp : 0;
+    k_mz_begin<T><<<256, 256, 0, g->s>>>(mzp(g, MZ_PARK), g->mz_cnt + C_PARK, g->mz_cap, D,
+                                          g->mz_cnt + C_ACT + ((Nz - 1) & 1), fresh,
+                                          g->mz_cnt + C_ACT + (Nz & 1), g->mz_cnt + C_STOP, g->mz_cnt + C_LEFT);
+    if (fresh) {
+      MzBatchArgs ba = mz_batch_args(g, g->step, g->zn[Nz], g->Delta, 0,
+                                     (g->mz_batches + g->step) * g->nperp);
+      k_mz_batch<T><<<nblk(g->nperp, 256), 256, 0, g->s>>>(ba, mzp(g, MZ_ACT + ((Nz - 1) & 1)));
+    }
+    if ((rc = launch_check(g, "zeta-march step start"))) return rc;
+    if ((rc = mark(g, 1))) return rc;
+    C* out6[6];
+    const C* in6[6];
+    for (int q = 0; q < 6; ++q) {
+      out6[q] = (C*)g->mz_out6 + q * M;
+      in6[q] = out6[q];
+    }
+    for (int n = Nz - 1; n >= 0; --n) {
+      if (G.dims == 3) mz_stage<3>(g, n, D);
+      else mz_stage<2>(g, n, D);
+      fft_fwd(g, (const T*)g->mz_dep, (C*)g->mz_jhat, 3);
+      MzNodeArgs<T> a = mz_node_args(g, n, D);
+      a.jhat = (const C*)g->mz_jhat;
+      for (int q = 0; q < 6; ++q) a.out[q] = out6[q];
+      a.dep = (T*)g->mz_dep;
+      for (int q = 0; q < 3; ++q) a.jrec[q] = (T*)g->J[q] + (int64_t)(n + 2) * nxy;
+      a.zero_count = g->mz_cnt + C_ACT + (n & 1);
+      k_mz_node<T><<<nblk(std::max<int64_t>(M, 3 * nxy / 8), 256), 256, 0, g->s>>>(a);
+      if (G.Ny > 1) fft_y(g, out6[0], 6, 1);
+      c2r6(g, in6, (T*)g->F6b + (int64_t)n * nxy * 6, G.Ny);
+    }
+    if ((rc = launch_check(g, "zeta-march stages"))) return rc;
+    if ((rc = mark(g, 2))) return rc;
+    mz_sort(g);
+    std::swap(g->F6, g->F6b);
+    g->mz_first = 0;
+    g->s_total += g->Delta;
+    if ((rc = launch_check(g, "zeta-march parking"))) return rc;
+    if ((rc = mark(g, 3))) return rc;
+    if ((rc = mark(g, 4))) return rc;
+    if (g->timing) g->tsteps += 1;
+    g->step += 1;
+    return GEMPIC_OK;
+  }
+
+  static int mz_diag(gempic* g, gempic_diag* d) {
+    const Geom& G = g->g;
+    int cnt[5] = {0, 0, 0, 0, 0};
+    HIPCHK(g, hipMemcpyAsync(cnt, g->mz_cnt, sizeof(cnt), hipMemcpyDeviceToHost, g->s));
+    k_mz_wsum<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->mz_part[MZ_PARK][7], g->mz_cnt + C_PARK,
+                                                 g->partial);
+    k_final<<<1, 256, 0, g->s>>>(g->partial, DIAG_BLOCKS, 1, g->dres + 1);
+    k_mz_energy<T><<<DIAG_BLOCKS, 256, 0, g->s>>>((const T*)g->F6, g->mz_hnode, G.Nz, (int64_t)G.Ny * G.Nx,
+                                                  g->partial + 2 * DIAG_BLOCKS);
+    k_final<<<1, 256, 0, g->s>>>(g->partial + 2 * DIAG_BLOCKS, DIAG_BLOCKS, 1, g->dres);
+    double res[2] = {0, 0};
+    HIPCHK(g, hipMemcpyAsync(res, g->dres, 16, hipMemcpyDeviceToHost, g->s));
+    HIPCHK(g, hipStreamSynchronize(g->s));
+    d->tau = g->s_total;
+    d->step = g->step;
+    d->n_particles = cnt[C_PARK];
+    d->field_energy = 0.5 * res[0] * G.hx * (G.dims == 3 ? G.hy : 1.0);
+    d->charge_particles = -1.0 * res[1];
+    d->charge_grid = 0.0;
+    d->continuity_rel = 0.0;
+    d->fallbacks = 0;
+    d->denoise_rel = 0.0;
+    return GEMPIC_OK;
+  }
+
   static int diag(gempic* g, gempic_diag* d) {
     const Geom& G = g->g;
     int64_t n = 0, np = 0;
@@ -773,6 +1043,7 @@ static int check_errors(gempic* g) {
   if (e & ERR_NUMERIC) return fail(g, GEMPIC_ENUMERIC, "non-finite particle momentum");
   if (e & ERR_CAPACITY) return fail(g, GEMPIC_ECAPACITY, "particle buffer capacity exceeded");
   if (e & ERR_TILE) return fail(g, GEMPIC_EDEVICE, "internal: particle outside its tile or chunk too long");
+  if (e & ERR_MARCH) return fail(g, GEMPIC_EDEVICE, "internal: a particle exceeded the sub-step bound of a zeta-march stage");
   return GEMPIC_OK;
 }
 
@@ -789,6 +1060,7 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
     return GEMPIC_EINVAL;
   }
   if (c->filter_passes < 0 || c->filter_passes > 2) { *why = "filter_passes must be 0, 1 or 2"; return GEMPIC_EINVAL; }
+  if (c->scheme < 0 || c->scheme > 2) { *why = "scheme must be 0 (tau), 1 (GT1 zeta march) or 2 (GT2)"; return GEMPIC_EINVAL; }
   double lu = c->length_unit;
   G->dims = c->dims;
   G->Nx = c->n[0];
@@ -813,12 +1085,40 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->hy = c->dims == 3 ? c->d[1] * lu : 1.0;
   G->h = c->d[2] * lu;
   if (!(G->hx > 0 && G->hy > 0 && G->h > 0)) { *why = "grid steps must be > 0"; return GEMPIC_EINVAL; }
-  G->dtau = c->dtau * lu;
-  if (G->dtau == 0.0) G->dtau = 0.5 * G->h;
-  if (!(G->dtau > 0)) { *why = "dtau must be >= 0"; return GEMPIC_EINVAL; }
-  if (2.0 * G->dtau > G->h * (1.0 + 1e-12)) { *why = "slow step too large: need 2 dtau <= h"; return GEMPIC_ECFL; }
   if (c->n_e < 0) { *why = "n_e must be >= 0"; return GEMPIC_EINVAL; }
-  if (c->n_e > 0.0 && G->dtau * G->h > 4.0 / c->n_e) { *why = "slow step violates Delta*h <= 4/omega_p^2"; return GEMPIC_ECFL; }
+  if (c->scheme == 0) {
+    G->dtau = c->dtau * lu;
+    if (G->dtau == 0.0) G->dtau = 0.5 * G->h;
+    if (!(G->dtau > 0)) { *why = "dtau must be >= 0"; return GEMPIC_EINVAL; }
+    if (2.0 * G->dtau > G->h * (1.0 + 1e-12)) { *why = "slow step too large: need 2 dtau <= h"; return GEMPIC_ECFL; }
+    if (c->n_e > 0.0 && G->dtau * G->h > 4.0 / c->n_e) { *why = "slow step violates Delta*h <= 4/omega_p^2"; return GEMPIC_ECFL; }
+  } else {
+    G->dtau = 0.5 * G->h;   // unused by the zeta march
+    if (c->precision == GEMPIC_FP32_ABS) { *why = "the zeta march needs precision FP64 or FP32_CELL"; return GEMPIC_EINVAL; }
+    if (c->beam_np != 0) { *why = "the zeta march takes no driver beam"; return GEMPIC_EINVAL; }
+    if (c->deposit_rho) { *why = "the zeta march deposits no charge (deposit_rho = 0)"; return GEMPIC_EINVAL; }
+    if (G->Nz > 65536) { *why = "the zeta march needs n[2] <= 65536"; return GEMPIC_EINVAL; }
+    if (!(c->delta > 0)) { *why = "the zeta march needs delta > 0"; return GEMPIC_EINVAL; }
+    double hmax = G->h;
+    if (c->zeta_nodes) {
+      const double* zn = c->zeta_nodes;
+      if (zn[0] != 0.0) { *why = "zeta_nodes must start at 0"; return GEMPIC_EINVAL; }
+      hmax = 0.0;
+      for (int n = 0; n < G->Nz; ++n) {
+        double hn = zn[n + 1] - zn[n];
+        if (!(hn > 0)) { *why = "zeta_nodes must increase"; return GEMPIC_EINVAL; }
+        hmax = std::max(hmax, hn * lu);
+      }
+    }
+    if (c->n_e > 0.0 && c->delta * lu * hmax > 4.0 / c->n_e) {
+      *why = "slow step violates Delta*h <= 4/omega_p^2";
+      return GEMPIC_ECFL;
+    }
+    if (c->ch_ratio < 0 || (c->ch_ratio > 0 && c->ch_ratio != 1.0 && !(c->ch_radius > 0))) {
+      *why = "channel needs ch_ratio >= 0 and ch_radius > 0";
+      return GEMPIC_EINVAL;
+    }
+  }
   if (c->ppc[0] < 1 || c->ppc[2] < 1 || (c->dims == 3 && c->ppc[1] < 1)) { *why = "ppc must be >= 1"; return GEMPIC_EINVAL; }
   if (c->pol != 0 && c->pol != 1) { *why = "pol must be 0 or 1"; return GEMPIC_EINVAL; }
   G->P = c->filter_passes;
@@ -856,6 +1156,105 @@ static int validate(const gempic_config* c, Geom* G, std::string* why) {
   G->Lx = (float)((double)G->Nx * G->hx);
   G->Ly = (float)((double)G->Ny * G->hy);
   return GEMPIC_OK;
+}
+
+static int upload_twiddles(gempic* g) {
+  const Geom& G = g->g;
+  auto twiddles = [&](int N, void* dst) -> int {
+    int hN = std::max(1, N / 2);
+    std::vector<double> tw(2 * hN);
+    for (int t = 0; t < hN; ++t) {
+      double a = -2.0 * M_PI * (double)t / (double)N;
+      tw[2 * t] = std::cos(a);
+      tw[2 * t + 1] = std::sin(a);
+    }
+    if (g->prec == 0) return (int)hipMemcpy(dst, tw.data(), tw.size() * 8, hipMemcpyHostToDevice);
+    std::vector<float> f(tw.begin(), tw.end());
+    return (int)hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+  };
+  if (twiddles(G.Nx, g->twx) || twiddles(std::max(G.Ny, 2), g->twy) ||
+      hipMemset(g->err_dev, 0, sizeof(int)) != hipSuccess)
+    return fail(g, GEMPIC_EDEVICE, "initial device copies failed");
+  return GEMPIC_OK;
+}
+
+// sub-step bound of a zeta-march stage: every sub-step that neither reaches
+// the node nor ends the budget advances time by the transverse limit and
+// either zeta or the budget by at least half of it (GT1: all of it)
+static void march_subcap(gempic* g) {
+  const Geom& G = g->g;
+  double hmax = 0.0;
+  for (int n = 0; n < G.Nz; ++n) hmax = std::max(hmax, g->zn[n + 1] - g->zn[n]);
+  double dsp = 0.5 * (G.dims == 3 ? std::min(G.hx, G.hy) : G.hx);
+  g->mz_subcap = (int)std::min(1e8, 2.0 * std::ceil((hmax + g->Delta) / dsp) + 8.0);
+}
+
+// creation of a zeta-march handle (scheme 1, 2)
+static int create_march(gempic* g) {
+  const gempic_config* cfg = &g->cfg;
+  const Geom& G = g->g;
+  const double lu = cfg->length_unit;
+  g->zn.resize(G.Nz + 1);
+  for (int n = 0; n <= G.Nz; ++n) g->zn[n] = cfg->zeta_nodes ? cfg->zeta_nodes[n] * lu : (double)n * G.h;
+  g->Delta = cfg->delta * lu;
+  g->nperp = cfg->n_e > 0.0 ? (int64_t)G.Nx * G.Ny * g->ppcx * g->ppcy : 0;
+  const double L = g->zn[G.Nz];
+  int64_t mb = cfg->scheme == 1 ? (int64_t)std::ceil(L / g->Delta) : (int64_t)std::ceil(L / g->Delta) + 1;
+  int64_t cap = g->nperp * (mb + 3) + g->nperp / 2 + 4096;
+  if (cap > (int64_t)INT32_MAX) return fail(g, GEMPIC_EINVAL, "zeta-march particle capacity beyond 2^31 - 1");
+  g->mz_cap = (int)cap;
+  g->mz_stage_blocks = (int)std::max<int64_t>(64, std::min<int64_t>(4096, (2 * g->nperp + 255) / 256));
+  march_subcap(g);
+  Dev& d = g->dev;
+  bool ok = true;
+  size_t es = g->esz;
+  auto A = [&](size_t bytes) { void* p = d.alloc(bytes); ok = ok && p; return p; };
+  for (int k = 0; k < 4; ++k) {
+    g->mz_part[k][0] = A((size_t)cap * 4);
+    for (int q = 1; q <= 8; ++q) g->mz_part[k][q] = A((size_t)cap * es);
+    g->mz_part[k][9] = cfg->track_ids ? A((size_t)cap * 8) : nullptr;
+  }
+  g->mz_cnt = (int*)A(8 * sizeof(int));
+  g->mz_pstart = (int*)A((size_t)G.Nz * 4);
+  g->mz_pcount = (int*)A((size_t)G.Nz * 4);
+  g->mz_cursor = (int*)A((size_t)G.Nz * 4);
+  int64_t nxy = (int64_t)G.Ny * G.Nx;
+  int64_t M = (int64_t)G.Ny * G.Nxh;
+  int64_t nsp = (int64_t)G.Nz * M;
+  int64_t nf = (int64_t)G.Nz * nxy;
+  g->mz_dep = A((size_t)3 * nxy * es);
+  g->mz_jhat = A((size_t)3 * M * 2 * es);
+  g->mz_out6 = A((size_t)6 * M * 2 * es);
+  for (int q = 0; q < 2; ++q) g->mz_j0[q] = A((size_t)(nsp + M) * 2 * es);
+  g->F6 = A((size_t)6 * nf * es);
+  g->F6b = A((size_t)6 * nf * es);
+  for (int q = 0; q < 3; ++q) g->J[q] = A((size_t)G.NPJ * nxy * es);
+  for (int q = 0; q < 4; ++q) g->st[q] = A((size_t)nsp * 2 * es);
+  for (int q = 0; q < 6; ++q) g->outs[q] = A((size_t)nsp * 2 * es);
+  for (int q = 0; q < 2; ++q) g->Lsp[q] = A((size_t)nsp * 2 * es);
+  g->twx = A((size_t)std::max(1, G.Nx / 2) * 2 * es);
+  g->twy = A((size_t)std::max(1, G.Ny / 2) * 2 * es);
+  g->partial = (double*)A(6 * DIAG_BLOCKS * 8);
+  g->dres = (double*)A(4 * 8);
+  g->err_dev = (int*)A(sizeof(int));
+  g->mz_hnode = (double*)A((size_t)G.Nz * 8);
+  if (!ok) return fail(g, GEMPIC_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(d.last));
+  int rc = upload_twiddles(g);
+  if (rc) return rc;
+  std::vector<double> hnode(G.Nz);
+  for (int n = 0; n < G.Nz; ++n) {
+    double hl = n > 0 ? g->zn[n] - g->zn[n - 1] : g->zn[1] - g->zn[0];
+    hnode[n] = 0.5 * (hl + (g->zn[n + 1] - g->zn[n]));
+  }
+  HIPCHK(g, hipMemcpy(g->mz_hnode, hnode.data(), G.Nz * 8, hipMemcpyHostToDevice));
+  if (g->prec == 0) Impl<double>::set_lds_limits(); else Impl<float>::set_lds_limits();
+  for (int q = 0; q < 3; ++q) {
+    if (g->prec == 0) Impl<double>::fill(g, g->J[q], (int64_t)G.NPJ * nxy);
+    else Impl<float>::fill(g, g->J[q], (int64_t)G.NPJ * nxy);
+  }
+  rc = g->prec == 0 ? Impl<double>::mz_init(g) : Impl<float>::mz_init(g);
+  if (rc == GEMPIC_OK) rc = check_errors(g);
+  return rc;
 }
 
 extern "C" {
@@ -932,6 +1331,18 @@ int gempic_create(const gempic_config* cfg, gempic_t** out) {
   g->tsteps = 0;
   g->cur = 0;
   g->ctc = 0;
+  g->scheme = cfg->scheme;
+  g->s_total = 0.0;
+  if (g->scheme != 0) {
+    rc = create_march(g);
+    if (rc) {
+      g_create_error = g->err;
+      gempic_destroy(g);
+      return rc;
+    }
+    *out = g;
+    return GEMPIC_OK;
+  }
 
   // capacities
   int64_t ncell_p = (int64_t)G.Nzp * G.Ny * G.Nx;
@@ -1045,13 +1456,16 @@ int gempic_step(gempic_t* g, int32_t nsteps, gempic_diag* diag) {
   if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
   if (nsteps < 0) return fail(g, GEMPIC_EINVAL, "nsteps < 0");
   for (int k = 0; k < nsteps; ++k) {
-    int rc = g->prec == 0 ? Impl<double>::one_step(g) : Impl<float>::one_step(g);
+    int rc;
+    if (g->scheme) rc = g->prec == 0 ? Impl<double>::mz_step(g) : Impl<float>::mz_step(g);
+    else rc = g->prec == 0 ? Impl<double>::one_step(g) : Impl<float>::one_step(g);
     if (rc) return rc;
   }
   int rc = check_errors(g);
   if (rc) return rc;
   if (diag) {
-    rc = g->prec == 0 ? Impl<double>::diag(g, diag) : Impl<float>::diag(g, diag);
+    if (g->scheme) rc = g->prec == 0 ? Impl<double>::mz_diag(g, diag) : Impl<float>::mz_diag(g, diag);
+    else rc = g->prec == 0 ? Impl<double>::diag(g, diag) : Impl<float>::diag(g, diag);
     if (rc) return rc;
   }
   return GEMPIC_OK;
@@ -1094,9 +1508,32 @@ int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size
   return GEMPIC_OK;
 }
 
+static int march_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, void* u, int64_t* id,
+                           void* w, void* b, size_t capacity, size_t* count) {
+  int n = 0;
+  HIPCHK(g, hipMemcpyAsync(&n, g->mz_cnt + 4, sizeof(int), hipMemcpyDeviceToHost, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  *count = (size_t)n;
+  if ((size_t)n > capacity) return fail(g, GEMPIC_EINVAL, "capacity smaller than the particle count");
+  if (id && !g->mz_part[0][9]) return fail(g, GEMPIC_EINVAL, "ids need track_ids = 1");
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  size_t es = g->esz;
+  if (cell) HIPCHK(g, hipMemcpyAsync(cell, g->mz_part[0][0], (size_t)n * 4, kind, g->s));
+  for (int q = 0; q < 3; ++q) {
+    if (off) HIPCHK(g, hipMemcpyAsync((char*)off + q * capacity * es, g->mz_part[0][1 + q], (size_t)n * es, kind, g->s));
+    if (u) HIPCHK(g, hipMemcpyAsync((char*)u + q * capacity * es, g->mz_part[0][4 + q], (size_t)n * es, kind, g->s));
+  }
+  if (w) HIPCHK(g, hipMemcpyAsync(w, g->mz_part[0][7], (size_t)n * es, kind, g->s));
+  if (b) HIPCHK(g, hipMemcpyAsync(b, g->mz_part[0][8], (size_t)n * es, kind, g->s));
+  if (id) HIPCHK(g, hipMemcpyAsync(id, g->mz_part[0][9], (size_t)n * 8, kind, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
 int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, void* u, int64_t* id,
                      size_t capacity, size_t* count) {
   if (!g || !count) return GEMPIC_EINVAL;
+  if (g->scheme) return march_particles(g, on_device, cell, off, u, id, nullptr, nullptr, capacity, count);
   int64_t n = 0;
   HIPCHK(g, hipMemcpyAsync(&n, g->total, 8, hipMemcpyDeviceToHost, g->s));
   HIPCHK(g, hipStreamSynchronize(g->s));
@@ -1129,9 +1566,36 @@ int gempic_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, v
   return GEMPIC_OK;
 }
 
+int gempic_march_particles(gempic_t* g, int32_t on_device, void* w, void* b, size_t capacity, size_t* count) {
+  if (!g || !count) return GEMPIC_EINVAL;
+  if (!g->scheme) return fail(g, GEMPIC_EINVAL, "weights and budgets belong to the zeta march");
+  return march_particles(g, on_device, nullptr, nullptr, nullptr, nullptr, w, b, capacity, count);
+}
+
+int gempic_set_slow_step(gempic_t* g, double delta) {
+  if (!g) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  if (!g->scheme) return fail(g, GEMPIC_EINVAL, "the tau scheme's slow step is fixed at creation (dtau)");
+  if (!(delta > 0)) return fail(g, GEMPIC_EINVAL, "delta must be > 0");
+  double D = delta * g->cfg.length_unit;
+  double hmax = 0.0;
+  for (int n = 0; n < g->g.Nz; ++n) hmax = std::max(hmax, g->zn[n + 1] - g->zn[n]);
+  if (g->cfg.n_e > 0.0 && D * hmax > 4.0 / g->cfg.n_e)
+    return fail(g, GEMPIC_EINVAL, "slow step violates Delta*h <= 4/omega_p^2");
+  // the particle buffers hold the batches of the smallest Delta they were sized for
+  const double L = g->zn[g->g.Nz];
+  int64_t mb = (int64_t)std::ceil(L / D) + 1;
+  if (g->nperp * (mb + 3) + g->nperp / 2 + 4096 > (int64_t)g->mz_cap)
+    return fail(g, GEMPIC_EINVAL, "delta smaller than the particle buffers were sized for at creation");
+  g->Delta = D;
+  march_subcap(g);
+  return GEMPIC_OK;
+}
+
 int gempic_set_state(gempic_t* g, int64_t step, const int32_t* cell, const void* off, const void* u,
                      const int64_t* id, size_t count, const void* spectral, size_t spectral_bytes) {
   if (!g) return GEMPIC_EINVAL;
+  if (g->scheme) return fail(g, GEMPIC_EINVAL, "gempic_set_state serves the tau scheme");
   if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
   const Geom& G = g->g;
   size_t es = g->esz;
@@ -1247,6 +1711,7 @@ int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps) {
 
 int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes) {
   if (!g || !fields) return GEMPIC_EINVAL;
+  if (g->scheme) return fail(g, GEMPIC_EINVAL, "gempic_set_fields serves the tau scheme");
   if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
   const Geom& G = g->g;
   size_t nb = (size_t)G.Nz * G.Ny * G.Nx * g->esz;
@@ -1268,6 +1733,7 @@ int gempic_set_denoiser(gempic_t* g, gempic_dn_t* d, double threshold) {
   if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
   const Geom& G = g->g;
   if (!d) { g->dn = nullptr; return GEMPIC_OK; }
+  if (g->scheme) return fail(g, GEMPIC_EINVAL, "the denoiser serves the tau scheme");
   if (g->prec != 1 || G.dims != 3) return fail(g, GEMPIC_EINVAL, "the denoiser needs an FP32 3-D simulation");
   if (G.Nx % 16 || G.Ny % 8) return fail(g, GEMPIC_EINVAL, "the denoiser needs Nx % 16 == 0 and Ny % 8 == 0");
   if (!(g->cfg.n_e > 0)) return fail(g, GEMPIC_EINVAL, "the denoiser needs a plasma (n_e > 0)");

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libgempic.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 BEAM_BIT = 1 << 30
 FP64, FP32_CELL, FP32_ABS = 0, 1, 2
 EX, EY, EZ, BX, BY, BZ, JX, JY, JZ, RHO = (1 << i for i in range(10))
@@ -45,7 +45,9 @@ class gempic_config(ctypes.Structure):
         ("track_ids", ctypes.c_int32), ("deposit_rho", ctypes.c_int32),
         ("beam_n", ctypes.c_double), ("beam_sr", ctypes.c_double), ("beam_sz", ctypes.c_double),
         ("beam_zc", ctypes.c_double), ("beam_gamma", ctypes.c_double), ("beam_dgamma", ctypes.c_double),
-        ("beam_np", ctypes.c_int64), ("stream", ctypes.c_void_p),
+        ("beam_np", ctypes.c_int64), ("scheme", ctypes.c_int32), ("delta", ctypes.c_double),
+        ("zeta_nodes", ctypes.c_void_p), ("ch_ratio", ctypes.c_double), ("ch_radius", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -78,6 +80,9 @@ _SIGS = {
     "gempic_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "gempic_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "gempic_set_slow_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "gempic_march_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "gempic_destroy": (None, [ctypes.c_void_p]),
     "gempic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gempic_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -163,6 +168,15 @@ def make_config(cfg, stream=None, track_ids=False, deposit_rho=False):
     c.beam_gamma = float(b.get("gamma", 1.0))
     c.beam_dgamma = float(b.get("dgamma", 0.0))
     c.beam_np = int(b.get("np", 0))
+    c.scheme = int(cfg.get("scheme", 0))
+    c.delta = float(cfg.get("delta", 0.0))
+    zn = cfg.get("zeta_nodes")
+    if zn is not None:
+        arr = np.ascontiguousarray(zn, np.float64)
+        c._zeta_nodes = arr            # kept alive with the struct until creation copies it
+        c.zeta_nodes = arr.ctypes.data_as(ctypes.c_void_p)
+    c.ch_ratio = float(cfg.get("ch_ratio", 0.0))
+    c.ch_radius = float(cfg.get("ch_radius", 0.0))
     c.stream = stream
     return c
 
@@ -315,6 +329,20 @@ class Sim:
             raise ValueError("names must follow the library order " + str(FIELD_NAMES))
         gempic_fields(self.h, mask, 1, ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size())
         return out
+
+    def march_particles(self):
+        """Zeta march: weights and remaining slow budgets, in the order of
+        particles()."""
+        cap = self._count()
+        w = np.empty(cap, self.dtype)
+        b = np.empty(cap, self.dtype)
+        cnt = ctypes.c_size_t()
+        _check(lib().gempic_march_particles(self.h, 0, _ptr(w), _ptr(b), cap, ctypes.byref(cnt)), self.h)
+        return dict(w=w[:cnt.value], b=b[:cnt.value])
+
+    def set_slow_step(self, delta):
+        """Zeta march: slow step of the following steps (config units)."""
+        _check(lib().gempic_set_slow_step(self.h, float(delta)), self.h)
 
     def set_denoiser(self, dn, threshold=1e-3):
         """Attach a Denoiser (None detaches); the Denoiser must outlive it."""

@@ -120,3 +120,29 @@ def test_denoiser_parameter_count_and_rejections():
     assert L.gempic_dn_create(None, 5, None, ctypes.byref(h)) == -1
     assert L.gempic_dn_apply(None, None, None, 1.0, None, 1, 1e-3, None, None, None, None) == -1
     assert L.gempic_set_denoiser(None, None, 1e-3) == -1
+
+
+def _march(**kw):
+    cfg = workloads.small3d(precision="fp64", n=(16, 16, 32))
+    cfg.update(scheme=1, delta=0.5)
+    cfg.update(kw)
+    return cfg
+
+
+@pytest.mark.parametrize("change,why", [
+    (dict(scheme=3), b"scheme"), (dict(delta=0.0), b"delta > 0"), (dict(precision="fp32abs"), b"FP64 or FP32_CELL"),
+    (dict(beam=dict(n=1.0, sr=0.3, sz=0.3, gamma=100.0, np=10)), b"driver beam"),
+    (dict(n_e=1e3, delta=50.0), b"4/omega_p^2"), (dict(ch_ratio=0.5, ch_radius=0.0), b"channel"),
+    (dict(zeta_nodes=[0.0] + [0.05] * 32), b"increase"), (dict(zeta_nodes=[0.1 * k + 0.1 for k in range(33)]), b"start at 0")])
+def test_zeta_march_rejections(change, why):
+    cfg = _march(**change)
+    rc, h = _create(cfg)
+    assert rc in (-1, -4) and not h.value
+    assert why in gp.lib().gempic_last_error(None)
+
+
+def test_zeta_march_rejects_deposit_rho():
+    c = gp.make_config(_march(), deposit_rho=True)
+    h = ctypes.c_void_p()
+    assert gp.lib().gempic_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    assert b"deposit_rho" in gp.lib().gempic_last_error(None)
