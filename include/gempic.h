@@ -266,10 +266,30 @@ int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes);
 int gempic_timing(gempic_t* g, int32_t enable);
 int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps);
 
+/* Witness-bunch diagnostics in the style of Table 1 (Sec. 6): over the
+ * macro-particles with gamma >= gamma_min, weighted by their electrons w,
+ * the charge q sum w, the mean and rms of gamma (energy gamma m c^2), the
+ * weighted means and rms sizes of x, y (from the axis node (Nx/2, Ny/2)) and
+ * zeta (from zeta = 0), and the normalised rms emittances
+ * eps = sqrt(<dx^2><du_x^2> - <dx du_x>^2) (u = gamma v in units of c;
+ * lengths in the normalised unit).  FP64, two-pass and deterministic.  Both
+ * schemes; GEMPIC_EINVAL in the FP32-absolute mode. */
+typedef struct {
+  double  charge;
+  int64_t n_macro;
+  double  gamma_mean, gamma_rms;
+  double  mean[3];
+  double  sigma[3];
+  double  emittance[2];
+} gempic_bunch;
+int gempic_bunch_diag(gempic_t* g, double gamma_min, gempic_bunch* out);
+
 /* Zeta march (scheme 1, 2): slow step Delta (config units) of the following
  * steps (Sec. 7: Delta may change from one step to the next; the new step's
  * fresh particles carry the new Q_f).  Delta h_max <= 4 / n_e is required
- * (Sec. 4.2).  GEMPIC_EINVAL for the tau scheme or an invalid Delta. */
+ * (Sec. 4.2), and Delta at least a quarter of the creation's delta (the
+ * particle buffers are sized for that many batches in the box).
+ * GEMPIC_EINVAL for the tau scheme or an invalid Delta. */
 int gempic_set_slow_step(gempic_t* g, double delta);
 
 /* Zeta march: weights w (electrons per macro-particle) and remaining slow

@@ -116,6 +116,7 @@ struct gempic {
   void* mz_j0[2];
   void* F6b;                    // new-level node records
   double* mz_hnode;             // node volumes / (h_x h_y): (h_{n-1} + h_n) / 2
+  double* mz_zn;                // node positions on the device
   double s_total;               // slow coordinate reached (sum of the steps' Delta)
   // timing: five events per step while enabled
   bool timing;
@@ -986,6 +987,60 @@ struct Impl {
     return GEMPIC_OK;
   }
 
+  static int bunch(gempic* g, double gamma_min, gempic_bunch* out) {
+    const Geom& G = g->g;
+    BunchArgs<T> a;
+    a.g = G;
+    a.gamma_min = gamma_min;
+    a.partial = g->partial;
+    if (g->scheme) {
+      MzParts<T> P = mzp(g, MZ_PARK);
+      a.count32 = g->mz_cnt + C_PARK;
+      a.count64 = nullptr;
+      a.capacity = g->mz_cap;
+      a.cell = P.cell; a.ox = P.ox; a.oy = P.oy; a.oz = P.oz; a.ux = P.ux; a.uy = P.uy; a.uz = P.uz;
+      a.w = P.w;
+      a.w_plasma = a.w_beam = 0.0;
+      a.zn = g->mz_zn;
+    } else {
+      PartPtrs<T> P = parts(g, g->cur);
+      a.count32 = nullptr;
+      a.count64 = g->total;
+      a.capacity = (int)g->capacity;
+      a.cell = P.cell; a.ox = P.ox; a.oy = P.oy; a.oz = P.oz; a.ux = P.ux; a.uy = P.uy; a.uz = P.uz;
+      a.w = nullptr;
+      a.w_plasma = g->w;
+      a.w_beam = g->wb > 0 ? g->wb : g->w;
+      a.zn = nullptr;
+    }
+    const int nb = 96;   // 96 * BUNCH_NS partials fit the diagnostics buffer (6 * DIAG_BLOCKS)
+    k_bunch<T><<<nb, 256, 0, g->s>>>(a);
+    k_final<<<1, 256, 0, g->s>>>(g->partial, nb, BUNCH_NS, g->partial + nb * BUNCH_NS);
+    double r[BUNCH_NS];
+    HIPCHK(g, hipMemcpyAsync(r, g->partial + nb * BUNCH_NS, sizeof(r), hipMemcpyDeviceToHost, g->s));
+    HIPCHK(g, hipStreamSynchronize(g->s));
+    std::memset(out, 0, sizeof(*out));
+    const double W = r[0];
+    out->n_macro = (int64_t)std::llround(r[15]);
+    out->charge = -1.0 * W;
+    if (!(W > 0)) return GEMPIC_OK;
+    auto mean = [&](int k) { return r[k] / W; };
+    auto var = [&](int k2, int k1a, int k1b) { return r[k2] / W - mean(k1a) * mean(k1b); };
+    out->gamma_mean = mean(1);
+    out->gamma_rms = std::sqrt(std::max(var(2, 1, 1), 0.0));
+    out->mean[0] = mean(3);
+    out->mean[1] = mean(5);
+    out->mean[2] = mean(7);
+    out->sigma[0] = std::sqrt(std::max(var(4, 3, 3), 0.0));
+    out->sigma[1] = std::sqrt(std::max(var(6, 5, 5), 0.0));
+    out->sigma[2] = std::sqrt(std::max(var(8, 7, 7), 0.0));
+    const double vx = var(4, 3, 3), vux = var(10, 9, 9), cx = var(11, 3, 9);
+    const double vy = var(6, 5, 5), vuy = var(13, 12, 12), cy = var(14, 5, 12);
+    out->emittance[0] = std::sqrt(std::max(vx * vux - cx * cx, 0.0));
+    out->emittance[1] = std::sqrt(std::max(vy * vuy - cy * cy, 0.0));
+    return GEMPIC_OK;
+  }
+
   static int diag(gempic* g, gempic_diag* d) {
     const Geom& G = g->g;
     int64_t n = 0, np = 0;
@@ -1198,8 +1253,9 @@ static int create_march(gempic* g) {
   for (int n = 0; n <= G.Nz; ++n) g->zn[n] = cfg->zeta_nodes ? cfg->zeta_nodes[n] * lu : (double)n * G.h;
   g->Delta = cfg->delta * lu;
   g->nperp = cfg->n_e > 0.0 ? (int64_t)G.Nx * G.Ny * g->ppcx * g->ppcy : 0;
+  // room for the batches of a slow step down to Delta / 4 (gempic_set_slow_step)
   const double L = g->zn[G.Nz];
-  int64_t mb = cfg->scheme == 1 ? (int64_t)std::ceil(L / g->Delta) : (int64_t)std::ceil(L / g->Delta) + 1;
+  int64_t mb = (int64_t)std::ceil(4.0 * L / g->Delta) + 1;
   int64_t cap = g->nperp * (mb + 3) + g->nperp / 2 + 4096;
   if (cap > (int64_t)INT32_MAX) return fail(g, GEMPIC_EINVAL, "zeta-march particle capacity beyond 2^31 - 1");
   g->mz_cap = (int)cap;
@@ -1238,6 +1294,7 @@ static int create_march(gempic* g) {
   g->dres = (double*)A(4 * 8);
   g->err_dev = (int*)A(sizeof(int));
   g->mz_hnode = (double*)A((size_t)G.Nz * 8);
+  g->mz_zn = (double*)A((size_t)(G.Nz + 1) * 8);
   if (!ok) return fail(g, GEMPIC_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(d.last));
   int rc = upload_twiddles(g);
   if (rc) return rc;
@@ -1247,6 +1304,7 @@ static int create_march(gempic* g) {
     hnode[n] = 0.5 * (hl + (g->zn[n + 1] - g->zn[n]));
   }
   HIPCHK(g, hipMemcpy(g->mz_hnode, hnode.data(), G.Nz * 8, hipMemcpyHostToDevice));
+  HIPCHK(g, hipMemcpy(g->mz_zn, g->zn.data(), (G.Nz + 1) * 8, hipMemcpyHostToDevice));
   if (g->prec == 0) Impl<double>::set_lds_limits(); else Impl<float>::set_lds_limits();
   for (int q = 0; q < 3; ++q) {
     if (g->prec == 0) Impl<double>::fill(g, g->J[q], (int64_t)G.NPJ * nxy);
@@ -1572,6 +1630,12 @@ int gempic_march_particles(gempic_t* g, int32_t on_device, void* w, void* b, siz
   return march_particles(g, on_device, nullptr, nullptr, nullptr, nullptr, w, b, capacity, count);
 }
 
+int gempic_bunch_diag(gempic_t* g, double gamma_min, gempic_bunch* out) {
+  if (!g || !out) return GEMPIC_EINVAL;
+  if (g->g.abs_pos) return fail(g, GEMPIC_EINVAL, "bunch diagnostics need cell + offset positions");
+  return g->prec == 0 ? Impl<double>::bunch(g, gamma_min, out) : Impl<float>::bunch(g, gamma_min, out);
+}
+
 int gempic_set_slow_step(gempic_t* g, double delta) {
   if (!g) return GEMPIC_EINVAL;
   if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
@@ -1582,11 +1646,11 @@ int gempic_set_slow_step(gempic_t* g, double delta) {
   for (int n = 0; n < g->g.Nz; ++n) hmax = std::max(hmax, g->zn[n + 1] - g->zn[n]);
   if (g->cfg.n_e > 0.0 && D * hmax > 4.0 / g->cfg.n_e)
     return fail(g, GEMPIC_EINVAL, "slow step violates Delta*h <= 4/omega_p^2");
-  // the particle buffers hold the batches of the smallest Delta they were sized for
+  // the particle buffers hold the batches of Delta / 4 of the creation's Delta
   const double L = g->zn[g->g.Nz];
   int64_t mb = (int64_t)std::ceil(L / D) + 1;
   if (g->nperp * (mb + 3) + g->nperp / 2 + 4096 > (int64_t)g->mz_cap)
-    return fail(g, GEMPIC_EINVAL, "delta smaller than the particle buffers were sized for at creation");
+    return fail(g, GEMPIC_EINVAL, "delta below a quarter of the creation's delta (particle buffers)");
   g->Delta = D;
   march_subcap(g);
   return GEMPIC_OK;

@@ -671,3 +671,70 @@ __global__ __launch_bounds__(256) void k_mz_energy(const T* F6, const double* hn
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
+
+// ---------------------------------------------------------------------------
+// Witness-bunch sums (Table 1 style): over the particles with gamma >=
+// gamma_min, weighted by their electrons w, the 16 sums
+//   W, W g, W g^2, W x, W x^2, W y, W y^2, W z, W z^2,
+//   W ux, W ux^2, W x ux, W uy, W uy^2, W y uy, count
+// with x, y measured from the axis node (Nx/2, Ny/2) and z = zeta.  The
+// positions come from cell + offset: along zeta (iz + oz) h in the tau
+// scheme, zn[iz] + oz (zn[iz + 1] - zn[iz]) in the zeta march.  Weights: the
+// march's per-particle w, else w_plasma or (GEMPIC_BEAM_BIT) w_beam.
+#define BUNCH_NS 16
+template <typename T>
+struct BunchArgs {
+  Geom g;
+  const int* count32;       // march: parked count (nullable)
+  const int64_t* count64;   // tau: particles in the buffer (nullable)
+  int capacity;
+  const int32_t* cell;
+  const T *ox, *oy, *oz, *ux, *uy, *uz;
+  const T* w;               // nullable (tau scheme)
+  double w_plasma, w_beam;
+  const double* zn;         // nullable (tau scheme)
+  double gamma_min;
+  double* partial;          // [gridDim][BUNCH_NS]
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bunch(BunchArgs<T> a) {
+  __shared__ double sh[4];
+  const Geom& g = a.g;
+  int64_t n = a.count32 ? (int64_t)*a.count32 : *a.count64;
+  n = min(n, (int64_t)a.capacity);
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(n, i0 + per);
+  double s[BUNCH_NS];
+#pragma unroll
+  for (int k = 0; k < BUNCH_NS; ++k) s[k] = 0.0;
+  const double xa = (double)(g.Nx / 2) * g.hx, ya = (double)(g.Ny / 2) * g.hy;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double ux = (double)a.ux[i], uy = (double)a.uy[i], uz = (double)a.uz[i];
+    const double gm = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    if (!(gm >= a.gamma_min)) continue;
+    int c = a.cell[i];
+    double w;
+    if (a.w) {
+      w = (double)a.w[i];
+    } else {
+      w = (c & GEMPIC_BEAM_BIT) ? a.w_beam : a.w_plasma;
+      c &= ~GEMPIC_BEAM_BIT;
+    }
+    const int ix = c % g.Nx, iy = (c / g.Nx) % g.Ny, iz = c / (g.Nx * g.Ny);
+    const double x = ((double)ix + (double)a.ox[i]) * g.hx - xa;
+    const double y = g.dims == 3 ? ((double)iy + (double)a.oy[i]) * g.hy - ya : 0.0;
+    const double z = a.zn ? a.zn[iz] + (double)a.oz[i] * (a.zn[iz + 1] - a.zn[iz])
+                          : ((double)iz + (double)a.oz[i]) * g.h;
+    const double v[BUNCH_NS] = {w,          w * gm,      w * gm * gm, w * x,      w * x * x,  w * y,
+                                w * y * y,  w * z,       w * z * z,   w * ux,     w * ux * ux, w * x * ux,
+                                w * uy,     w * uy * uy, w * y * uy,  1.0};
+#pragma unroll
+    for (int k = 0; k < BUNCH_NS; ++k) s[k] += v[k];
+  }
+  for (int k = 0; k < BUNCH_NS; ++k) {
+    double t = block_sum(s[k], sh);
+    if (threadIdx.x == 0) a.partial[blockIdx.x * BUNCH_NS + k] = t;
+    __syncthreads();
+  }
+}

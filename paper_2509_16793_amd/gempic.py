@@ -60,6 +60,14 @@ class gempic_diag(ctypes.Structure):
     ]
 
 
+class gempic_bunch(ctypes.Structure):
+    _fields_ = [
+        ("charge", ctypes.c_double), ("n_macro", ctypes.c_int64), ("gamma_mean", ctypes.c_double),
+        ("gamma_rms", ctypes.c_double), ("mean", ctypes.c_double * 3), ("sigma", ctypes.c_double * 3),
+        ("emittance", ctypes.c_double * 2),
+    ]
+
+
 _lib = None
 
 # exported symbols and their signatures (argument marshalling only)
@@ -81,6 +89,7 @@ _SIGS = {
     "gempic_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
     "gempic_set_slow_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "gempic_bunch_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(gempic_bunch)]),
     "gempic_march_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "gempic_destroy": (None, [ctypes.c_void_p]),
@@ -339,6 +348,14 @@ class Sim:
         cnt = ctypes.c_size_t()
         _check(lib().gempic_march_particles(self.h, 0, _ptr(w), _ptr(b), cap, ctypes.byref(cnt)), self.h)
         return dict(w=w[:cnt.value], b=b[:cnt.value])
+
+    def bunch(self, gamma_min):
+        """Witness-bunch diagnostics of the particles with gamma >= gamma_min."""
+        b = gempic_bunch()
+        _check(lib().gempic_bunch_diag(self.h, float(gamma_min), ctypes.byref(b)), self.h)
+        return dict(charge=b.charge, n_macro=b.n_macro, gamma_mean=b.gamma_mean, gamma_rms=b.gamma_rms,
+                    mean_x=b.mean[0], mean_y=b.mean[1], mean_z=b.mean[2], sigma_x=b.sigma[0],
+                    sigma_y=b.sigma[1], sigma_z=b.sigma[2], eps_x=b.emittance[0], eps_y=b.emittance[1])
 
     def set_slow_step(self, delta):
         """Zeta march: slow step of the following steps (config units)."""

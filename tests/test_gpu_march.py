@@ -124,3 +124,21 @@ def test_march_fp32_fields_against_fp64_oracle(cfg):
     g.step(4)
     err = rel_errors(_oracle_fields(o), g.fields(), floor=1e-3)
     assert max(err.values()) < 2e-4, err
+
+
+def test_march_nonuniform_grid_and_changing_delta():
+    """Sec. 7: h varying smoothly along zeta (a tanh ramp by 2.5 between the
+    rear and the front) and Delta changed between steps; FP64 bars as above."""
+    from test_oracle_march_grid import _smooth_nodes
+    cfg = _cfg3(0.5, zeta_nodes=list(_smooth_nodes(64, 64 * 0.05, 2.5)))
+    o = MarchSim(cfg)
+    g = Sim(cfg, track_ids=True)
+    err = rel_errors(_oracle_fields(o), g.fields())
+    assert max(err.values()) < 1e-12, err
+    for D in (0.5, 0.3, 0.8):
+        o.step(Delta=D)
+        g.set_slow_step(D)
+        dg = g.step(1, diag=True)
+        _compare(o, g)
+        assert dg["n_particles"] == len(o.P)
+        assert abs(dg["tau"] - o.s) < 1e-12 * o.s

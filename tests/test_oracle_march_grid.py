@@ -1,0 +1,140 @@
+"""Pins of the zeta march on a non-uniform fast grid and with a slow step that
+changes from step to step (Sec. 7: Delta may vary arbitrarily between
+levels; h may vary smoothly along zeta).
+
+* A transversally uniform (K = 0) pulse is frozen exactly on any node
+  distribution (the node system leaves R unchanged and L = 0 when K = 0 and
+  there is no current).
+* Discrete continuity to roundoff on a non-uniform grid, with Delta changed
+  between steps; the fresh batch of each step carries Q_f of that step's
+  Delta, and the slow coordinate is the sum of the steps.
+* A fresh plasma drifting at v deposits j = q n v / (1 - v_z) in every cell of
+  a non-uniform grid.
+* A diffracting vacuum pulse on smooth non-uniform grids converges at second
+  order to the continuum solution of the universal reduced system, each
+  (K, kappa) component turned by exp(-i Omega s) with
+  Omega = 2 kappa K^2 / (4 kappa^2 - K^2): the vacuum, K != 0 form of Sec.
+  4.2's omega = 2 kappa omega_p^2 / (4 kappa^2 - omega_p^2) (omega_p^2 -> K^2),
+  the limit h, Delta -> 0 of the scheme's per-mode relation (whose paraxial
+  limit K << kappa is K^2 / (2 kappa))."""
+import math
+
+import numpy as np
+
+import workloads
+from oracle.march import MarchSim, continuity_residual
+
+
+def _smooth_nodes(N, L, ratio=2.0):
+    """N + 1 nodes on [0, L]: h changes smoothly by `ratio` between the rear
+    and the front third (a tanh ramp), the paper's refined rear region."""
+    x = (np.arange(N) + 0.5) / N
+    hh = 1.0 + (ratio - 1.0) * 0.5 * (1.0 + np.tanh((x - 0.5) / 0.08))
+    z = np.r_[0.0, np.cumsum(hh)]
+    return z * (L / z[-1])
+
+
+def test_uniform_pulse_frozen_exactly_on_a_nonuniform_grid():
+    cfg = workloads.small3d(precision="fp64", n=(8, 8, 64), tile=(4, 4, 4), n_e=0.0)
+    L = 64 * 0.05
+    cfg.update(delta=2.0, waist=0.0, zeta_c=1.6, zeta_nodes=list(_smooth_nodes(64, L, 3.0)))
+    s = MarchSim(cfg)
+    R0 = s.state.Rx.copy()
+    assert np.abs(R0).max() > 0.1
+    s.run(3)
+    assert np.array_equal(s.state.Rx, R0)
+    assert not np.any(s.state.Lx) and not np.any(s.state.Ez)
+
+
+def test_continuity_with_nonuniform_grid_and_changing_delta():
+    cfg = workloads.small3d(precision="fp64", n=(16, 16, 64), tile=(8, 8, 4))
+    L = 64 * 0.05
+    cfg.update(delta=0.5, scheme=1, zeta_nodes=list(_smooth_nodes(64, L, 2.5)))
+    s = MarchSim(cfg, record=True)
+    s_sum = 0.0
+    for D in (0.5, 0.3, 0.8):
+        s.step(Delta=D)
+        s_sum += D * cfg["length_unit"]
+        r = continuity_residual(s.m, s.rho0, s.rho1, s.J, s.flux)
+        assert np.abs(r).max() < 1e-12 * np.abs(s.rho0).max() / s.m.Delta
+        # this step's fresh batch (one particle per transverse cell: the
+        # zeta march uses ppc[0] x ppc[1] = 1) carries Q_f of this Delta
+        fresh = s.P.pid >= s.next_pid - 16 * 16
+        w = np.r_[s.P.w[fresh], s.left.w[s.left.pid >= s.next_pid - 256]]
+        assert len(w) == 256
+        want = s.p.n_e * s.p.hx * s.p.hy * D * cfg["length_unit"]
+        assert np.max(np.abs(w - want)) < 1e-14 * want
+    assert abs(s.s - s_sum) < 1e-12 * s_sum
+
+
+def test_drifting_plasma_on_nonuniform_grid():
+    n_e = 0.01
+    cfg = workloads._base(dims=3, n=[4, 4, 32], d=[0.5, 0.5, 0.1], length_unit=1.0, precision="fp64",
+                          tile=[4, 4, 4], n_e=n_e, ppc=[1, 1, 1], load=1, a0=0.0, seed=7)
+    cfg.update(delta=100.0, scheme=1, zeta_nodes=list(_smooth_nodes(32, 3.2, 3.0)))
+    s = MarchSim(cfg, solver=False, record=True)
+    u0 = (0.3, 0.2, 0.4)
+    s.inject_u0 = u0
+    s.step()
+    g = math.sqrt(1 + sum(u * u for u in u0))
+    v = [u / g for u in u0]
+    for c in range(3):
+        want = -n_e * v[c] / (1.0 - v[2])
+        assert np.max(np.abs(s.J[c] - want)) < 1e-12 * abs(want), c
+
+
+def _refine(z):
+    """Insert the midpoint of every cell: h_n halves, the profile is kept."""
+    out = np.empty(2 * len(z) - 1)
+    out[0::2] = z
+    out[1::2] = 0.5 * (z[:-1] + z[1:])
+    return out
+
+
+def _vacuum_pulse_run(zn, steps, S=16.0, Lz=51.2):
+    """2-D vacuum pulse (broad waist, long pulse: no spectral content near
+    kappa = K / 2, where the zeta recursion's free solution makes the right
+    boundary matter) on the nodes zn after slow path S in `steps` steps."""
+    N = len(zn) - 1
+    T = 6.0
+    cfg = workloads._base(dims=2, n=[32, 1, N], d=[2.0, 1.0, Lz / N], length_unit=1.0, precision="fp64",
+                          tile=[4, 1, 4], n_e=0.0, a0=0.1, waist=8.0, fwhm=T * np.sqrt(2 * np.log(2)),
+                          zeta_c=Lz / 2, seed=1)
+    cfg.update(delta=S / steps, scheme=1, zeta_nodes=list(zn))
+    s = MarchSim(cfg).run(steps)
+    return s, np.real(np.fft.ifft(s.state.Rx[:, 0, :], axis=-1))
+
+
+def _continuum(s, S=16.0, Lz=51.2):
+    """R_x of the universal reduced system after S at the nodes of s."""
+    p = s.p
+    Nx, fine = p.Nx, 8192
+    zf = np.arange(fine) * (2 * Lz / fine) - Lz / 2
+    x = np.arange(Nx) * p.hx - (Nx // 2) * p.hx
+    ph = zf - p.zeta_c
+    R0 = 2 * (p.a0 * np.cos(ph) * np.exp(-ph ** 2 / p.T ** 2))[:, None] * np.exp(-x ** 2 / p.waist ** 2)[None, :]
+    kap = 2 * np.pi * np.fft.fftfreq(fine, d=2 * Lz / fine)[:, None]
+    K = 2 * np.pi * np.fft.fftfreq(Nx, d=p.hx)[None, :]
+    den = 4 * kap ** 2 - K ** 2
+    safe = np.abs(den) > 1e-9
+    Om = np.where(safe, 2 * kap * K ** 2 / np.where(safe, den, 1.0), 0.0)
+    F = np.fft.fft2(R0)
+    F[:, Nx // 2] = 0.0
+    Rs = np.real(np.fft.ifft2(F * np.exp(-1j * Om * S)))
+    return np.stack([np.interp(s.m.zn[:p.Nz], zf, Rs[:, i]) for i in range(Nx)], axis=1), R0
+
+
+def test_smooth_nonuniform_grid_converges_at_second_order():
+    z1 = _smooth_nodes(256, 51.2, 2.0)
+    z2 = _refine(z1)
+    z3 = _refine(z2)
+    _, R1 = _vacuum_pulse_run(z1, 8)
+    _, R2 = _vacuum_pulse_run(z2, 16)
+    s3, R3 = _vacuum_pulse_run(z3, 32)
+    d1 = np.linalg.norm(R1 - R2[0::2])
+    d2 = np.linalg.norm(R2[0::2] - R3[0::4])
+    assert 3.0 < d1 / d2 < 5.5, (d1, d2)
+    # and against the continuum (the pulse changed by a fifth of its norm):
+    # the scheme's error on the finest grid is below 1e-3 of it
+    want, _ = _continuum(s3)
+    assert np.linalg.norm(R3 - want) / np.linalg.norm(want) < 1e-3

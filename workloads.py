@@ -121,10 +121,39 @@ def small3d(precision="fp64", n=(32, 32, 64), tile=(8, 8, 8), ppc=(1, 1, 2),
                  fwhm=1.5, zeta_c=None, steps=steps, seed=seed)
 
 
+def lwfa_channel(nz=4096, delta=40.0, scheme=1, nodes=None):
+    """The paper's example (Sec. 6) scaled down to one GPU and without
+    ionisation: hydrogen plasma in a Gaussian channel, n_e = n_0 [1 + (n_1 -
+    n_0) / n_0 exp(-r^2 / R_ch^2)] with n_0 = 5e17 cm^-3 (2.9e-4 of the
+    critical density at 0.8 um), n_1 / n_0 = 0.25 on the axis, R_ch = 76.4 um
+    (95.5 lambda); laser a0 = 2, T = 50.9 fs in exp(-phi^2 / T^2) (19.1
+    lambda, intensity FWHM 22.5 lambda), R = 22.9 um (28.6 lambda); window
+    150 x 150 x 180 um (187.5 x 187.5 x 225 lambda) at h_x = h_y = 1.46
+    lambda (128 x 128) and h = 50 nm (0.0549 lambda, 4096 nodes); zeta march
+    with Delta = 32 um (40 lambda).  Lengths in lambda = 0.8 um.
+    nodes: optional zeta node positions (a refined rear, as the paper's
+    6.3 nm rear third)."""
+    cfg = _base(dims=3, n=[128, 128, nz], d=[187.5 / 128, 187.5 / 128, 225.0 / nz], precision="fp32",
+                tile=[8, 8, 4], n_e=2.9e-4, ppc=[1, 1, 1], a0=2.0, waist=28.6, fwhm=22.5,
+                zeta_c=225.0 - 40.0, steps=20)
+    cfg.update(scheme=scheme, delta=delta, ch_ratio=0.25, ch_radius=95.5)
+    if nodes is not None:
+        cfg["zeta_nodes"] = list(nodes)
+    return cfg
+
+
+def channel_small(precision="fp64", scheme=1, delta=0.5):
+    """A small 3-D zeta-march case with the Gaussian channel, for parity tests."""
+    cfg = small3d(precision=precision, n=(32, 32, 64), tile=(8, 8, 4))
+    cfg.update(scheme=scheme, delta=delta, ch_ratio=0.25, ch_radius=3.0)
+    return cfg
+
+
 CONFIGS = {
     "lwfa2d_fp64": lwfa2d_fp64,
     "lwfa3d_fp32": lwfa3d_fp32,
     "precision_study": precision_study,
     "pwfa3d_fp32": pwfa3d_fp32,
     "denoiser_lwfa": denoiser_lwfa,
+    "lwfa_channel": lwfa_channel,
 }
