@@ -10,16 +10,29 @@ sort + window injection, and the field update (FFT, march, inverse FFT).
 1e7-particle driver, plasma units).
 
 Prints one JSON line.  value = particle updates per second of the
-gather + push + deposit kernel (HIP events around its launches, on the stream
-the library runs on); ms_per_step = wall time per whole step over the timed
-region.  roofline = that kernel's algorithmic bytes (2 x 28 B particle state,
-24 B of fields and 12 B of current per cell) per launch over its average
-duration, against 8 TB/s.  cpu_baseline = the FP64 CPU oracle's gather + push
-+ deposit on a bounded crop of the same workload, timed on the host.
+gather + push + deposit kernel: particles over the median of its per-step
+durations (HIP events on the stream the library runs on); ms_per_step = wall
+time per whole step over the timed region.  roofline = that kernel's
+algorithmic bytes (2 x 28 B particle state, 24 B of fields and 12 B of current
+per cell) per launch over its median duration, against 8 TB/s.
+cpu_baseline = the FP64 CPU oracle's gather + push + deposit on bounded
+transverse crops of the same workload, on every host core (one crop per
+process) and on one core.
+
+Extra objects on the same line:
+  march   -- the paper's own slow step (the zeta march, GT1) on the same
+             physics at 1 particle per transverse cell per batch and
+             Delta = 8 lambda (320 times the tau scheme's dtau), its median
+             wall time per slow step and the time the tau scheme needs for the
+             same Delta; and the paper's example scaled down to one GPU
+             (Gaussian channel, 128 x 128 x 4096, Delta = 32 um).
+  denoise -- wall time per whole step at 1 ppc with the committed network
+             against 16 ppc without it (the same LWFA physics).
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -48,46 +61,143 @@ def algorithmic_bytes_per_update(ppc):
     return 2 * STATE_BYTES + (24.0 + 12.0) / ppc
 
 
-def cpu_baseline(workload="lwfa", seconds_budget=30.0):
-    """FP64 oracle gather + push + deposit on a transverse crop of the workload:
-    LWFA 32 x 32 x 512 cells (same steps, density, ppc; laser waist scaled to
-    the crop); PWFA 16 x 16 x 512 cells of its plasma (same steps, density,
-    ppc; the driver is left out: its 1e7 particles do not fit a crop)."""
-    import numpy as np
+def _oracle_crop(args):
+    """One process: FP64 oracle gather + push + deposit on a crop (seeded by
+    its index), `steps` steps or until `budget` seconds; returns (particle
+    updates, seconds)."""
+    workload, nx, index, steps, budget = args
     import workloads
     from oracle.sim import Simulation
     from oracle.push import push_and_move
     from oracle.deposit import deposit
-
     if workload == "pwfa":
         cfg = workloads.pwfa3d_fp32()
-        cfg["n"] = [16, 16, 512]
         cfg["beam"] = None
-        crop = "16x16x512 crop of the PWFA plasma (no driver)"
     else:
         cfg = workloads.lwfa3d_fp32()
-        cfg["n"] = [32, 32, 512]
-        cfg["waist"] = 2.0
-        crop = "32x32x512 crop of the workload"
+        cfg["waist"] = 2.0 * nx / 32
+    cfg["n"] = [nx, nx, 512]
     cfg["precision"] = "fp64"
+    cfg["seed"] = index
     s = Simulation(cfg)
     p = s.p
-    done = 0
-    t_used = 0.0
-    steps = 0
     P = s.P
-    while steps < 3 and t_used < seconds_budget:
+    done, used, k = 0, 0.0, 0
+    while k < steps and used < budget:
         t0 = time.perf_counter()
         old, st, vy = push_and_move(p, P, s.F)
         deposit(p, old, (P.ix, P.iy, P.iz, P.dx, P.dy, P.dz), st, vy)
-        t_used += time.perf_counter() - t0
+        used += time.perf_counter() - t0
         done += len(P)
-        steps += 1
+        k += 1
         P = P.take(P.iz >= 0)          # particles that left the box (untimed)
-    return {"value": done / t_used, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 numpy oracle, gather+push+deposit, {steps} steps of a "
-                      f"{crop} ({len(s.P)} particles), single thread",
-            "seconds": t_used}
+    return done, used, len(s.P)
+
+
+def cpu_baseline(workload="lwfa"):
+    """The FP64 oracle (as it stands) on every host core: one transverse crop
+    of 16 x 16 x 512 cells of the workload per process (same cell sizes,
+    density, ppc; the LWFA laser waist scaled to the crop; PWFA without the
+    driver, whose 1e7 particles do not fit a crop), 3 steps each; aggregate
+    updates over the slowest process's time.  Plus one process alone."""
+    import multiprocessing as mp
+    import platform
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ncpu = os.cpu_count() or 1
+    try:
+        ncpu = min(ncpu, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    nproc = max(1, min(ncpu, 16))
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    one_done, one_s, one_n = _oracle_crop((workload, 16, 0, 3, 20.0))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(nproc) as pool:
+        res = pool.map(_oracle_crop, [(workload, 16, i, 3, 20.0) for i in range(nproc)])
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    slowest = max(r[1] for r in res)
+    return {"value": done / slowest, "unit": "particle updates/s", "cores": nproc, "kind": "oracle",
+            "sample": f"FP64 numpy oracle, gather+push+deposit, 3 steps of {nproc} independent 16x16x512 "
+                      f"transverse crops of the workload ({res[0][2]} particles each), one process per "
+                      f"core (slowest process's compute time); wall {wall:.1f} s with start-up",
+            "single_thread": {"value": one_done / one_s, "cores": 1, "seconds": one_s},
+            "host_cpu": model, "os_cpu_count": os.cpu_count()}
+
+
+def median_step_phases(sim, steps):
+    """Per-step HIP-event phases (ms) of `steps` single steps."""
+    rows = []
+    for _ in range(steps):
+        sim.timing(True)
+        sim.step(1)
+        ph, n = sim.get_timing()
+        rows.append(ph)
+    return {k: statistics.median(r[k] for r in rows) for k in rows[0]}, rows
+
+
+def bench_march(stream, steps=5):
+    """The zeta march on the LWFA physics, and the paper's example scaled down."""
+    import workloads
+    from paper_2509_16793_amd.gempic import Sim
+    out = {}
+    cfg = workloads.lwfa3d_fp32(ppc=(1, 1, 1))
+    cfg.update(scheme=1, delta=8.0)
+    g = Sim(cfg, stream=stream)
+    g.step(1)
+    med, _ = median_step_phases(g, steps)
+    d = g.step(1, diag=True)
+    out["lwfa"] = {"workload": "lwfa3d physics (256x256x512, dx=dy=0.4, dzeta=0.05 lambda, n_e=0.001, a0=2), "
+                               "zeta march GT1, 1 particle per transverse cell per batch, Delta = 8 lambda",
+                   "ms_per_slow_step": med["step"], "delta_over_dtau": 8.0 / 0.025,
+                   "particles_in_box": d["n_particles"]}
+    g.close()
+    cfg = workloads.lwfa_channel()
+    g = Sim(cfg, stream=stream)
+    g.step(1)
+    med2, _ = median_step_phases(g, 3)
+    n_steps_paper = 31.8e-2 / 32e-6          # 31.8 cm at Delta = 32 um
+    out["paper_example"] = {
+        "workload": "Sec. 6 example scaled down: Gaussian channel n1/n0 = 0.25, R_ch 95.5 lambda, "
+                    "n0 = 2.9e-4 n_c, a0 = 2, 128x128x4096 cells over 187.5x187.5x225 lambda, "
+                    "zeta march GT1, Delta = 32 um (40 lambda)",
+        "ms_per_slow_step": med2["step"],
+        "hours_for_31.8_cm": med2["step"] * n_steps_paper / 3.6e6,
+        "paper_context": "GEM-PIC: 12 h on 432 Xeon E5-2697 v2 cores for 31.8 cm (150x150x180 um window, "
+                         "4+4 macro-atoms per cell, ionisation) -- other hardware and physics, not a target"}
+    g.close()
+    return out, med
+
+
+def bench_denoise(stream, steps=8):
+    """1 ppc + the committed network against 16 ppc on the LWFA physics."""
+    import numpy as np
+    import workloads
+    from paper_2509_16793_amd.gempic import Denoiser, Sim
+    theta = np.load(os.path.join(ROOT, "paper_2509_16793_amd", "weights", "denoiser_lwfa.npy"))
+    lo = Sim(workloads.denoiser_lwfa(ppc=(1, 1, 1)), stream=stream)
+    dn = Denoiser(theta, stream=stream)
+    lo.set_denoiser(dn, 1e-3)
+    lo.step(3)
+    t_lo, _ = median_step_phases(lo, steps)
+    lo.close()
+    hi = Sim(workloads.denoiser_lwfa(ppc=(2, 2, 4)), stream=stream)
+    hi.step(3)
+    t_hi, _ = median_step_phases(hi, steps)
+    hi.close()
+    return {"workload": "lwfa3d physics at 1 ppc + network (3->16->32->16->3 BF16 MFMA) against 16 ppc",
+            "ms_per_step_1ppc_net": t_lo["step"], "ms_per_step_16ppc": t_hi["step"],
+            "ratio": t_hi["step"] / t_lo["step"],
+            "accuracy": "on-axis E_z within 2 % of 16 ppc: see profiles/k_conv_denoiser_lwfa3d_256x256x512_1ppc.md"}
 
 
 def main():
@@ -96,6 +206,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the march and denoise objects")
     ap.add_argument("--workload", choices=("lwfa", "pwfa"), default="lwfa",
                     help="lwfa: 3-D LWFA 256x256x512 at 2 ppc (default); pwfa: 3-D PWFA "
                          "512x512x1024 at 4 ppc with a 1e7-particle driver")
@@ -133,13 +244,11 @@ def main():
     n0 = sim._count()
     print(f"[bench] warmup {args.warmup} steps done, {n0} particles", file=sys.stderr, flush=True)
 
-    sim.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    med, rows = median_step_phases(sim, args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ph, nt = sim.get_timing()
     n1 = sim._count()
     print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
 
@@ -148,9 +257,8 @@ def main():
     same_kernel = hashlib.sha256(src).hexdigest()[:16] == MEASURED_TRAFFIC["push_h_sha256_prefix"]
     traffic = MEASURED_TRAFFIC["bytes_per_launch"] if same_kernel and args.workload == "lwfa" else None
     n_avg = 0.5 * (n0 + n1)
-    push_s = ph["push_deposit"] / 1e3
-    value = n_avg * args.steps / push_s
-    launch_s = push_s / args.steps
+    launch_s = med["push_deposit"] / 1e3
+    value = n_avg / launch_s
     bpu = algorithmic_bytes_per_update(ppc)
     achieved = n_avg * bpu / launch_s / 1e9
     out = {
@@ -171,13 +279,22 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_push_deposit", "bytes_per_update": bpu,
-                     "avg_launch_ms": launch_s * 1e3},
-        "phase_ms_per_step": {k: v / args.steps for k, v in ph.items()},
-        "step_updates_per_s": n_avg * args.steps / (t1 - t0),
+                     "median_launch_ms": launch_s * 1e3,
+                     "mean_launch_ms": statistics.fmean(r["push_deposit"] for r in rows)},
+        "phase_ms_per_step": med,
+        "step_updates_per_s": n_avg / (med["step"] / 1e3),
     }
     sim.close()
+    if args.workload == "lwfa" and not args.no_extras:
+        print("[bench] zeta march", file=sys.stderr, flush=True)
+        m, _ = bench_march(stream)
+        m["lwfa"]["tau_ms_for_same_delta"] = med["step"] * m["lwfa"]["delta_over_dtau"]
+        m["lwfa"]["speedup_over_tau"] = m["lwfa"]["tau_ms_for_same_delta"] / m["lwfa"]["ms_per_slow_step"]
+        out["march"] = m
+        print("[bench] denoiser", file=sys.stderr, flush=True)
+        out["denoise"] = bench_denoise(stream)
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a crop", file=sys.stderr, flush=True)
+        print("[bench] timing the CPU oracle on crops", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
