@@ -86,6 +86,11 @@ template <> struct Fix<double> {
   static GP_DEV double value(double v) { return v; }
 };
 
+// value of lane - 1 (row_shr:1) / lane + 1 (row_shl:1) within a 16-lane DPP
+// row; 0 at the row's edge
+GP_DEV int dpp_from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true); }
+GP_DEV int dpp_from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x101, 0xf, 0xf, true); }
+
 // 3-node window starting at min(c0, c0 + k): old and new linear weights.
 template <typename T>
 GP_DEV void window3(int k, T d0, T d1, T* S0, T* S1) {
@@ -530,23 +535,58 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
               add(&sJx[(cc * JY + b) * JX + 0], px0 * (S0y[b] * Az[cc] + DSy[b] * Bz[cc]));
-#pragma unroll
-          for (int aa = 0; aa < 2; ++aa)
+          if constexpr (std::is_same<T, float>::value) {
+            // A wave is usually one zeta sub-row of the tile's columns, so the
+            // window of lane l starts one node right of lane l - 1's: the node
+            // they share gets lane l - 1's second value added to lane l's
+            // first (as integers: exact), moved by a DPP shift, and one atomic
+            // instead of two.  Both lanes test the same address relation, so
+            // each value is added exactly once whatever the layout.
+            const int key = (jz0 * JY + jy0) * JX + jx0 + 2;   // never 0 or 1
+            const bool take = dpp_from_left(key) + 1 == key;
+            const bool give = key + 1 == dpp_from_right(key);
+            auto add2 = [&](A* p0, T v0, T v1) {
+              const int i1 = (int)v1;             // Fix<float>::to without the widening
+              const int r = dpp_from_left(i1);
+              long long i0 = (int)v0;
+              if (take) i0 += r;                  // two int32 terms: no overflow in 64 bits
+              atomicAdd(p0, (A)i0);
+              if (!give) atomicAdd(p0 + 1, (A)(long long)i1);
+            };
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
-              add(&sJy[(cc * JY + 0) * JX + aa], py0 * (S0x[aa] * Az[cc] + DSx[aa] * Bz[cc]));
-#pragma unroll
-          for (int aa = 0; aa < 2; ++aa)
+              add2(&sJy[(cc * JY + 0) * JX + 0], py0 * (S0x[0] * Az[cc] + DSx[0] * Bz[cc]),
+                   py0 * (S0x[1] * Az[cc] + DSx[1] * Bz[cc]));
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-              T Fz = S0x[aa] * Cy[b] + DSx[aa] * Dy[b];
-              T t0 = qr * (S0x[aa] * S0y[b]), t1 = qr * (S1x[aa] * S1y[b]);
-              A* pz = &sJz[b * JX + aa];
-              add(pz + 0 * JY * JX, t0 * s0e[0] + t1 * s1e[0]);
-              add(pz + 1 * JY * JX, t0 * s0e[1] + t1 * s1e[1] + pz0 * Fz);
-              add(pz + 2 * JY * JX, t0 * s0e[2] + t1 * s1e[2] + pz1 * Fz);
-              add(pz + 3 * JY * JX, t0 * s0e[3] + t1 * s1e[3]);
+              T Fz0 = S0x[0] * Cy[b] + DSx[0] * Dy[b], Fz1 = S0x[1] * Cy[b] + DSx[1] * Dy[b];
+              T t00 = qr * (S0x[0] * S0y[b]), t10 = qr * (S1x[0] * S1y[b]);
+              T t01 = qr * (S0x[1] * S0y[b]), t11 = qr * (S1x[1] * S1y[b]);
+              A* pz = &sJz[b * JX + 0];
+              add2(pz + 0 * JY * JX, t00 * s0e[0] + t10 * s1e[0], t01 * s0e[0] + t11 * s1e[0]);
+              add2(pz + 1 * JY * JX, t00 * s0e[1] + t10 * s1e[1] + pz0 * Fz0, t01 * s0e[1] + t11 * s1e[1] + pz0 * Fz1);
+              add2(pz + 2 * JY * JX, t00 * s0e[2] + t10 * s1e[2] + pz1 * Fz0, t01 * s0e[2] + t11 * s1e[2] + pz1 * Fz1);
+              add2(pz + 3 * JY * JX, t00 * s0e[3] + t10 * s1e[3], t01 * s0e[3] + t11 * s1e[3]);
             }
+          } else {
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+              for (int cc = 0; cc < 3; ++cc)
+                add(&sJy[(cc * JY + 0) * JX + aa], py0 * (S0x[aa] * Az[cc] + DSx[aa] * Bz[cc]));
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                T Fz = S0x[aa] * Cy[b] + DSx[aa] * Dy[b];
+                T t0 = qr * (S0x[aa] * S0y[b]), t1 = qr * (S1x[aa] * S1y[b]);
+                A* pz = &sJz[b * JX + aa];
+                add(pz + 0 * JY * JX, t0 * s0e[0] + t1 * s1e[0]);
+                add(pz + 1 * JY * JX, t0 * s0e[1] + t1 * s1e[1] + pz0 * Fz);
+                add(pz + 2 * JY * JX, t0 * s0e[2] + t1 * s1e[2] + pz1 * Fz);
+                add(pz + 3 * JY * JX, t0 * s0e[3] + t1 * s1e[3]);
+              }
+          }
         }
       } else {
         // 2-D (x, zeta): W_x, out-of-plane J_y = q w v_y x time-averaged shape, J_z
