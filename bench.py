@@ -134,6 +134,46 @@ def cpu_baseline(workload="lwfa"):
             "host_cpu": model, "os_cpu_count": os.cpu_count()}
 
 
+def _oracle_march_crop(args):
+    """One process: the FP64 oracle's zeta march (GT1, Delta = 8 lambda) on an
+    nx x nx x 512 crop of the LWFA physics (laser waist scaled to the crop),
+    one untimed slow step after creation, then one timed; returns (transverse
+    column slow steps, seconds, particles)."""
+    nx, index = args
+    import workloads
+    from oracle.march import MarchSim
+    cfg = workloads.lwfa3d_fp32(ppc=(1, 1, 1))
+    cfg.update(scheme=1, delta=8.0, n=[nx, nx, 512], precision="fp64", waist=2.0 * nx / 32, seed=index)
+    s = MarchSim(cfg)
+    s.step()
+    t0 = time.perf_counter()
+    s.step()
+    return nx * nx, time.perf_counter() - t0, len(s.P)
+
+
+def cpu_baseline_march(nx=32):
+    """The oracle's zeta march on every host core (<= 16 processes), one
+    nx x nx x 512 crop per process; aggregate column slow steps over the
+    slowest process's time."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    try:
+        ncpu = min(ncpu, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    nproc = max(1, min(ncpu, 16))
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    with mp.get_context("spawn").Pool(nproc) as pool:
+        res = pool.map(_oracle_march_crop, [(nx, i) for i in range(nproc)])
+    cols = sum(r[0] for r in res)
+    slowest = max(r[1] for r in res)
+    return {"value": cols / slowest, "unit": "transverse-column slow steps/s", "cores": nproc, "kind": "oracle",
+            "sample": f"FP64 numpy oracle zeta march (GT1, Delta = 8 lambda), one slow step of {nproc} "
+                      f"independent {nx}x{nx}x512 crops of the LWFA physics ({res[0][2]} particles each), "
+                      f"one process per core (slowest process's time)"}
+
+
 def median_step_phases(sim, steps):
     """Per-step HIP-event phases (ms) of `steps` single steps."""
     rows = []
@@ -145,7 +185,7 @@ def median_step_phases(sim, steps):
     return {k: statistics.median(r[k] for r in rows) for k in rows[0]}, rows
 
 
-def bench_march(stream, steps=5):
+def bench_march(stream, steps=5, cpu=True):
     """The zeta march on the LWFA physics, and the paper's example scaled down."""
     import workloads
     from paper_2509_16793_amd.gempic import Sim
@@ -156,11 +196,21 @@ def bench_march(stream, steps=5):
     g.step(1)
     med, _ = median_step_phases(g, steps)
     d = g.step(1, diag=True)
+    nz, ncol = cfg["n"][2], cfg["n"][0] * cfg["n"][1]
+    # in a zeta-march step the second timing phase is the stage loop (stage
+    # kernel, per-plane transforms, node solve), the third the parking sort
     out["lwfa"] = {"workload": "lwfa3d physics (256x256x512, dx=dy=0.4, dzeta=0.05 lambda, n_e=0.001, a0=2), "
                                "zeta march GT1, 1 particle per transverse cell per batch, Delta = 8 lambda",
-                   "ms_per_slow_step": med["step"], "delta_over_dtau": 8.0 / 0.025,
-                   "particles_in_box": d["n_particles"]}
+                   "ms_per_slow_step": med["step"], "value": ncol / (med["step"] / 1e3),
+                   "unit": "transverse-column slow steps/s",
+                   "us_per_stage": med["push_deposit"] * 1e3 / nz, "ms_parking_sort": med["sort_window"],
+                   "delta_over_dtau": 8.0 / 0.025, "particles_in_box": d["n_particles"]}
     g.close()
+    if cpu:
+        print("[bench] timing the CPU oracle's zeta march on crops", file=sys.stderr, flush=True)
+        cb = cpu_baseline_march()
+        out["lwfa"]["cpu_baseline"] = cb
+        out["lwfa"]["gpu_over_cpu"] = out["lwfa"]["value"] / cb["value"]
     cfg = workloads.lwfa_channel()
     g = Sim(cfg, stream=stream)
     g.step(1)
@@ -207,6 +257,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the march and denoise objects")
+    ap.add_argument("--march-only", action="store_true",
+                    help="only the zeta-march object (no CPU oracle), for profiling")
     ap.add_argument("--workload", choices=("lwfa", "pwfa"), default="lwfa",
                     help="lwfa: 3-D LWFA 256x256x512 at 2 ppc (default); pwfa: 3-D PWFA "
                          "512x512x1024 at 4 ppc with a 1e7-particle driver")
@@ -235,6 +287,10 @@ def main():
     torch.cuda.init()
     dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream(dev).cuda_stream
+    if args.march_only:
+        m, _ = bench_march(stream, cpu=False)
+        print(json.dumps({"march": m}), flush=True)
+        return
     cfg = workloads.pwfa3d_fp32() if args.workload == "pwfa" else workloads.lwfa3d_fp32()
     ppc = cfg["ppc"][0] * cfg["ppc"][1] * cfg["ppc"][2]
     sim = Sim(cfg, stream=stream)
@@ -287,7 +343,7 @@ def main():
     sim.close()
     if args.workload == "lwfa" and not args.no_extras:
         print("[bench] zeta march", file=sys.stderr, flush=True)
-        m, _ = bench_march(stream)
+        m, _ = bench_march(stream, cpu=not args.no_cpu_baseline)
         m["lwfa"]["tau_ms_for_same_delta"] = med["step"] * m["lwfa"]["delta_over_dtau"]
         m["lwfa"]["speedup_over_tau"] = m["lwfa"]["tau_ms_for_same_delta"] / m["lwfa"]["ms_per_slow_step"]
         out["march"] = m

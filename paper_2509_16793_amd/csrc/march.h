@@ -103,19 +103,35 @@ GP_DEV void mz_gather(const MzStageArgs<T>& a, int ix, int iy, T dx, T dy, T t, 
   const int ys[2] = {iy, DIM == 3 ? (iy + 1 == g.Ny ? 0 : iy + 1) : iy};
   const T wx[2] = {(T)1 - dx, dx};
   const T wy[2] = {(T)1 - dy, dy};
+  constexpr int NB = DIM == 3 ? 2 : 1;
+  // every record of both levels is loaded before any is used, so that the
+  // loads are in flight together; at the top cell the new-level node is the
+  // ghost node (zero fields): its loads read node n instead (in bounds) and
+  // the values are replaced by zero
+  const int64_t up = top ? 0 : (int64_t)g.Ny * g.Nx * 6;
+  T v0[NB][2][6], v1[NB][2][6];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
+      const int64_t r0 = (((int64_t)n * g.Ny + ys[b]) * g.Nx + xs[aa]) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        v0[b][aa][c] = a.F0[r0 + c];
+        v1[b][aa][c] = a.F1[r0 + up + c];
+      }
+    }
 #pragma unroll
   for (int c = 0; c < 6; ++c) f[c] = (T)0;
 #pragma unroll
-  for (int b = 0; b < (DIM == 3 ? 2 : 1); ++b) {
+  for (int b = 0; b < NB; ++b) {
 #pragma unroll
     for (int aa = 0; aa < 2; ++aa) {
       const T w = DIM == 3 ? wx[aa] * wy[b] : wx[aa];
-      const int64_t r0 = (((int64_t)n * g.Ny + ys[b]) * g.Nx + xs[aa]) * 6;
-      const int64_t r1 = r0 + (int64_t)g.Ny * g.Nx * 6;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        T v1 = top ? (T)0 : a.F1[r1 + c];
-        f[c] = f[c] + w * (((T)1 - t) * a.F0[r0 + c] + t * v1);
+        const T u1 = top ? (T)0 : v1[b][aa][c];
+        f[c] = f[c] + w * (((T)1 - t) * v0[b][aa][c] + t * u1);
       }
     }
   }
@@ -138,6 +154,13 @@ GP_DEV void mz_window(int k, T d0, T d1, T S0[3], T S1[3]) {
     S0[i] = (i == o0 ? (T)1 - d0 : (T)0) + (i == o0 + 1 ? d0 : (T)0);
     S1[i] = (i == o1 ? (T)1 - d1 : (T)0) + (i == o1 + 1 ? d1 : (T)0);
   }
+}
+
+// a current contribution; exact zeros (the third window node of a sub-step
+// that crosses no transverse cell face) issue no atomic
+template <typename T>
+GP_DEV void mz_add(T* p, T v) {
+  if (v != (T)0) atomicAdd(p, v);
 }
 
 // currents of one sub-step inside cell n (Qw = q w)
@@ -177,13 +200,16 @@ GP_DEV void mz_deposit(const MzStageArgs<T>& a, T Qw, int ix0, int iy0, T dx0, T
     }
     const T cx = -Qw / ((D * a.hy) * hn);
     const T cy = -Qw / ((D * a.hx) * hn);
+    // without a crossing in x (y) the second face's sum DS[0] + DS[1]
+    // vanishes (the window's third node has no weight): it is left out
+    // rather than deposited as a rounding residue
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       T acc = (T)0;
 #pragma unroll
       for (int aa = 0; aa < 2; ++aa) {
         acc = acc + DSx[aa] * (S0y[b] + (T)0.5 * DSy[b]);
-        atomicAdd(Jx + (int64_t)ys[b] * g.Nx + xs[aa], cx * acc);
+        if (aa == 0 || kx != 0) mz_add(Jx + (int64_t)ys[b] * g.Nx + xs[aa], cx * acc);
       }
     }
 #pragma unroll
@@ -192,7 +218,7 @@ GP_DEV void mz_deposit(const MzStageArgs<T>& a, T Qw, int ix0, int iy0, T dx0, T
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         acc = acc + DSy[b] * (S0x[aa] + (T)0.5 * DSx[aa]);
-        atomicAdd(Jy + (int64_t)ys[b] * g.Nx + xs[aa], cy * acc);
+        if (b == 0 || ky != 0) mz_add(Jy + (int64_t)ys[b] * g.Nx + xs[aa], cy * acc);
       }
     }
 #pragma unroll
@@ -200,7 +226,7 @@ GP_DEV void mz_deposit(const MzStageArgs<T>& a, T Qw, int ix0, int iy0, T dx0, T
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         T w = (S0x[aa] * S0y[b] + (T)0.5 * (DSx[aa] * S0y[b] + S0x[aa] * DSy[b])) + DSx[aa] * DSy[b] / (T)3;
-        atomicAdd(Jz + (int64_t)ys[b] * g.Nx + xs[aa], tz * w);
+        mz_add(Jz + (int64_t)ys[b] * g.Nx + xs[aa], tz * w);
       }
     }
   } else {
@@ -209,14 +235,14 @@ GP_DEV void mz_deposit(const MzStageArgs<T>& a, T Qw, int ix0, int iy0, T dx0, T
 #pragma unroll
     for (int aa = 0; aa < 2; ++aa) {
       acc = acc + DSx[aa];
-      atomicAdd(Jx + xs[aa], cx * acc);
+      if (aa == 0 || kx != 0) mz_add(Jx + xs[aa], cx * acc);
     }
     const T ty = Qw * dy_len / (D * V);
 #pragma unroll
     for (int aa = 0; aa < 3; ++aa) {
       T w = S0x[aa] + (T)0.5 * DSx[aa];
-      atomicAdd(Jy + xs[aa], ty * w);
-      atomicAdd(Jz + xs[aa], tz * w);
+      mz_add(Jy + xs[aa], ty * w);
+      mz_add(Jz + xs[aa], tz * w);
     }
   }
 }

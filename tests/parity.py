@@ -57,6 +57,21 @@ def rel_errors(ref, got, floor=1e-6):
     return out
 
 
+def check_fp32_fields(ref, got, rel=2e-4, ulps=30):
+    """FP32 fields against the FP64 oracle, every component against its own
+    norm: relative L2 error at most max(rel, ulps 2^-24 |largest| / |own|).
+    FP32 roundoff of the largest fields leaves an error of a few units of
+    2^-24 of them in every component, which is a large fraction of a
+    component 1e-3 of the largest (observed: 2 to 3 units); the bar allows
+    ten times that and no more."""
+    norms = {k: np.linalg.norm(np.asarray(ref[k], np.float64)) for k in ref}
+    big = max(norms.values())
+    for k in ref:
+        d = np.linalg.norm(np.asarray(got[k], np.float64) - np.asarray(ref[k], np.float64))
+        bar = max(rel * norms[k], ulps * 2.0 ** -24 * big)
+        assert d <= bar, (k, d / max(norms[k], 1e-300), bar / max(norms[k], 1e-300))
+
+
 def oracle_fields(o):
     return {nm: o.F[c, :o.p.Nz] for c, nm in enumerate(FIELDS)}
 

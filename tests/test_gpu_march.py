@@ -8,7 +8,8 @@ particle (matched by id) in the same cell, offsets and momenta within 1e-9,
 weights within 1e-14 relative and budgets within 1e-9 of Delta; the same
 numbers of particles parked and gone.  The GPU sums a cell's currents with
 FP64 atomics in arrival order, so both sides agree to roundoff, not bit for
-bit.  FP32 (cell + offset) against the FP64 oracle: fields within 2e-4.
+bit.  FP32 (cell + offset) against the FP64 oracle: every field component
+within 2e-4 of its own norm or 30 units of 2^-24 of the largest component.
 Cases: GT1 with particles parked in the box (Delta < L) and streaming through
 it (Delta > L), GT2, 2-D, a quiet plasma at rest (exactly zero current), and
 vacuum."""
@@ -18,7 +19,7 @@ import pytest
 import workloads
 from oracle.march import MarchSim
 from paper_2509_16793_amd.gempic import Sim
-from parity import rel_errors
+from parity import check_fp32_fields, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -122,8 +123,7 @@ def test_march_fp32_fields_against_fp64_oracle(cfg):
     o = MarchSim(c64).run(4)
     g = Sim(cfg)
     g.step(4)
-    err = rel_errors(_oracle_fields(o), g.fields(), floor=1e-3)
-    assert max(err.values()) < 2e-4, err
+    check_fp32_fields(_oracle_fields(o), g.fields())
 
 
 def test_march_nonuniform_grid_and_changing_delta():

@@ -12,7 +12,7 @@ import pytest
 import workloads
 from oracle.sim import Simulation
 from paper_2509_16793_amd.gempic import BEAM_BIT, Sim
-from parity import oracle_particles, rel_errors, oracle_fields, oracle_currents
+from parity import check_fp32_fields, oracle_particles, rel_errors, oracle_fields, oracle_currents
 
 pytestmark = pytest.mark.gpu
 
@@ -68,8 +68,7 @@ def test_pwfa_fp32_steps():
     o = Simulation(workloads.pwfa_small()).run(8)
     g = Sim(workloads.pwfa_small("fp32"))
     g.step(8)
-    # B_z is ~1e-3 of the transverse fields here: FP32 roundoff of the large
-    # fields (~1e-7 of them) is ~1e-4 of it, so components below 1e-3 of the
-    # largest are measured against the largest
-    err = rel_errors(oracle_fields(o), g.fields(), floor=1e-3)
-    assert max(err.values()) < 2e-4, err
+    # B_z is ~6e-4 of the transverse fields here, so FP32 roundoff of the
+    # large fields is ~2e-4 of it: every component within 2e-4 of its own
+    # norm or 30 units of 2^-24 of the largest (B_z: 0.3 %)
+    check_fp32_fields(oracle_fields(o), g.fields())
