@@ -23,9 +23,10 @@ Extra objects on the same line:
   march   -- the paper's own slow step (the zeta march, GT1) on the same
              physics at 1 particle per transverse cell per batch and
              Delta = 8 lambda (320 times the tau scheme's dtau), its median
-             wall time per slow step and the time the tau scheme needs for the
-             same Delta; and the paper's example scaled down to one GPU
-             (Gaussian channel, 128 x 128 x 4096, Delta = 32 um).
+             wall time per slow step, the time the tau scheme needs for the
+             same Delta, and the oracle's march on crops beside it; and the
+             paper's example scaled down to one GPU (Gaussian channel,
+             128 x 128 x 4096, Delta = 32 um, GT2).
   denoise -- wall time per whole step at 1 ppc with the committed network
              against 16 ppc without it (the same LWFA physics).
 """
@@ -219,7 +220,7 @@ def bench_march(stream, steps=5, cpu=True):
     out["paper_example"] = {
         "workload": "Sec. 6 example scaled down: Gaussian channel n1/n0 = 0.25, R_ch 95.5 lambda, "
                     "n0 = 2.9e-4 n_c, a0 = 2, 128x128x4096 cells over 187.5x187.5x225 lambda, "
-                    "zeta march GT1, Delta = 32 um (40 lambda)",
+                    "zeta march GT2, Delta = 32 um (40 lambda)",
         "ms_per_slow_step": med2["step"],
         "hours_for_31.8_cm": med2["step"] * n_steps_paper / 3.6e6,
         "paper_context": "GEM-PIC: 12 h on 432 Xeon E5-2697 v2 cores for 31.8 cm (150x150x180 um window, "

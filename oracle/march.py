@@ -25,9 +25,14 @@ Readings (where the paper is silent; the HIP path takes the same ones):
       node exactly); a sub-step limited by the remaining slow budget, or by
       the transverse limit M4, is parametrised by lab time (= s in GT1).
   M2  Fields inside cell n (between nodes n and n + 1): linear in zeta
-      between node n + 1 at the new level (already solved) and node n at the
-      old level (the new one is not known yet); linear (cloud-in-cell) in x
-      and y.
+      between node n + 1 and node n at the new level, linear (cloud-in-cell)
+      in x and y.  Node n at the new level depends on the currents of cell n,
+      so each stage is a predictor-corrector pair (Sec. 4.1 names a
+      predictor-corrector procedure): the predictor pushes the cell's
+      particles with node n at the old level, deposits and solves node n;
+      the corrector pushes them again, from their state at the start of the
+      stage, with the predicted node n, deposits and solves node n again.
+      Only the corrector's particles and currents are kept.
   M3  Predictor: j^1 on half-node n - 1/2 (needed by RxN, RyN at node n) is
       the previous step's j^0 there.  In the first step after creation there
       is no j^0: both levels and the predictor use the current j^1 of
@@ -199,8 +204,8 @@ def transverse_advance(i, d, shift, N):
 
 def gather(m, F0, F1, n, ix, iy, dx, dy, t):
     """E and B (each (3, N)) at transverse (ix + dx, iy + dy) and fraction t
-    of cell n: linear between node n of F0 (old level) and node n + 1 of F1
-    (new level) (M2), cloud-in-cell across."""
+    of cell n: linear between node n of F0 and node n + 1 of F1 (M2),
+    cloud-in-cell across."""
     p = m.p
     out = np.zeros((6, len(ix)))
     xs = (ix, (ix + 1) % p.Nx)
@@ -311,10 +316,11 @@ class MarchSim:
         self.trace = None                    # list: (n, particles on node n) per stage (pins)
 
     # ---- particle sub-steps inside cell n --------------------------------
-    def _stage_particles(self, n, A, F1, dep, flux):
+    def _stage_particles(self, n, A, F1, dep, flux, Flow=None):
         """Push the particles A of cell n (M1 .. M8); returns (those that
         reached node n with budget left, those that stopped or left)."""
         m, p = self.m, self.p
+        Flow = self.F0 if Flow is None else Flow    # node n (M2)
         q = p.q
         hn = m.hz[n]
         ds_perp = 0.5 * (min(p.hx, p.hy) if p.dims == 3 else p.hx)
@@ -334,7 +340,7 @@ class MarchSim:
             # small rest, GT2: of either sign, is carried to the next step)
             blim = ~zstep & (t_budget <= ds_perp)
             # midpoint
-            E, B = gather(m, self.F0, F1, n, W.ix, W.iy, W.dx, W.dy, W.dz)
+            E, B = gather(m, Flow, F1, n, W.ix, W.iy, W.dx, W.dy, W.dz)
             Fx, Fy, Fz = force(E, B, vx, vy, vz, q)
             h1 = np.where(zstep, 0.5 * dist / omv, 0.5 * dt)
             uxm, uym, uzm = W.ux + h1 * Fx, W.uy + h1 * Fy, W.uz + h1 * Fz
@@ -345,7 +351,7 @@ class MarchSim:
                 iym, dym = W.iy, W.dy
             tm = np.where(zstep, 0.5 * W.dz, np.clip(W.dz - h1 * omv / hn, 0.0, 1.0))
             gm, vxm, vym, vzm, omvm = velocity(uxm, uym, uzm)
-            Em, Bm = gather(m, self.F0, F1, n, ixm, iym, dxm, dym, tm)
+            Em, Bm = gather(m, Flow, F1, n, ixm, iym, dxm, dym, tm)
             Fxm, Fym, Fzm = force(Em, Bm, vxm, vym, vzm, q)
             ds = np.where(zstep, dist / omvm, dt)
             ux1, uy1, uz1 = W.ux + ds * Fxm, W.uy + ds * Fym, W.uz + ds * Fzm
@@ -429,8 +435,24 @@ class MarchSim:
         for n in range(p.Nz - 1, -1, -1):
             A = MP.concat(active, P.take(P.iz == n))
             dep = Deposit(m)
+            Flow = None
+            if self.solver and len(A):
+                # predictor (M2): node n at the old level, then node n solved
+                # with the currents of that push
+                dp = Deposit(m)
+                self._stage_particles(n, A, F1, dp, None)
+                jq = solver_currents(m, dp.Jx, dp.Jy, dp.Jz, KX, KY, nyq)
+                if first:
+                    qp0 = qm0 = jq[:2]
+                else:
+                    qp0 = (self.j0[0][n + 1], self.j0[1][n + 1])
+                    qm0 = (self.j0[0][n], self.j0[1][n])
+                old = [getattr(self.state, nm)[n] for nm in ("Rx", "Ry", "Ez", "Bz")]
+                pred = solve_node(m, n, D, old, right, qm0, qm0, qp0, jq, KX, KY, nyq)
+                Flow = self.F0.copy()
+                Flow[:, n] = node_real_fields(pred)
             if len(A):
-                active, st, lf = self._stage_particles(n, A, F1, dep, flux)
+                active, st, lf = self._stage_particles(n, A, F1, dep, flux, Flow)
                 stopped.append(st)
                 left.append(lf)
                 if self.trace is not None:

@@ -878,7 +878,7 @@ struct Impl {
   }
 
   template <int DIM>
-  static void mz_stage(gempic* g, int n, T D) {
+  static void mz_stage(gempic* g, int n, T D, bool pred) {
     const Geom& G = g->g;
     MzStageArgs<T> a;
     a.g = G;
@@ -889,9 +889,12 @@ struct Impl {
     a.D = D;
     a.ds_perp = (T)(0.5 * (G.dims == 3 ? std::min(G.hx, G.hy) : G.hx));
     a.scheme = g->scheme;
+    a.pred = pred ? 1 : 0;
     a.cap = g->mz_subcap;
     a.capacity = g->mz_cap;
-    a.F0 = (const T*)g->F6;
+    // node n: the old level in the predictor, the predicted new level in the
+    // corrector (without plasma there is no predictor and no particle)
+    a.F0 = (const T*)(pred || g->nperp == 0 ? g->F6 : g->F6b);
     a.F1 = (const T*)g->F6b;
     a.dep = (T*)g->mz_dep;
     a.in = mzp(g, MZ_ACT + (n & 1));
@@ -934,19 +937,29 @@ struct Impl {
       out6[q] = (C*)g->mz_out6 + q * M;
       in6[q] = out6[q];
     }
+    // predictor-corrector stages: with plasma, each stage first pushes and
+    // deposits with node n at the old level and solves node n (records
+    // only), then pushes again with that node and solves for good
+    const int passes = g->nperp > 0 ? 2 : 1;
     for (int n = Nz - 1; n >= 0; --n) {
-      if (G.dims == 3) mz_stage<3>(g, n, D);
-      else mz_stage<2>(g, n, D);
-      fft_fwd(g, (const T*)g->mz_dep, (C*)g->mz_jhat, 3);
-      MzNodeArgs<T> a = mz_node_args(g, n, D);
-      a.jhat = (const C*)g->mz_jhat;
-      for (int q = 0; q < 6; ++q) a.out[q] = out6[q];
-      a.dep = (T*)g->mz_dep;
-      for (int q = 0; q < 3; ++q) a.jrec[q] = (T*)g->J[q] + (int64_t)(n + 2) * nxy;
-      a.zero_count = g->mz_cnt + C_ACT + (n & 1);
-      k_mz_node<T><<<nblk(std::max<int64_t>(M, 3 * nxy / 8), 256), 256, 0, g->s>>>(a);
-      if (G.Ny > 1) fft_y(g, out6[0], 6, 1);
-      c2r6(g, in6, (T*)g->F6b + (int64_t)n * nxy * 6, G.Ny);
+      for (int pass = 2 - passes; pass < 2; ++pass) {
+        const bool pred = pass == 0;
+        if (G.dims == 3) mz_stage<3>(g, n, D, pred);
+        else mz_stage<2>(g, n, D, pred);
+        fft_fwd(g, (const T*)g->mz_dep, (C*)g->mz_jhat, 3);
+        MzNodeArgs<T> a = mz_node_args(g, n, D);
+        a.jhat = (const C*)g->mz_jhat;
+        for (int q = 0; q < 6; ++q) a.out[q] = out6[q];
+        a.dep = (T*)g->mz_dep;
+        a.pred = pred ? 1 : 0;
+        if (!pred) {
+          for (int q = 0; q < 3; ++q) a.jrec[q] = (T*)g->J[q] + (int64_t)(n + 2) * nxy;
+          a.zero_count = g->mz_cnt + C_ACT + (n & 1);
+        }
+        k_mz_node<T><<<nblk(std::max<int64_t>(M, 3 * nxy / 8), 256), 256, 0, g->s>>>(a);
+        if (G.Ny > 1) fft_y(g, out6[0], 6, 1);
+        c2r6(g, in6, (T*)g->F6b + (int64_t)n * nxy * 6, G.Ny);
+      }
     }
     if ((rc = launch_check(g, "zeta-march stages"))) return rc;
     if ((rc = mark(g, 2))) return rc;

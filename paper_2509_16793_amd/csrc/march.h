@@ -17,8 +17,13 @@
 //   3. k_mz_node solves node n for every transverse mode (App. B closed form
 //      with the currents of both slow levels);
 //   4. the node's six field spectra are transformed back into node records.
-// Fields inside cell n are linear in zeta between node n + 1 (new level) and
-// node n (old level); cloud-in-cell across.  A sub-step that reaches the
+// Fields inside cell n are linear in zeta between nodes n + 1 and n at the
+// new level; cloud-in-cell across.  Node n at the new level depends on the
+// cell's own currents, so a stage runs 1-4 twice: the predictor pushes the
+// particles with node n at the old level and only deposits (no particle is
+// written), and its node solve writes only the node's records; the
+// corrector pushes them again, from the same start, with the predicted node
+// n and is kept.  A sub-step that reaches the
 // node is parametrised by zeta and ends on it; a sub-step limited by the
 // budget or by the transverse limit (half a cell) is parametrised by lab
 // time and ends on the node if it would pass it.  GT1 spends budget at rate
@@ -51,9 +56,11 @@ struct MzStageArgs {
   T D;                 // slow step Delta
   T ds_perp;           // transverse sub-step limit min(hx, hy) / 2
   int scheme;          // 1 = GT1, 2 = GT2
+  int pred;            // predictor pass: deposit only, no particle written
   int cap;             // sub-steps per particle and stage (hang guard)
   int capacity;        // of each particle buffer
-  const T* F0;         // old-level node records [Nz][Ny][Nx][6]
+  const T* F0;         // records [Nz][Ny][Nx][6] giving node n: the old level
+                       // (predictor) or the predicted new level (corrector)
   const T* F1;         // new-level node records (node n + 1 already written)
   T* dep;              // [3][Ny][Nx] currents of cell n
   MzParts<T> in;       // particles that reached node n + 1 in stage n + 1
@@ -387,6 +394,7 @@ __global__ __launch_bounds__(256) void k_mz_stage(MzStageArgs<T> a) {
         status = 2;
       }
     }
+    if (a.pred) continue;
     const int ncell = (izc * g.Ny + (DIM == 3 ? iy : 0)) * g.Nx + ix;
     const int po = mz_append(a.out_count, status == 1);
     if (po >= a.capacity) atomicOr(a.err, ERR_CAPACITY);
@@ -426,6 +434,7 @@ struct MzNodeArgs {
   T* dep;               // nullable: [3][Ny][Nx] deposit plane to clear
   T* jrec[3];           // nullable: raw current planes to record into
   int* zero_count;      // nullable
+  int pred;             // predictor: only out[] is written (and dep cleared)
 };
 
 template <typename T>
@@ -449,10 +458,11 @@ __global__ __launch_bounds__(256) void k_mz_node(MzNodeArgs<T> a) {
   const int kyi = (int)(m / g.Nxh), kxi = (int)(m % g.Nxh);
   const cplx<T> z = mk((T)0, (T)0);
   if (g.Ny > 1 && kyi == g.Ny / 2) {
+    for (int q = 0; q < 6; ++q) a.out[q][m] = z;
+    if (a.pred) return;
     for (int q = 0; q < 4; ++q) a.st[q][o] = z;
     a.L[0][o] = z;
     a.L[1][o] = z;
-    for (int q = 0; q < 6; ++q) a.out[q][m] = z;
     a.j0[0][o + M] = z;
     a.j0[1][o + M] = z;
     if (n == 0) { a.j0[0][m] = z; a.j0[1][m] = z; }
@@ -518,18 +528,21 @@ __global__ __launch_bounds__(256) void k_mz_node(MzNodeArgs<T> a) {
   const cplx<T> Ezp = Ez1 + Ez, Bzp = Bz + Bz1;
   const cplx<T> Lx = Lx1 - ((T)0.5 * h) * (mul_i((T)0.5 * (kx * Ezp - ky * Bzp)) + jxp);
   const cplx<T> Ly = Ly1 - ((T)0.5 * h) * (mul_i((T)0.5 * (ky * Ezp + kx * Bzp)) + jyp);
-  a.st[0][o] = Rx;
-  a.st[1][o] = Ry;
-  a.st[2][o] = Ez;
-  a.st[3][o] = Bz;
-  a.L[0][o] = Lx;
-  a.L[1][o] = Ly;
+  if (!a.pred) {
+    a.st[0][o] = Rx;
+    a.st[1][o] = Ry;
+    a.st[2][o] = Ez;
+    a.st[3][o] = Bz;
+    a.L[0][o] = Lx;
+    a.L[1][o] = Ly;
+  }
   a.out[0][m] = (T)0.5 * (Rx + Lx);
   a.out[1][m] = (T)0.5 * (Ry + Ly);
   a.out[2][m] = Ez;
   a.out[3][m] = (T)0.5 * (Ly - Ry);
   a.out[4][m] = (T)0.5 * (Rx - Lx);
   a.out[5][m] = Bz;
+  if (a.pred) return;
   a.j0[0][o + M] = jxp;
   a.j0[1][o + M] = jyp;
   if (n == 0) { a.j0[0][m] = z; a.j0[1][m] = z; }

@@ -1,4 +1,4 @@
-"""Pins of the zeta march on a non-uniform fast grid and with a slow step that
+"""Pins of the zeta march on a non-uniform fast grid, with a slow step that
 changes from step to step (Sec. 7: Delta may vary arbitrarily between
 levels; h may vary smoothly along zeta).
 
@@ -138,3 +138,51 @@ def test_smooth_nonuniform_grid_converges_at_second_order():
     # the scheme's error on the finest grid is below 1e-3 of it
     want, _ = _continuum(s3)
     assert np.linalg.norm(R3 - want) / np.linalg.norm(want) < 1e-3
+
+
+def _wake_run(nz, delta, steps, scheme):
+    """2-D plane-wave laser (a0 = 0.1, T = 4.247 lambda in exp(-phi^2/T^2),
+    centred 12 lambda behind the front of a 51.2 lambda box) in a uniform
+    cold plasma at n_e = 0.01 n_c: on-axis E_z after `steps` slow steps, the
+    linear-theory amplitude and the plasma wavelength."""
+    a0, n, T_lambda = 0.1, 0.01, 4.247
+    cfg = workloads._base(dims=2, n=[2, 1, nz], d=[0.25, 1.0, 51.2 / nz], n_e=n, ppc=[1, 1, 1], load=1,
+                          a0=a0, waist=0.0, fwhm=T_lambda * np.sqrt(2 * np.log(2)), zeta_c=51.2 - 12.0,
+                          tile=[2, 1, 8], precision="fp64")
+    cfg.update(scheme=scheme, delta=delta)
+    s = MarchSim(cfg).run(steps)
+    p = s.p
+    kp, T = np.sqrt(n), p.T
+    amp = kp ** 2 * (a0 ** 2 / 4) * T * np.sqrt(np.pi / 2) * np.exp(-kp ** 2 * T ** 2 / 8)
+    lam = 2 * np.pi / kp
+    zeta = s.m.zn[:p.Nz]
+    win = (zeta < p.zeta_c - 2.6 * T) & (zeta > p.zeta_c - 2.6 * T - 1.2 * lam)
+    e = s.F0[2, :p.Nz, 0, 0][win]
+    zc = zeta[win][:-1][np.sign(e[:-1]) != np.sign(e[1:])]
+    return np.abs(e).max() / amp, np.diff(zc) / (lam / 2)
+
+
+def test_linear_wake_gt2_converges_to_linear_theory():
+    """The plasma's field coupling (M2 predictor-corrector, M3, M5, Q_f): in
+    GT2 a fresh batch streams through the whole box in one slow step and
+    builds the quasi-static linear wake, E_max = k_p^2 (a0^2 / 4) T sqrt(pi/2)
+    exp(-k_p^2 T^2 / 8) behind a Gaussian pulse, with half-periods lambda_p / 2.
+    The amplitude converges at second order in h to within 3 % of it (the
+    rest is the O(a0^2) relativistic correction and the laser's evolution)."""
+    r = []
+    for nz in (512, 1024, 2048):
+        amp, half = _wake_run(nz, 0.5, 2, 2)
+        r.append(amp)
+        assert len(half) >= 2 and np.all(np.abs(half - 1.0) < 0.01), (nz, half)
+    assert 3.0 < (r[1] - r[0]) / (r[2] - r[1]) < 5.5, r
+    assert abs(r[2] - 1.0) < 0.03, r
+
+
+def test_linear_wake_gt1_with_large_slow_step():
+    """GT1 with Delta = 2 lambda (Delta omega_p = 1.26, 40 h): the parked
+    batches carry the wake from step to step; after the plasma in the box has
+    been renewed (35 steps) the wake is the linear one within 5 % and its
+    half-periods within 1 % of lambda_p / 2."""
+    amp, half = _wake_run(1024, 2.0, 35, 1)
+    assert len(half) >= 2 and np.all(np.abs(half - 1.0) < 0.01), half
+    assert abs(amp - 1.0) < 0.05, amp

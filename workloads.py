@@ -121,7 +121,7 @@ def small3d(precision="fp64", n=(32, 32, 64), tile=(8, 8, 8), ppc=(1, 1, 2),
                  fwhm=1.5, zeta_c=None, steps=steps, seed=seed)
 
 
-def lwfa_channel(nz=4096, delta=40.0, scheme=1, nodes=None):
+def lwfa_channel(nz=4096, delta=40.0, scheme=2, nodes=None):
     """The paper's example (Sec. 6) scaled down to one GPU and without
     ionisation: hydrogen plasma in a Gaussian channel, n_e = n_0 [1 + (n_1 -
     n_0) / n_0 exp(-r^2 / R_ch^2)] with n_0 = 5e17 cm^-3 (2.9e-4 of the
@@ -130,7 +130,9 @@ def lwfa_channel(nz=4096, delta=40.0, scheme=1, nodes=None):
     lambda, intensity FWHM 22.5 lambda), R = 22.9 um (28.6 lambda); window
     150 x 150 x 180 um (187.5 x 187.5 x 225 lambda) at h_x = h_y = 1.46
     lambda (128 x 128) and h = 50 nm (0.0549 lambda, 4096 nodes); zeta march
-    with Delta = 32 um (40 lambda).  Lengths in lambda = 0.8 um.
+    with Delta = 32 um (40 lambda), in GT2: with GT1 and Delta < L the
+    parked plasma stitches the density every Delta (Sec. 5), which the
+    temporal transformation avoids.  Lengths in lambda = 0.8 um.
     nodes: optional zeta node positions (a refined rear, as the paper's
     6.3 nm rear third)."""
     cfg = _base(dims=3, n=[128, 128, nz], d=[187.5 / 128, 187.5 / 128, 225.0 / nz], precision="fp32",
