@@ -432,6 +432,14 @@ class MarchSim:
         stopped = []
         left = []
         right = [np.zeros((p.Ny, p.Nx), complex) for _ in range(6)]
+        def node_currents(n, jp1):
+            """(j0 of n - 1/2, predicted j1 of n - 1/2 (M3), j0 of n + 1/2)
+            for the R rows of node n, given j1 of n + 1/2."""
+            if first:
+                return jp1[:2], jp1[:2], jp1[:2]
+            jm0 = (self.j0[0][n], self.j0[1][n])
+            return jm0, jm0, (self.j0[0][n + 1], self.j0[1][n + 1])
+
         for n in range(p.Nz - 1, -1, -1):
             A = MP.concat(active, P.take(P.iz == n))
             dep = Deposit(m)
@@ -442,13 +450,9 @@ class MarchSim:
                 dp = Deposit(m)
                 self._stage_particles(n, A, F1, dp, None)
                 jq = solver_currents(m, dp.Jx, dp.Jy, dp.Jz, KX, KY, nyq)
-                if first:
-                    qp0 = qm0 = jq[:2]
-                else:
-                    qp0 = (self.j0[0][n + 1], self.j0[1][n + 1])
-                    qm0 = (self.j0[0][n], self.j0[1][n])
+                qm0, qm1, qp0 = node_currents(n, jq)
                 old = [getattr(self.state, nm)[n] for nm in ("Rx", "Ry", "Ez", "Bz")]
-                pred = solve_node(m, n, D, old, right, qm0, qm0, qp0, jq, KX, KY, nyq)
+                pred = solve_node(m, n, D, old, right, qm0, qm1, qp0, jq, KX, KY, nyq)
                 Flow = self.F0.copy()
                 Flow[:, n] = node_real_fields(pred)
             if len(A):
@@ -464,13 +468,7 @@ class MarchSim:
                 F1[:, n] = self.F0[:, n]
                 continue
             jp1 = solver_currents(m, dep.Jx, dep.Jy, dep.Jz, KX, KY, nyq)
-            if first:
-                jp0 = jp1[:2]
-                jm0 = jp1[:2]
-            else:
-                jp0 = (self.j0[0][n + 1], self.j0[1][n + 1])
-                jm0 = (self.j0[0][n], self.j0[1][n])
-            jm1 = jm0                                       # M3 predictor
+            jm0, jm1, jp0 = node_currents(n, jp1)
             jst[0][n + 1], jst[1][n + 1] = jp1[0], jp1[1]
             old = [getattr(self.state, nm)[n] for nm in ("Rx", "Ry", "Ez", "Bz")]
             vals = solve_node(m, n, D, old, right, jm0, jm1, jp0, jp1, KX, KY, nyq)
