@@ -281,6 +281,11 @@ struct Impl {
                                                                       inverse);
   }
   static void fft_fwd(gempic* g, const T* in, C* out, int64_t planes) {
+    fft_xfwd(g, in, out, planes);
+    if (g->g.Ny > 1) fft_y(g, out, planes, 0);
+  }
+  // the x part of fft_fwd: real rows -> half spectra along x
+  static void fft_xfwd(gempic* g, const T* in, C* out, int64_t planes) {
     const Geom& G = g->g;
     int64_t rows = planes * G.Ny;
     int64_t pairs = (rows + 1) / 2;
@@ -292,7 +297,6 @@ struct Impl {
       k_fft_x_r2c_512<T><<<(unsigned)((pairs + R2C512_P - 1) / R2C512_P), 128, 0, g->s>>>(in, out, rows, (const C*)g->twx);
     else
       k_fft_x_r2c<T><<<nblk(pairs, nseq), 256, sh, g->s>>>(in, out, rows, G.Nx, nseq, (const C*)g->twx);
-    if (G.Ny > 1) fft_y(g, out, planes, 0);
   }
   // inverse x transforms of `rows` rows of six field spectra (in[q] + row
   // Nxh) -> interleaved real node records
@@ -513,8 +517,13 @@ struct Impl {
     return (unsigned)(8 * ((nitem + 7) / 8));
   }
 
+  static size_t colnode_lds(const Geom& G) {
+    return (12 * (size_t)(G.Ny + FFTY_PAD) + (size_t)G.Ny) * sizeof(C);
+  }
+
   static void set_lds_limits() {
     int lim = 160 * 1024;
+    (void)hipFuncSetAttribute((const void*)k_mz_colnode<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_fft_x_r2c<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_fft_x_c2r6<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)k_fft_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -946,7 +955,6 @@ struct Impl {
         const bool pred = pass == 0;
         if (G.dims == 3) mz_stage<3>(g, n, D, pred);
         else mz_stage<2>(g, n, D, pred);
-        fft_fwd(g, (const T*)g->mz_dep, (C*)g->mz_jhat, 3);
         MzNodeArgs<T> a = mz_node_args(g, n, D);
         a.jhat = (const C*)g->mz_jhat;
         for (int q = 0; q < 6; ++q) a.out[q] = out6[q];
@@ -956,8 +964,19 @@ struct Impl {
           for (int q = 0; q < 3; ++q) a.jrec[q] = (T*)g->J[q] + (int64_t)(n + 2) * nxy;
           a.zero_count = g->mz_cnt + C_ACT + (n & 1);
         }
-        k_mz_node<T><<<nblk(std::max<int64_t>(M, 3 * nxy / 8), 256), 256, 0, g->s>>>(a);
-        if (G.Ny > 1) fft_y(g, out6[0], 6, 1);
+        if (G.Ny > 1 && G.Ny != 256 && G.Ny != 512) {
+          // x transform of the deposit, then one work-group per kx column:
+          // y transform, node solve and inverse y transforms in LDS (where
+          // no four-step y transform exists; with one, its coalesced
+          // launches are faster than a work-group per column)
+          fft_xfwd(g, (const T*)g->mz_dep, (C*)g->mz_jhat, 3);
+          k_mz_colnode<T><<<(unsigned)G.Nxh, 256, colnode_lds(G), g->s>>>(a, (const C*)g->mz_jhat,
+                                                                           (const C*)g->twy);
+        } else {
+          fft_fwd(g, (const T*)g->mz_dep, (C*)g->mz_jhat, 3);
+          k_mz_node<T><<<nblk(std::max<int64_t>(M, 3 * nxy / 8), 256), 256, 0, g->s>>>(a);
+          if (G.Ny > 1) fft_y(g, out6[0], 6, 1);
+        }
         c2r6(g, in6, (T*)g->F6b + (int64_t)n * nxy * 6, G.Ny);
       }
     }

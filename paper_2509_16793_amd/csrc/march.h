@@ -437,28 +437,37 @@ struct MzNodeArgs {
   int pred;             // predictor: only out[] is written (and dep cleared)
 };
 
+// the deposit plane recorded (corrector) and cleared for the next pass, and
+// the stage's particle counter reset; thread t of nt strides over the plane
 template <typename T>
-__global__ __launch_bounds__(256) void k_mz_node(MzNodeArgs<T> a) {
+GP_DEV void mz_node_clear(const MzNodeArgs<T>& a, int64_t t, int64_t nt) {
   const Geom& g = a.g;
-  const int64_t M = (int64_t)g.Ny * g.Nxh;
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t P = (int64_t)g.Ny * g.Nx;
   if (a.dep) {
-    for (int64_t i = m; i < 3 * P; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = t; i < 3 * P; i += nt) {
       const int c = (int)(i / P);
       const int64_t r = i - (int64_t)c * P;
       if (a.jrec[0]) a.jrec[c][r] = a.dep[i];
       a.dep[i] = (T)0;
     }
   }
-  if (m == 0 && a.zero_count) *a.zero_count = 0;
-  if (m >= M) return;
+  if (t == 0 && a.zero_count) *a.zero_count = 0;
+}
+
+// node n for transverse mode m = ky Nxh + kx, given the transforms of the
+// cell's deposit at that mode (jh; zero without current): the new level's
+// state (R, E_z, B_z, L and this step's solver currents) unless predicting,
+// and the six field spectra in out[]
+template <typename T>
+GP_DEV void mz_node_mode(const MzNodeArgs<T>& a, int64_t m, const cplx<T> jh[3], cplx<T> out[6]) {
+  const Geom& g = a.g;
+  const int64_t M = (int64_t)g.Ny * g.Nxh;
   const int n = a.n;
   const int64_t o = (int64_t)n * M + m;
   const int kyi = (int)(m / g.Nxh), kxi = (int)(m % g.Nxh);
   const cplx<T> z = mk((T)0, (T)0);
   if (g.Ny > 1 && kyi == g.Ny / 2) {
-    for (int q = 0; q < 6; ++q) a.out[q][m] = z;
+    for (int q = 0; q < 6; ++q) out[q] = z;
     if (a.pred) return;
     for (int q = 0; q < 4; ++q) a.st[q][o] = z;
     a.L[0][o] = z;
@@ -481,12 +490,7 @@ __global__ __launch_bounds__(256) void k_mz_node(MzNodeArgs<T> a) {
   const cplx<T> sy = g.dims == 3 ? mk((T)(phi * cos(0.5 * kyd * g.hy)), (T)(-phi * sin(0.5 * kyd * g.hy)))
                                  : mk((T)phi, (T)0);
   const T kx = (T)kxd, ky = (T)kyd;
-  cplx<T> jxp = z, jyp = z, jzp = z;
-  if (a.jhat) {
-    jxp = sx * a.jhat[m];
-    jyp = sy * a.jhat[M + m];
-    jzp = (T)phi * a.jhat[2 * M + m];
-  }
+  const cplx<T> jxp = sx * jh[0], jyp = sy * jh[1], jzp = (T)phi * jh[2];
   cplx<T> jx0p, jy0p, jx0m, jy0m;
   if (a.first) {
     jx0p = jx0m = jxp;
@@ -536,16 +540,78 @@ __global__ __launch_bounds__(256) void k_mz_node(MzNodeArgs<T> a) {
     a.L[0][o] = Lx;
     a.L[1][o] = Ly;
   }
-  a.out[0][m] = (T)0.5 * (Rx + Lx);
-  a.out[1][m] = (T)0.5 * (Ry + Ly);
-  a.out[2][m] = Ez;
-  a.out[3][m] = (T)0.5 * (Ly - Ry);
-  a.out[4][m] = (T)0.5 * (Rx - Lx);
-  a.out[5][m] = Bz;
+  out[0] = (T)0.5 * (Rx + Lx);
+  out[1] = (T)0.5 * (Ry + Ly);
+  out[2] = Ez;
+  out[3] = (T)0.5 * (Ly - Ry);
+  out[4] = (T)0.5 * (Rx - Lx);
+  out[5] = Bz;
   if (a.pred) return;
   a.j0[0][o + M] = jxp;
   a.j0[1][o + M] = jyp;
   if (n == 0) { a.j0[0][m] = z; a.j0[1][m] = z; }
+}
+
+
+// node n for every mode, one thread per mode (spectra already transformed
+// along y, or Ny = 1)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mz_node(MzNodeArgs<T> a) {
+  const int64_t M = (int64_t)a.g.Ny * a.g.Nxh;
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  mz_node_clear(a, m, (int64_t)gridDim.x * blockDim.x);
+  if (m >= M) return;
+  cplx<T> jh[3] = {mk((T)0, (T)0), mk((T)0, (T)0), mk((T)0, (T)0)};
+  if (a.jhat) {
+    jh[0] = a.jhat[m];
+    jh[1] = a.jhat[M + m];
+    jh[2] = a.jhat[2 * M + m];
+  }
+  cplx<T> out[6];
+  mz_node_mode(a, m, jh, out);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) a.out[q][m] = out[q];
+}
+
+// One kx column per work-group: the cell's deposit, transformed along x
+// (jhx, [3][Ny][Nxh]), is transformed along y in LDS, node n is solved for
+// each of the column's modes, and the six field spectra are transformed back
+// along y in LDS and written to out[] (still to be transformed along x).
+// Fuses the forward y transform, k_mz_node and the inverse y transforms of a
+// pass; dynamic LDS: 2 x 6 sequences of Ny + FFTY_PAD plus Ny twiddles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mz_colnode(MzNodeArgs<T> a, const cplx<T>* jhx, const cplx<T>* twy) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Geom& g = a.g;
+  const int Ny = g.Ny, Nxh = g.Nxh;
+  const int S = Ny + FFTY_PAD;
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* B = A + 6 * S;
+  cplx<T>* tl = B + 6 * S;
+  const int kx = blockIdx.x;
+  mz_node_clear(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+  const int64_t M = (int64_t)Ny * Nxh;
+  for (int i = threadIdx.x; i < 3 * Ny; i += blockDim.x) {
+    const int c = i / Ny, ky = i - c * Ny;
+    A[c * S + ky] = a.jhat ? jhx[c * M + (int64_t)ky * Nxh + kx] : mk((T)0, (T)0);
+  }
+  __syncthreads();
+  cplx<T>* Z = lds_fft(A, B, tl, Ny, 3, twy, false, S);
+  cplx<T>* W = Z == A ? B : A;
+  for (int ky = threadIdx.x; ky < Ny; ky += blockDim.x) {
+    const cplx<T> jh[3] = {Z[ky], Z[S + ky], Z[2 * S + ky]};
+    cplx<T> out[6];
+    mz_node_mode(a, (int64_t)ky * Nxh + kx, jh, out);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) W[q * S + ky] = out[q];
+  }
+  __syncthreads();
+  cplx<T>* R = lds_fft(W, Z, tl, Ny, 6, twy, true, S);
+  const T sc = (T)1 / (T)Ny;
+  for (int i = threadIdx.x; i < 6 * Ny; i += blockDim.x) {
+    const int q = i / Ny, ky = i - q * Ny;
+    a.out[q][(int64_t)ky * Nxh + kx] = sc * R[q * S + ky];
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -11,8 +11,9 @@ FP64 atomics in arrival order, so both sides agree to roundoff, not bit for
 bit.  FP32 (cell + offset) against the FP64 oracle: every field component
 within 2e-4 of its own norm or 30 units of 2^-24 of the largest component.
 Cases: GT1 with particles parked in the box (Delta < L) and streaming through
-it (Delta > L), GT2, 2-D, a quiet plasma at rest (exactly zero current), and
-vacuum."""
+it (Delta > L), GT2, 2-D, Ny = 256 (the node solve between the four-step y
+transforms; other Ny take the fused per-column kernel), a quiet plasma at
+rest (exactly zero current), and vacuum."""
 import numpy as np
 import pytest
 
@@ -77,8 +78,9 @@ def _compare(o, g, field_bar=1e-10):
     assert np.max(np.abs(b - P.b)) < 1e-9 * o.m.Delta
 
 
-@pytest.mark.parametrize("cfg", [_cfg3(0.5), _cfg3(50.0), _cfg3(0.5, scheme=2), _cfg2(0.7)],
-                         ids=["gt1_parked", "gt1_through", "gt2", "gt1_2d"])
+@pytest.mark.parametrize("cfg", [_cfg3(0.5), _cfg3(50.0), _cfg3(0.5, scheme=2), _cfg2(0.7),
+                                 _cfg3(0.5, n=(16, 256, 32))],
+                         ids=["gt1_parked", "gt1_through", "gt2", "gt1_2d", "gt1_ny256"])
 def test_march_fp64_matches_oracle(cfg):
     o = MarchSim(cfg)
     g = Sim(cfg, track_ids=True)
