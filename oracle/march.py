@@ -34,9 +34,17 @@ Readings (where the paper is silent; the HIP path takes the same ones):
       stage, with the predicted node n, deposits and solves node n again.
       Only the corrector's particles and currents are kept.
   M3  Predictor: j^1 on half-node n - 1/2 (needed by RxN, RyN at node n) is
-      the previous step's j^0 there.  In the first step after creation there
-      is no j^0: both levels and the predictor use the current j^1 of
-      half-node n + 1/2.
+      the previous step's j^0 there plus the change that half-node n + 1/2
+      has just seen, j^1_{-1/2} = j^0_{-1/2} + (j^1_{+1/2} - j^0_{+1/2}).
+      The four-term sum of the R rows is then 2 (j^1_{+1/2} + j^0_{-1/2}),
+      centred on node n and on the middle of the slow step, and the R update
+      keeps the amplitude of a mode whose current turns its phase (the
+      laser in the plasma).  Taking j^0_{-1/2} alone would weigh the old
+      level three to one, which multiplies the laser's amplitude by about
+      1 + theta^2 / 4 per step, theta = Delta omega_p^2 / (2 omega): a few
+      percent per step once Delta is several laser periods.  In the first
+      step after creation there is no j^0: both levels and the predictor
+      use the current j^1 of half-node n + 1/2.
   M4  A sub-step moves at most half a transverse cell: its time is at most
       min(h_x, h_y) / 2.
   M5  Current of a sub-step inside cell n, charged to half-node n + 1/2:
@@ -438,7 +446,9 @@ class MarchSim:
             if first:
                 return jp1[:2], jp1[:2], jp1[:2]
             jm0 = (self.j0[0][n], self.j0[1][n])
-            return jm0, jm0, (self.j0[0][n + 1], self.j0[1][n + 1])
+            jp0 = (self.j0[0][n + 1], self.j0[1][n + 1])
+            jm1 = tuple(jm0[c] + (jp1[c] - jp0[c]) for c in range(2))
+            return jm0, jm1, jp0
 
         for n in range(p.Nz - 1, -1, -1):
             A = MP.concat(active, P.take(P.iz == n))

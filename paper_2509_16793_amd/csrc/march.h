@@ -414,8 +414,12 @@ __global__ __launch_bounds__(256) void k_mz_stage(MzStageArgs<T> a) {
 // transforms of cell n's deposit, shifted from the faces x_{i+1/2} (y_{j+1/2}
 // in 3-D) to the nodes by exp(-i k h / 2) and filtered transversally by
 // cos^2(k h / 2) per pass; j^0 is the previous step's (stored), and j^1 on
-// half-node n - 1/2 is predicted by j^0 there (first step: every term is the
-// current j^1 of half-node n + 1/2).  The R rows carry the four-term sum.
+// half-node n - 1/2 is predicted as j^0 there plus the change half-node
+// n + 1/2 has seen, j^0_{-1/2} + (j^1_{+1/2} - j^0_{+1/2}), so that the R
+// rows' four-term sum is 2 (j^1_{+1/2} + j^0_{-1/2}), centred on the node
+// and on the middle of the slow step: the R update then keeps the amplitude
+// of a mode whose current only turns its phase (first step: every term is
+// the current j^1 of half-node n + 1/2).
 // The kernel also stores j^1 for the next step, records the cell's raw
 // currents (jrec), clears the deposit plane for the next stage and resets a
 // particle counter.
@@ -491,19 +495,11 @@ GP_DEV void mz_node_mode(const MzNodeArgs<T>& a, int64_t m, const cplx<T> jh[3],
                                  : mk((T)phi, (T)0);
   const T kx = (T)kxd, ky = (T)kyd;
   const cplx<T> jxp = sx * jh[0], jyp = sy * jh[1], jzp = (T)phi * jh[2];
-  cplx<T> jx0p, jy0p, jx0m, jy0m;
-  if (a.first) {
-    jx0p = jx0m = jxp;
-    jy0p = jy0m = jyp;
-  } else {
-    jx0p = a.j0[0][o + M];
-    jy0p = a.j0[1][o + M];
-    jx0m = a.j0[0][o];
-    jy0m = a.j0[1][o];
-  }
-  // four-term sums: j^1_{-1/2} (predicted = j^0_{-1/2}) + j^0_{-1/2} + j^1_{+1/2} + j^0_{+1/2}
-  const cplx<T> Jx = ((jx0m + jx0m) + jxp) + jx0p;
-  const cplx<T> Jy = ((jy0m + jy0m) + jyp) + jy0p;
+  const cplx<T> jx0m = a.first ? jxp : a.j0[0][o];
+  const cplx<T> jy0m = a.first ? jyp : a.j0[1][o];
+  // four-term sums with the predicted j^1_{-1/2}: 2 (j^1_{+1/2} + j^0_{-1/2})
+  const cplx<T> Jx = (T)2 * (jxp + jx0m);
+  const cplx<T> Jy = (T)2 * (jyp + jy0m);
   const T h = a.h, D = a.D;
   const T K2 = kx * kx + ky * ky;
   const T Dd = (T)16 + h * ((T)2 * D + h) * K2;
