@@ -23,6 +23,7 @@ import numpy as np
 
 import workloads
 from oracle.march import MarchSim, continuity_residual
+from wake import wake_cfg, wake_measure
 
 
 def _smooth_nodes(N, L, ratio=2.0):
@@ -141,35 +142,14 @@ def test_smooth_nonuniform_grid_converges_at_second_order():
 
 
 def _wake_run(nz, delta, steps, scheme):
-    """2-D plane-wave laser (a0 = 0.1, T = 4.247 lambda in exp(-phi^2/T^2),
-    centred 12 lambda behind the front of a 51.2 lambda box) in a uniform
-    cold plasma at n_e = 0.01 n_c: on-axis E_z after `steps` slow steps, the
-    linear-theory amplitude and the plasma wavelength."""
-    return _wake_measure(MarchSim(_wake_cfg(nz, delta, scheme)).run(steps))
+    """On-axis E_z of the plane-wave linear wake (tests/wake.py) after
+    `steps` slow steps, against linear theory, and its half-periods."""
+    cfg = wake_cfg(nz, delta, scheme)
+    return _wake_measure(cfg, MarchSim(cfg).run(steps))
 
 
-def _wake_cfg(nz, delta, scheme):
-    """The _wake_run configuration."""
-    a0, n, T_lambda = 0.1, 0.01, 4.247
-    cfg = workloads._base(dims=2, n=[2, 1, nz], d=[0.25, 1.0, 51.2 / nz], n_e=n, ppc=[1, 1, 1], load=1,
-                          a0=a0, waist=0.0, fwhm=T_lambda * np.sqrt(2 * np.log(2)), zeta_c=51.2 - 12.0,
-                          tile=[2, 1, 8], precision="fp64")
-    cfg.update(scheme=scheme, delta=delta)
-    return cfg
-
-
-def _wake_measure(s, a0=0.1, n=0.01):
-    """On-axis E_z of a _wake_run simulation (its a0 and n_e / n_c) against
-    linear theory, and its half-periods in lambda_p / 2."""
-    p = s.p
-    kp, T = np.sqrt(n), p.T
-    amp = kp ** 2 * (a0 ** 2 / 4) * T * np.sqrt(np.pi / 2) * np.exp(-kp ** 2 * T ** 2 / 8)
-    lam = 2 * np.pi / kp
-    zeta = s.m.zn[:p.Nz]
-    win = (zeta < p.zeta_c - 2.6 * T) & (zeta > p.zeta_c - 2.6 * T - 1.2 * lam)
-    e = s.F0[2, :p.Nz, 0, 0][win]
-    zc = zeta[win][:-1][np.sign(e[:-1]) != np.sign(e[1:])]
-    return np.abs(e).max() / amp, np.diff(zc) / (lam / 2)
+def _wake_measure(cfg, s):
+    return wake_measure(cfg, s.F0[2, :s.p.Nz, 0, 0])
 
 
 def test_linear_wake_gt2_converges_to_linear_theory():
@@ -205,9 +185,10 @@ def test_linear_wake_gt2_steady_at_delta_omega_p_4():
     keeps its amplitude, so the wake it drives is steady from step to step
     (a predictor that weighs the old level three to one grows the wake by
     about 5 % per step here) and stays the linear one within 4 %."""
-    s = MarchSim(_wake_cfg(1024, 7.0, 2)).run(6)
-    a6, half = _wake_measure(s)
-    a18, half18 = _wake_measure(s.run(12))
+    cfg = wake_cfg(1024, 7.0, 2)
+    s = MarchSim(cfg).run(6)
+    a6, _ = _wake_measure(cfg, s)
+    a18, half18 = _wake_measure(cfg, s.run(12))
     assert len(half18) >= 1 and np.all(np.abs(half18 - 1.0) < 0.01), half18
     assert abs(a18 / a6 - 1.0) < 0.01, (a6, a18)
     assert abs(a18 - 1.0) < 0.04, a18
