@@ -58,6 +58,11 @@ int64_t n_params() { return layer_woff(NLAYER); }
 // the halo tile in LDS, double-buffered); a phase reduces over 16 or fewer
 // channels
 GP_HD constexpr int conv_split(int cinp) { return cinp == 32 ? 2 : 1; }
+// the output layer (16 -> 3) folds its y taps into the MFMA rows: row
+// 4 c + dy of operand A holds output channel c at tap row dy, and the
+// reduction index is (dz, dx, input channel) only: five k-steps of 32
+constexpr int FOLD_NKS = 5;
+int64_t fold_units() { return (int64_t)FOLD_NKS * 64; }
 int64_t packed_units(int cinp, int coutp) {
   int ce = cinp / conv_split(cinp);
   int tpk = 32 / ce;
@@ -66,6 +71,9 @@ int64_t packed_units(int cinp, int coutp) {
 }
 
 constexpr int TZ = 4, TY = 8, TX = 16;        // output tile of one work-group
+#ifndef PF_ROWS
+#define PF_ROWS(inmode, nct) ((nct) == 2 ? 5 : TY + 2)
+#endif
 constexpr int HZ = TZ + 2, HY = TY + 2, HX = TX + 2;
 constexpr int HALO = HZ * HY * HX;            // 1080 voxels
 constexpr int TILE = TZ * TY * TX;            // 512 voxels
@@ -93,6 +101,7 @@ struct PackArgs {
   int cin, cout;      // layer channels
   int cinp, coutp;    // padded channels of the packed convolution
   int transpose;      // 1: data-gradient convolution (cout -> cin, flipped taps)
+  int fold;           // 1: output layer with its y taps folded into the rows (cinp = 16, cout <= 4)
   u32x4* out;
   int64_t units;
 };
@@ -106,6 +115,28 @@ __global__ void k_pack(PackArgs a) {
   int j = (int)(r % nct);
   r /= nct;
   int g = lane >> 4, n = lane & 15;
+  if (a.fold) {
+    // k-step s: lane-group slot g / 2 takes the (dz, dx) combination
+    // q = 2 s + g / 2 (q = 9: zero padding), input channels 8 (g % 2) .. + 7;
+    // row n is output channel n / 4 at tap row dy = n % 4 (dy = 3: zero)
+    int s = (int)r;
+    int q = 2 * s + g / 2;
+    int co = n / 4, dy = n % 4;
+    unsigned w[8];
+    for (int e = 0; e < 8; ++e) {
+      int ci = 8 * (g % 2) + e;
+      float v = 0.0f;
+      if (q < 9 && dy < 3 && co < a.cout && ci < a.cin) v = a.W[((int64_t)co * a.cin + ci) * 27 + (q / 3) * 9 + dy * 3 + q % 3];
+      w[e] = f2bf(v);
+    }
+    u32x4 o;
+    o[0] = w[0] | (w[1] << 16);
+    o[1] = w[2] | (w[3] << 16);
+    o[2] = w[4] | (w[5] << 16);
+    o[3] = w[6] | (w[7] << 16);
+    a.out[u] = o;
+    return;
+  }
   // phase p reduces over the packed input channels p ce .. p ce + ce - 1;
   // its k-step s = 3 cg + (dy + 1) takes, in lane-group slot i, the (dz, dx)
   // combination q = cg tpk + i (q > 8: zero padding) at that dy
@@ -169,6 +200,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int NKS = 3 * NCG;              // k-steps of a phase: (column group, dy)
   constexpr int NCT = COUTP / 16;
   static_assert(TZ == 4, "one output plane per wave");
+  // FOLD (the 16 -> 3 output layer): operand A row 4 c + dy is output channel
+  // c at tap row dy, the k-steps run over (dz, dx, input channel) only, and
+  // each halo row h has its own accumulator; output row r of channel c (lane
+  // group c) is then the in-lane sum of rows dy of the accumulators of halo
+  // rows r + dy: 5 (TY + 2) MFMAs per wave and tile instead of 3 NCG TY
+  constexpr bool FOLD = INMODE == 0 && OUTMODE == 1 && CINP == 16 && COUTP == 16;
+  constexpr int NKSW = FOLD ? FOLD_NKS : NKS;   // packed k-steps per phase
+  constexpr int NACC = FOLD ? TY + 2 : TY;      // accumulators per row tile
+  // halo rows whose fragments are read ahead of their MFMAs (register
+  // budget: 32 output channels hold twice the accumulators)
+  constexpr int PF = PF_ROWS(INMODE, NCT);
   // halo tile, unit-major: sX[unit * HALO_P + voxel], so that the 16 lanes of
   // a lane group read 16 consecutive 16-byte units; the unit stride is padded
   // so that the units start on different banks
@@ -194,14 +236,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int ntile = nbx * nby * ((a.Z + TZ - 1) / TZ);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-  bf16x8 wr[KS][NKS][NCT];
+  bf16x8 wr[KS][NKSW][NCT];
 #pragma unroll
   for (int p = 0; p < KS; ++p)
 #pragma unroll
-    for (int s = 0; s < NKS; ++s)
+    for (int s = 0; s < NKSW; ++s)
 #pragma unroll
       for (int j = 0; j < NCT; ++j)
-        wr[p][s][j] = __builtin_bit_cast(bf16x8, a.wp[((p * NKS + s) * NCT + j) * 64 + lane]);
+        wr[p][s][j] = __builtin_bit_cast(bf16x8, a.wp[((p * NKSW + s) * NCT + j) * 64 + lane]);
 
   // biases in registers: loaded from global memory in the epilogue, they
   // would be reloaded after every output store (the pointers may alias) and
@@ -212,10 +254,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int co = 16 * j + 4 * g + i;
-      bias_r[j][i] = OUTMODE == 0 ? a.bias[co] : OUTMODE == 1 && j == 0 && i < 3 ? a.bias[i] : 0.0f;
+      if (FOLD) bias_r[j][i] = i == 0 && g < 3 ? a.bias[g] : 0.0f;
+      else bias_r[j][i] = OUTMODE == 0 ? a.bias[co] : OUTMODE == 1 && j == 0 && i < 3 ? a.bias[i] : 0.0f;
     }
 
-  constexpr int PU = U >= 4 ? 2 : 1;        // units prefetched into registers (register budget)
+  // units prefetched into registers (register budget); the folded output
+  // layer has the registers to take its whole halo, so no part of it is
+  // loaded between the barriers
+  constexpr int PU = FOLD ? U : U >= 4 ? 2 : 1;
   // staging of channel units [U0, U0 + UW): one halo row (HX voxels x UW
   // units, contiguous in global memory apart from the periodic wrap) per
   // group of HX * UW threads; row k of this thread is first + k * PER
@@ -351,9 +397,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   b /= nbx;
   const int by = b % nby, bz = b / nby;
   const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-  f32x4 acc[TY][NCT];
+  f32x4 acc[NACC][NCT];
 #pragma unroll
-  for (int r = 0; r < TY; ++r)
+  for (int r = 0; r < NACC; ++r)
 #pragma unroll
     for (int j = 0; j < NCT; ++j) acc[r][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -368,6 +414,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     else prefetch_input(tn);
   }
 
+  if constexpr (FOLD) {
+    // k-step s: lane group g reads the (dz, dx) combination q = 2 s + g / 2
+    // (q = 9 is padding with zero weights; its read is clamped to q = 8),
+    // channel unit g % 2, of every halo row h
+    const int q0 = g >> 1, c0u = g & 1;
+    const int lb = c0u * HALO_P + (wave + 1) * HY * HX + n + 1;
+#pragma unroll
+    for (int s = 0; s < FOLD_NKS; ++s) {
+      int q = 2 * s + q0;
+      q = q > 8 ? 8 : q;
+      const int off = lb + (q / 3 - 1) * HY * HX + (q % 3 - 1);
+#pragma unroll
+      for (int h = 0; h < TY + 2; ++h) {
+        const bf16x8 f = __builtin_bit_cast(bf16x8, sX[off + h * HX]);
+        acc[h][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[p][s][0], f, acc[h][0], 0, 0, 0);
+      }
+    }
+  } else
   // Each wave computes the TY rows (16 x voxels each) of output plane
   // z0 + wave.  The k-steps are ordered (column group cg, dy): column group
   // cg holds the (dz, dx) combinations cg * TPK .. cg * TPK + TPK - 1, one per
@@ -386,9 +450,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       else q = slot == 0 ? 4 * cg : slot == 1 ? 4 * cg + 1 : slot == 2 ? 4 * cg + 2 : 4 * cg + 3;
       q = q > 8 ? 8 : q;                    // padding slots (zero weights)
       const int off = lb + (q / 3 - 1) * HY * HX + (q % 3 - 1);
+      // the fragments of PF halo rows are read before the first of their
+      // MFMAs, so that the reads of later rows are in flight while the MFMAs
+      // of earlier ones run (a read waited for right before its three MFMAs
+      // leaves the matrix pipe idle for the LDS latency)
 #pragma unroll
-      for (int h = 0; h < TY + 2; ++h) {
-        const bf16x8 f = __builtin_bit_cast(bf16x8, sX[off + h * HX]);
+      for (int h0 = 0; h0 < TY + 2; h0 += PF) {
+      bf16x8 fr[PF];
+#pragma unroll
+      for (int i = 0; i < PF; ++i)
+        if (h0 + i < TY + 2) fr[i] = __builtin_bit_cast(bf16x8, sX[off + (h0 + i) * HX]);
+      // keep the instruction scheduler from sinking the reads back to their
+      // uses
+      if (PF > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int h = h0; h < h0 + PF && h < TY + 2; ++h) {
+        const bf16x8 f = fr[h - h0];
 #pragma unroll
         for (int dyi = 0; dyi < 3; ++dyi) {
           const int r = h - dyi;
@@ -398,6 +475,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
               acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[p][3 * cg + dyi][j], f, acc[r][j], 0, 0, 0);
           }
         }
+      }
       }
     }
   }
@@ -426,7 +504,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int r = 0; r < TY; ++r) {
       if (z >= a.Z) break;
       int64_t vox = ((int64_t)z * a.Y + (y0 + r)) * a.X + (x0 + n);
-      if (OUTMODE == 1) {
+      if (FOLD) {
+        // lane group g < 3 holds output channel g: rows dy = 0, 1, 2 of the
+        // accumulators of halo rows r, r + 1, r + 2
+        if (g < 3)
+          a.outf[g][vox] = ((acc[r][0][0] + acc[r + 1][0][1]) + acc[r + 2][0][2]) + bias_r[0][0];
+      } else if (OUTMODE == 1) {
         if (g == 0) {
           a.outf[0][vox] = acc[r][0][0] + bias_r[0][0];
           a.outf[1][vox] = acc[r][0][1] + bias_r[0][1];
@@ -977,13 +1060,15 @@ static int repack(gempic_dn* d, hipStream_t s) {
     p.cinp = pad_in(L_CIN[l]);
     p.coutp = pad_out(L_COUT[l]);
     p.transpose = 0;
+    p.fold = l == NLAYER - 1;
     p.out = d->fw[l];
-    p.units = packed_units(p.cinp, p.coutp);
+    p.units = p.fold ? fold_units() : packed_units(p.cinp, p.coutp);
     k_pack<<<nblk(p.units, 256), 256, 0, s>>>(p);
     if (l > 0) {
       p.cinp = pad_in(L_COUT[l]);
       p.coutp = pad_out(L_CIN[l]);
       p.transpose = 1;
+      p.fold = 0;
       p.out = d->bw[l];
       p.units = packed_units(p.cinp, p.coutp);
       k_pack<<<nblk(p.units, 256), 256, 0, s>>>(p);
