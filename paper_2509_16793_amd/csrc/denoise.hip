@@ -211,20 +211,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // halo rows whose fragments are read ahead of their MFMAs (register
   // budget: 32 output channels hold twice the accumulators)
   constexpr int PF = PF_ROWS(INMODE, NCT);
-  // halo tile, unit-major: sX[unit * HALO_P + voxel], so that the 16 lanes of
-  // a lane group read 16 consecutive 16-byte units; the unit stride is padded
-  // so that the units start on different banks
   // DIRECT (two-unit phases: 16-channel inputs with 32 output channels, and
   // both halves of 32-channel inputs): two halo buffers; the next phase's
   // halo is read straight from global memory into the other buffer
-  // (global_load_lds, 64 voxels of one unit per wave instruction) while the
-  // current one is used.  (16 -> 16 channels: the second buffer would cost a
-  // wave per SIMD; there the registers take part of the halo instead.)
+  // (global_load_lds) while the current one is used.  Its tile is
+  // voxel-major, sX[voxel * 2 + unit]: a wave instruction then loads both
+  // units of 32 voxels, 32 contiguous bytes each (one unit of 64 voxels
+  // would take 16 bytes out of every 32 or 64 and touch twice or four times
+  // the cache lines).  (16 -> 16 channels: the second buffer would cost a
+  // wave per SIMD; there the registers take the halo instead.)
+  // Otherwise the tile is unit-major, sX[unit * HALO_P + voxel], the unit
+  // stride padded so that the units start on different banks.
+  // Either way the 16 lanes of a lane group read one unit of 16 consecutive
+  // voxels.
   constexpr bool DIRECT = INMODE == 0 && UE == 2 && (COUTP == 32 || KS == 2);
   static_assert(KS == 1 || DIRECT, "split phases are double-buffered");
-  constexpr int NCH = (HALO + 63) / 64;     // 64-voxel chunks per unit
-  constexpr int HALO_P = (DIRECT ? NCH * 64 : HALO) + 2;
-  __shared__ u32x4 sXbuf[(DIRECT ? 2 : 1) * HALO_P * UE];
+  constexpr int NCH2 = (HALO + 31) / 32;    // DIRECT: 32-voxel chunks of the tile
+  constexpr int HALO_P = HALO + 2;
+  constexpr int BUFU = DIRECT ? NCH2 * 64 : HALO_P * UE;   // 16-byte units per halo buffer
+  constexpr int VS = DIRECT ? UE : 1;       // stride of one voxel in units
+  __shared__ u32x4 sXbuf[(DIRECT ? 2 : 1) * BUFU];
   u32x4* sX = sXbuf;
 
   // Persistent work-groups walk the output tiles t = blockIdx.x, + gridDim.x,
@@ -353,16 +359,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     input_vox(t, [&](int k, int hv, bool, int64_t) { sX[hv] = pack_in(pin[3 * k], pin[3 * k + 1], pin[3 * k + 2]); });
   };
 
-  // units p UE .. p UE + UE - 1 of tile t's halo into dst
+  // units p UE .. p UE + UE - 1 of tile t's halo into dst: chunk c of 32
+  // voxels per wave instruction, lane l loading unit l % 2 of voxel
+  // 32 c + l / 2 into dst[64 c + l]
   auto direct_load = [&](int t, int p, u32x4* dst) {
     int b = t;
     const int bx = b % nbx;
     b /= nbx;
     const int by = b % nby, bz = b / nby;
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-    for (int c = wave; c < UE * NCH; c += 4) {
-      const int u = c / NCH, ch = c - u * NCH;
-      const int hv = ch * 64 + lane;
+    for (int c = wave; c < NCH2; c += 4) {
+      const int u = lane & 1;
+      const int hv = c * 32 + (lane >> 1);
       const u32x4* src = &g_zero16;
       if (hv < HALO) {
         const int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
@@ -373,7 +381,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
       }
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                       (__attribute__((address_space(3))) void*)(dst + u * HALO_P + ch * 64),
+                                       (__attribute__((address_space(3))) void*)(dst + c * 64),
                                        16, 0, 0);
     }
   };
@@ -407,9 +415,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // the phase after this one: the next half of this tile, or the next tile
   const bool last = p == KS - 1;
   const int tn = last ? t + (int)gridDim.x : t;
-  sX = sXbuf + buf * (HALO_P * UE);
+  sX = sXbuf + buf * BUFU;
   if (tn < ntile) {
-    if (DIRECT) direct_load(tn, last ? 0 : p + 1, sXbuf + (buf ^ 1) * (HALO_P * UE));
+    if (DIRECT) direct_load(tn, last ? 0 : p + 1, sXbuf + (buf ^ 1) * BUFU);
     else if (INMODE == 0) prefetch(tn);
     else prefetch_input(tn);
   }
@@ -441,7 +449,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   {
     const int slot = (g * 8) / CE;          // this lane group's slot within a k-step
     const int c0u = ((g * 8) % CE) / 8;     // and its 16-byte channel unit
-    const int lb = c0u * HALO_P + (wave + 1) * HY * HX + n + 1;
+    const int lb = (DIRECT ? c0u : c0u * HALO_P) + ((wave + 1) * HY * HX + n + 1) * VS;
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) {
       int q;
@@ -449,7 +457,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       else if (TPK == 2) q = slot ? 2 * cg + 1 : 2 * cg;
       else q = slot == 0 ? 4 * cg : slot == 1 ? 4 * cg + 1 : slot == 2 ? 4 * cg + 2 : 4 * cg + 3;
       q = q > 8 ? 8 : q;                    // padding slots (zero weights)
-      const int off = lb + (q / 3 - 1) * HY * HX + (q % 3 - 1);
+      const int off = lb + ((q / 3 - 1) * HY * HX + (q % 3 - 1)) * VS;
       // the fragments of PF halo rows are read before the first of their
       // MFMAs, so that the reads of later rows are in flight while the MFMAs
       // of earlier ones run (a read waited for right before its three MFMAs
@@ -459,7 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       bf16x8 fr[PF];
 #pragma unroll
       for (int i = 0; i < PF; ++i)
-        if (h0 + i < TY + 2) fr[i] = __builtin_bit_cast(bf16x8, sX[off + (h0 + i) * HX]);
+        if (h0 + i < TY + 2) fr[i] = __builtin_bit_cast(bf16x8, sX[off + (h0 + i) * HX * VS]);
       // keep the instruction scheduler from sinking the reads back to their
       // uses
       if (PF > 1) __builtin_amdgcn_sched_barrier(0);
