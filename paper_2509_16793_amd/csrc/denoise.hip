@@ -6,7 +6,8 @@
 // Layouts
 //   boxes are (Z, Y, X) voxels, x and y periodic, zero beyond the Z planes;
 //   currents, A and their gradients: FP32 planar [3][Z][Y][X];
-//   hidden activations and their gradients: bf16 channels-last [Z][Y][X][C];
+//   hidden activations and their gradients: bf16 channels-last [Z][Y][X][C],
+//   32 channels as two halves [2][Z][Y][X][16];
 //   parameters: FP32, layer by layer W[Cout][Cin][kz][ky][kx] then b[Cout].
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 with the
@@ -92,6 +93,24 @@ GP_DEV unsigned pack_bf16(float lo, float hi) {
 }
 
 GP_DEV float bf2f(unsigned b) { return __uint_as_float(b << 16); }
+
+// Hidden activations (and their gradients) are bf16 channels-last; a
+// 32-channel tensor is stored as two 16-channel halves one after the other,
+// [half][voxel][16], so that either half of a voxel's channels (the part one
+// phase of the next convolution reduces over) is 32 contiguous bytes.
+// 16-byte unit u (channels 8u .. 8u + 7) of voxel v of a tensor with U units
+// per voxel and V voxels:
+template <int U>
+GP_DEV int64_t unit_at(int64_t v, int u, int64_t V) {
+  if constexpr (U == 4) return ((int64_t)(u >> 1) * V + v) * 2 + (u & 1);
+  else return v * U + u;
+}
+// element (channel c) of voxel v, for a tensor with C channels
+template <int C>
+GP_DEV int64_t chan_at(int64_t v, int c, int64_t V) {
+  if constexpr (C == 32) return ((int64_t)(c >> 4) * V + v) * 16 + (c & 15);
+  else return v * C + c;
+}
 GP_DEV int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // ---------------------------------------------------------------------------
@@ -291,7 +310,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int gz = z0 + hz - 1;
         const int gy = wrapi(y0 + hy - 1, a.Y);
         const bool inz = gz >= 0 && gz < a.Z;
-        put(k, part * HALO_P + row * HX + hx, inz, (((int64_t)gz * a.Y + gy) * a.X + gx) * U + part);
+        put(k, part * HALO_P + row * HX + hx, inz,
+            unit_at<U>(((int64_t)gz * a.Y + gy) * a.X + gx, part, (int64_t)a.Z * a.Y * a.X));
       }
     }
   };
@@ -377,7 +397,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int gz = z0 + hz - 1;
         if (gz >= 0 && gz < a.Z) {
           const int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
-          src = a.in + ((((int64_t)gz * a.Y + gy) * a.X + gx) * U + p * UE + u);
+          src = a.in + unit_at<U>(((int64_t)gz * a.Y + gy) * a.X + gx, p * UE + u, (int64_t)a.Z * a.Y * a.X);
         }
       }
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
@@ -532,7 +552,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[r][j][i] + bias_r[j][i], 0.0f);
           } else {
-            u32x2 m = *(const u32x2*)(a.mask + vox * COUTP + co0);
+            u32x2 m = *(const u32x2*)(a.mask + chan_at<COUTP>(vox, co0, (int64_t)a.Z * a.Y * a.X));
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               unsigned mb = (i & 1) ? (m[i >> 1] >> 16) : (m[i >> 1] & 0xFFFFu);
@@ -542,7 +562,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           u32x2 o;
           o[0] = pack_bf16(v[0], v[1]);
           o[1] = pack_bf16(v[2], v[3]);
-          *(u32x2*)(a.out + vox * COUTP + co0) = o;
+          *(u32x2*)(a.out + chan_at<COUTP>(vox, co0, (int64_t)a.Z * a.Y * a.X)) = o;
         }
       }
     }
@@ -594,7 +614,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       u32x4 v = {0u, 0u, 0u, 0u};
       if (gz >= 0 && gz < a.Z) {
         int gy = wrapi(y0 + hy - 1, a.Y), gx = wrapi(x0 + hx - 1, a.X);
-        v = a.x[(((int64_t)gz * a.Y + gy) * a.X + gx) * U + part];
+        v = a.x[unit_at<U>(((int64_t)gz * a.Y + gy) * a.X + gx, part, (int64_t)a.Z * a.Y * a.X)];
       }
       sXv[u] = v;
     }
@@ -621,7 +641,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       int zz = tv / (TY * TX), r = tv - zz * (TY * TX), yy = r / TX, xx = r - yy * TX;
       int gz = z0 + zz;
       u32x4 v = {0u, 0u, 0u, 0u};
-      if (gz < a.Z) v = a.gy[(((int64_t)gz * a.Y + (y0 + yy)) * a.X + (x0 + xx)) * U + part];
+      if (gz < a.Z) v = a.gy[unit_at<U>(((int64_t)gz * a.Y + (y0 + yy)) * a.X + (x0 + xx), part, (int64_t)a.Z * a.Y * a.X)];
       sGv[u] = v;
     }
   } else {
