@@ -2,13 +2,16 @@
 more slow steps and finer grids than the oracle's own wake tests take
 (tests/wake.py: plane-wave Gaussian pulse, a0 = 0.1, n_e = 0.01 n_c).
 
-GT2 with Delta = 7 lambda (Delta omega_p = 4.4), h = lambda / 40: the R
-update turns the laser's phase by Delta omega_p^2 / (2 omega) = 0.22 rad per
-step and, with the predicted current of the half-node below the node
-(Sec. 4.1), keeps its amplitude, so the wake is steady from step 6 to step
-36 (s = 42 to 252 lambda) within 1 %, within 2 % of linear theory, and its
-half-periods within 1 % of lambda_p / 2.  The same in FP32 (cell + offset)
-within 1 % of the FP64 run."""
+Delta = 7 lambda (Delta omega_p = 4.4), h = lambda / 40, 36 slow steps
+(s = 252 lambda).  The R update turns the laser's phase by
+Delta omega_p^2 / (2 omega) = 0.22 rad per step and, with the predicted
+current of the half-node below the node (Sec. 4.1), keeps its amplitude, so
+the wake is steady from step 6 to step 36: within 1 % in GT2 (the plasma is
+renewed every step), within 3 % in GT1 (batches parked in the box for
+L / Delta = 7 steps; measured 1.8 %).  A predictor that weighs the old
+level three to one grows it by about 5 % per step.  Both stay within 2 % of
+linear theory with half-periods within 1 % of lambda_p / 2, and FP32
+(cell + offset) is within 1 % of FP64."""
 import numpy as np
 import pytest
 
@@ -18,8 +21,8 @@ from wake import wake_cfg, wake_measure
 pytestmark = pytest.mark.gpu
 
 
-def _run(precision):
-    cfg = wake_cfg(2048, 7.0, 2, nx=4, tile=(4, 1, 4), precision=precision)
+def _run(scheme, precision):
+    cfg = wake_cfg(2048, 7.0, scheme, nx=4, tile=(4, 1, 4), precision=precision)
     g = Sim(cfg)
     g.step(6)
     a6, _ = wake_measure(cfg, g.fields(("Ez",))["Ez"][:, 0, 0])
@@ -29,10 +32,11 @@ def _run(precision):
     return a6, a36, half
 
 
-def test_gt2_wake_steady_over_36_slow_steps():
-    a6, a36, half = _run("fp64")
+@pytest.mark.parametrize("scheme,steady", [(2, 0.01), (1, 0.03)], ids=["gt2", "gt1"])
+def test_wake_steady_over_36_slow_steps(scheme, steady):
+    a6, a36, half = _run(scheme, "fp64")
     assert len(half) >= 1 and np.all(np.abs(half - 1.0) < 0.01), half
-    assert abs(a36 / a6 - 1.0) < 0.01, (a6, a36)
+    assert abs(a36 / a6 - 1.0) < steady, (a6, a36)
     assert abs(a36 - 1.0) < 0.02, a36
-    b6, b36, _ = _run("fp32")
+    b6, b36, _ = _run(scheme, "fp32")
     assert abs(b6 / a6 - 1.0) < 0.01 and abs(b36 / a36 - 1.0) < 0.01, (a6, a36, b6, b36)
