@@ -19,7 +19,9 @@
 // both operands, so operands A and B agree element by element.  The k-steps
 // are ordered by (group of (dz, dx) taps, dy), so that one LDS read serves
 // three output rows; 32-channel inputs are reduced in two 16-channel phases,
-// each with its half of the halo in its own LDS buffer.  The data gradient is
+// each with its half of the halo in its own LDS buffer.  The 16 -> 3 output
+// layer instead folds its y taps into the MFMA rows (row 4 c + dy) and sums
+// the three partial rows in-lane.  The data gradient is
 // the same kernel with flipped taps and transposed channels; weight
 // gradients are MFMAs with the voxels as the reduction index.
 #include <hip/hip_runtime.h>
@@ -72,9 +74,9 @@ int64_t packed_units(int cinp, int coutp) {
 }
 
 constexpr int TZ = 4, TY = 8, TX = 16;        // output tile of one work-group
-#ifndef PF_ROWS
-#define PF_ROWS(inmode, nct) ((nct) == 2 ? 5 : TY + 2)
-#endif
+// halo rows whose LDS fragments are read ahead of their MFMAs: all of them,
+// or half with 32 output channels (twice the accumulators in registers)
+constexpr int pf_rows(int nct) { return nct == 2 ? 5 : TY + 2; }
 constexpr int HZ = TZ + 2, HY = TY + 2, HX = TX + 2;
 constexpr int HALO = HZ * HY * HX;            // 1080 voxels
 constexpr int TILE = TZ * TY * TX;            // 512 voxels
@@ -227,9 +229,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr bool FOLD = INMODE == 0 && OUTMODE == 1 && CINP == 16 && COUTP == 16;
   constexpr int NKSW = FOLD ? FOLD_NKS : NKS;   // packed k-steps per phase
   constexpr int NACC = FOLD ? TY + 2 : TY;      // accumulators per row tile
-  // halo rows whose fragments are read ahead of their MFMAs (register
-  // budget: 32 output channels hold twice the accumulators)
-  constexpr int PF = PF_ROWS(INMODE, NCT);
+  constexpr int PF = pf_rows(NCT);          // halo rows read ahead
   // DIRECT (two-unit phases: 16-channel inputs with 32 output channels, and
   // both halves of 32-channel inputs): two halo buffers; the next phase's
   // halo is read straight from global memory into the other buffer
