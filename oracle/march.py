@@ -42,9 +42,17 @@ Readings (where the paper is silent; the HIP path takes the same ones):
       laser in the plasma).  Taking j^0_{-1/2} alone would weigh the old
       level three to one, which multiplies the laser's amplitude by about
       1 + theta^2 / 4 per step, theta = Delta omega_p^2 / (2 omega): a few
-      percent per step once Delta is several laser periods.  In the first
-      step after creation there is no j^0: both levels and the predictor
-      use the current j^1 of half-node n + 1/2.
+      percent per step once Delta is several laser periods.
+      j^0 of the level of creation: in GT1 the plasma in the box starts at
+      rest, so j^0 = 0.  In GT2 a particle at rest streams through the whole
+      box at fixed s~, so the plasma's level-s0 current is its response to
+      the initial fields: a startup march at creation pushes one fresh batch
+      through them, with node solves of zero slow step (R unchanged, L, E_z
+      and B_z taking the plasma's response), keeps its currents as j^0 and
+      its fields as the initial ones, and discards the particles.  (Using
+      j^1 for both levels in the first step instead would make that step
+      implicit in the current and damp the laser once by about
+      1 / sqrt(1 + theta^2).)
   M4  A sub-step moves at most half a transverse cell: its time is at most
       min(h_x, h_y) / 2.
   M5  Current of a sub-step inside cell n, charged to half-node n + 1/2:
@@ -322,6 +330,12 @@ class MarchSim:
         self.diag = None
         self.left = MP.empty()
         self.trace = None                    # list: (n, particles on node n) per stage (pins)
+        if self.solver and p.n_e > 0:
+            if m.scheme == 1:
+                z = np.zeros((p.Nz + 1, p.Ny, p.Nx), complex)
+                self.j0 = (z, z.copy())
+            else:
+                self.step(startup=True)
 
     # ---- particle sub-steps inside cell n --------------------------------
     def _stage_particles(self, n, A, F1, dep, flux, Flow=None):
@@ -412,13 +426,20 @@ class MarchSim:
         return self.m.p
 
     # ---- one slow step --------------------------------------------------
-    def step(self, Delta=None, diag=False):
+    def step(self, Delta=None, diag=False, startup=False):
+        """One slow step; ``startup``: the GT2 startup march of M3 (nothing
+        advances but the fields of the level of creation and j^0)."""
         m, p = self.m, self.p
         if Delta is not None:
             D = float(Delta) * self.lu
             m.check_delta(D)
             m.Delta = D
         D = m.Delta
+        Dn = 0.0 if startup else D           # slow step of the node solves
+        pid0 = self.next_pid
+        if startup:
+            diag = False
+            assert len(self.P) == 0 and m.scheme == 2
         # budgets of the particles in the box: the new step's Delta plus the
         # carried (non-positive) rest of the last one
         P = self.P
@@ -462,7 +483,7 @@ class MarchSim:
                 jq = solver_currents(m, dp.Jx, dp.Jy, dp.Jz, KX, KY, nyq)
                 qm0, qm1, qp0 = node_currents(n, jq)
                 old = [getattr(self.state, nm)[n] for nm in ("Rx", "Ry", "Ez", "Bz")]
-                pred = solve_node(m, n, D, old, right, qm0, qm1, qp0, jq, KX, KY, nyq)
+                pred = solve_node(m, n, Dn, old, right, qm0, qm1, qp0, jq, KX, KY, nyq)
                 Flow = self.F0.copy()
                 Flow[:, n] = node_real_fields(pred)
             if len(A):
@@ -481,12 +502,18 @@ class MarchSim:
             jm0, jm1, jp0 = node_currents(n, jp1)
             jst[0][n + 1], jst[1][n + 1] = jp1[0], jp1[1]
             old = [getattr(self.state, nm)[n] for nm in ("Rx", "Ry", "Ez", "Bz")]
-            vals = solve_node(m, n, D, old, right, jm0, jm1, jp0, jp1, KX, KY, nyq)
+            vals = solve_node(m, n, Dn, old, right, jm0, jm1, jp0, jp1, KX, KY, nyq)
             for c, nm in enumerate(SpectralState.NAMES):
                 getattr(new, nm)[n] = vals[c]
             right = vals
             F1[:, n] = node_real_fields(vals)
         # currents of the half-node below node 0 are those of no particle
+        if startup:
+            self.state = new
+            self.F0 = F1
+            self.j0 = (jst[0], jst[1])
+            self.next_pid = pid0
+            return self
         self.J = Jrec
         self.flux = flux
         P = MP.concat(*(stopped + [active])) if (stopped or len(active)) else MP.empty()

@@ -192,3 +192,22 @@ def test_linear_wake_gt2_steady_at_delta_omega_p_4():
     assert len(half18) >= 1 and np.all(np.abs(half18 - 1.0) < 0.01), half18
     assert abs(a18 / a6 - 1.0) < 0.01, (a6, a18)
     assert abs(a18 - 1.0) < 0.04, a18
+
+
+def test_first_slow_step_keeps_the_laser_in_dense_plasma():
+    """M3 at creation: GT2 with theta = Delta omega_p^2 / (2 omega) = 1.3
+    (n_e = 0.05 n_c, Delta = 8.3 lambda).  A plane-wave laser's current
+    only turns its phase, so with j^0 of the level of creation from the
+    startup march the peak |E_x| stays within 4 % of a0 over the first four
+    slow steps (using j^1 for both levels in the first step would make it
+    implicit and drop the laser to about 0.7 a0 at once)."""
+    a0, n = 0.1, 0.05
+    theta = 1.3
+    delta = 2.0 * theta / n / (2.0 * math.pi)
+    cfg = wake_cfg(512, delta, 2)
+    cfg.update(n_e=n)
+    s = MarchSim(cfg)
+    for _ in range(4):
+        s.step()
+        amp = np.abs(s.F0[0]).max()
+        assert abs(amp / a0 - 1.0) < 0.04, amp
