@@ -43,16 +43,18 @@ Readings (where the paper is silent; the HIP path takes the same ones):
       level three to one, which multiplies the laser's amplitude by about
       1 + theta^2 / 4 per step, theta = Delta omega_p^2 / (2 omega): a few
       percent per step once Delta is several laser periods.
-      j^0 of the level of creation: in GT1 the plasma in the box starts at
-      rest, so j^0 = 0.  In GT2 a particle at rest streams through the whole
-      box at fixed s~, so the plasma's level-s0 current is its response to
-      the initial fields: a startup march at creation pushes one fresh batch
-      through them, with node solves of zero slow step (R unchanged, L, E_z
-      and B_z taking the plasma's response), keeps its currents as j^0 and
-      its fields as the initial ones, and discards the particles.  (Using
-      j^1 for both levels in the first step instead would make that step
-      implicit in the current and damp the laser once by about
-      1 / sqrt(1 + theta^2).)
+      j^0 of the level of creation.  In GT2 a particle at rest streams
+      through the whole box at fixed s~, so the plasma's level-s0 current is
+      its response to the initial fields: a startup march at creation pushes
+      one fresh batch through them, with node solves of zero slow step (R
+      unchanged, L, E_z and B_z taking the plasma's response), keeps its
+      currents as j^0 and its fields as the initial ones, and discards the
+      particles.  GT1 has no such level-s0 current (its plasma in the box
+      is parked, and it takes up the laser's quiver within one laser
+      period, not one slow step): its first step uses the current j^1 of
+      half-node n + 1/2 for both levels and the predictor, which makes that
+      step implicit in the current and damps the laser once by about
+      1 / sqrt(1 + theta^2).
   M4  A sub-step moves at most half a transverse cell: its time is at most
       min(h_x, h_y) / 2.
   M5  Current of a sub-step inside cell n, charged to half-node n + 1/2:
@@ -330,12 +332,8 @@ class MarchSim:
         self.diag = None
         self.left = MP.empty()
         self.trace = None                    # list: (n, particles on node n) per stage (pins)
-        if self.solver and p.n_e > 0:
-            if m.scheme == 1:
-                z = np.zeros((p.Nz + 1, p.Ny, p.Nx), complex)
-                self.j0 = (z, z.copy())
-            else:
-                self.step(startup=True)
+        if self.solver and p.n_e > 0 and m.scheme == 2:
+            self.step(startup=True)
 
     # ---- particle sub-steps inside cell n --------------------------------
     def _stage_particles(self, n, A, F1, dep, flux, Flow=None):

@@ -882,6 +882,10 @@ struct Impl {
     mz_sort(g);
     int rc = launch_check(g, "zeta-march initial state");
     if (rc) return rc;
+    // GT2: the plasma's current of the level of creation (j^0 of the first
+    // step) from the startup march (plasma at rest streams through the box
+    // at fixed s~); GT1's first step uses j^1 for both levels (mz_first)
+    if (g->cfg.n_e > 0.0 && g->scheme == 2 && (rc = mz_step(g, true))) return rc;
     HIPCHK(g, hipStreamSynchronize(g->s));
     return GEMPIC_OK;
   }
@@ -920,13 +924,18 @@ struct Impl {
     k_mz_stage<T, DIM><<<g->mz_stage_blocks, 256, 0, g->s>>>(a);
   }
 
-  // one slow step of the zeta march
-  static int mz_step(gempic* g) {
+  // one slow step of the zeta march; startup (GT2, at creation): the
+  // startup march that gives the plasma's current of the level of creation
+  // (j^0 of the first step) and the fields with its response -- node solves
+  // of zero slow step, one fresh batch pushed through and discarded, nothing
+  // advanced
+  static int mz_step(gempic* g, bool startup = false) {
     const Geom& G = g->g;
     const int Nz = G.Nz;
     const int64_t M = (int64_t)G.Ny * G.Nxh;
     const int64_t nxy = (int64_t)G.Ny * G.Nx;
     const T D = (T)g->Delta;
+    const T Dn = startup ? (T)0 : D;          // slow step of the node solves
     int rc = mark(g, 0);
     if (rc) return rc;
     const int fresh = g->cfg.n_e > 0.0 ? (int)g->nperp : 0;
@@ -955,7 +964,7 @@ struct Impl {
         const bool pred = pass == 0;
         if (G.dims == 3) mz_stage<3>(g, n, D, pred);
         else mz_stage<2>(g, n, D, pred);
-        MzNodeArgs<T> a = mz_node_args(g, n, D);
+        MzNodeArgs<T> a = mz_node_args(g, n, Dn);
         a.jhat = (const C*)g->mz_jhat;
         for (int q = 0; q < 6; ++q) a.out[q] = out6[q];
         a.dep = (T*)g->mz_dep;
@@ -981,6 +990,13 @@ struct Impl {
       }
     }
     if ((rc = launch_check(g, "zeta-march stages"))) return rc;
+    if (startup) {
+      // the batch's particles are dropped: the next step's k_mz_begin resets
+      // the active, stopped and left counters, and no parked store changed
+      std::swap(g->F6, g->F6b);
+      g->mz_first = 0;
+      return GEMPIC_OK;
+    }
     if ((rc = mark(g, 2))) return rc;
     mz_sort(g);
     std::swap(g->F6, g->F6b);

@@ -418,8 +418,10 @@ __global__ __launch_bounds__(256) void k_mz_stage(MzStageArgs<T> a) {
 // n + 1/2 has seen, j^0_{-1/2} + (j^1_{+1/2} - j^0_{+1/2}), so that the R
 // rows' four-term sum is 2 (j^1_{+1/2} + j^0_{-1/2}), centred on the node
 // and on the middle of the slow step: the R update then keeps the amplitude
-// of a mode whose current only turns its phase (first step: every term is
-// the current j^1 of half-node n + 1/2).
+// of a mode whose current only turns its phase.  In GT2 j^0 of the first
+// step is the startup march's current; first = 1 (GT1's first step, no
+// plasma, or the startup march itself, whose zero slow step takes no current
+// into the R rows) uses j^1 of half-node n + 1/2.
 // The kernel also stores j^1 for the next step, records the cell's raw
 // currents (jrec), clears the deposit plane for the next stage and resets a
 // particle counter.

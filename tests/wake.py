@@ -29,7 +29,8 @@ def wake_cfg(nz, delta, scheme, nx=2, tile=(2, 1, 8), precision="fp64"):
 def wake_measure(cfg, ez_axis):
     """Peak |E_z| over the first plasma period behind the pulse (from 2.6 T
     behind its centre) in units of linear theory, and the distances between
-    the zero crossings there in units of lambda_p / 2.  ez_axis: E_z on the
+    the zero crossings there (interpolated between nodes) in units of
+    lambda_p / 2.  ez_axis: E_z on the
     nodes zeta_n = n h, n = 0 .. Nz - 1."""
     p = from_config(cfg)
     kp, T = np.sqrt(N_E), p.T
@@ -38,5 +39,8 @@ def wake_measure(cfg, ez_axis):
     zeta = np.arange(p.Nz) * p.h
     win = (zeta < p.zeta_c - 2.6 * T) & (zeta > p.zeta_c - 2.6 * T - 1.2 * lam)
     e = np.asarray(ez_axis, float)[win]
-    zc = zeta[win][:-1][np.sign(e[:-1]) != np.sign(e[1:])]
+    z = zeta[win]
+    # zero crossings, linearly interpolated between the nodes around each
+    i = np.nonzero(np.sign(e[:-1]) != np.sign(e[1:]))[0]
+    zc = z[i] - e[i] * (z[i + 1] - z[i]) / (e[i + 1] - e[i])
     return np.abs(e).max() / amp, np.diff(zc) / (lam / 2)
