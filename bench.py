@@ -29,6 +29,8 @@ Extra objects on the same line:
              128 x 128 x 4096, Delta = 32 um, GT2).
   denoise -- wall time per whole step at 1 ppc with the committed network
              against 16 ppc without it (the same LWFA physics).
+  pwfa    -- the push kernel's throughput and roofline fraction, and the
+             whole step, on the PWFA setup (5 timed steps after 2).
 """
 import argparse
 import json
@@ -186,6 +188,31 @@ def median_step_phases(sim, steps):
     return {k: statistics.median(r[k] for r in rows) for k in rows[0]}, rows
 
 
+def bench_pwfa(stream, steps=5, warmup=2):
+    """The PWFA setup (512 x 512 x 1024 cells, 4 ppc, 1e7-particle driver):
+    the push kernel's throughput and roofline fraction, and the whole step,
+    over a few steps (its creation samples the driver on the host)."""
+    import workloads
+    from paper_2509_16793_amd.gempic import Sim
+    cfg = workloads.pwfa3d_fp32()
+    ppc = cfg["ppc"][0] * cfg["ppc"][1] * cfg["ppc"][2]
+    g = Sim(cfg, stream=stream)
+    g.step(warmup)
+    n0 = g._count()
+    med, _ = median_step_phases(g, steps)
+    n_avg = 0.5 * (n0 + g._count())
+    g.close()
+    launch_s = med["push_deposit"] / 1e3
+    bpu = algorithmic_bytes_per_update(ppc)
+    achieved = n_avg * bpu / launch_s / 1e9
+    return {"workload": WORKLOAD_TEXT["pwfa"], "particles": int(n_avg), "steps": steps, "warmup": warmup,
+            "value": n_avg / launch_s, "unit": "particle updates/s",
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_push_deposit", "bytes_per_update": bpu,
+                         "median_launch_ms": launch_s * 1e3},
+            "ms_per_step": med["step"], "phase_ms_per_step": med}
+
+
 def bench_march(stream, steps=5, cpu=True):
     """The zeta march on the LWFA physics, and the paper's example scaled down."""
     import workloads
@@ -257,7 +284,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the march and denoise objects")
+    ap.add_argument("--no-extras", action="store_true", help="skip the march, denoise and pwfa objects")
     ap.add_argument("--march-only", action="store_true",
                     help="only the zeta-march object (no CPU oracle), for profiling")
     ap.add_argument("--workload", choices=("lwfa", "pwfa"), default="lwfa",
@@ -350,6 +377,8 @@ def main():
         out["march"] = m
         print("[bench] denoiser", file=sys.stderr, flush=True)
         out["denoise"] = bench_denoise(stream)
+        print("[bench] pwfa", file=sys.stderr, flush=True)
+        out["pwfa"] = bench_pwfa(stream)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on crops", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
