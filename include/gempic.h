@@ -144,7 +144,11 @@ typedef struct {
    * level below.  One batch of fresh particles (ppc[0] x ppc[1] per
    * transverse cell, u = 0, offsets as in `load`) enters at the right edge
    * per step; GT1 also loads, at creation, batches every delta below the
-   * edge.  Needs n[2] <= 65536, no driver beam, precision FP64 or FP32_CELL;
+   * edge.  GT2 creation ends with a startup march (one fresh batch pushed
+   * through the initial fields with node solves of zero slow step, its
+   * particles then dropped): the initial fields include the plasma's
+   * response and its current is the old-level current of the first step
+   * (Sec. 4.1); GT1's first step takes the new-level current for both.  Needs n[2] <= 65536, no driver beam, precision FP64 or FP32_CELL;
    * dtau, ppc[2], deposit_rho and the zeta passes of the filter are unused
    * (the transverse filter factor cos^2(k h / 2) per pass remains). */
   int32_t scheme;
