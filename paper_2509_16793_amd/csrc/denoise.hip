@@ -252,8 +252,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   __shared__ u32x4 sXbuf[(DIRECT ? 2 : 1) * BUFU];
   u32x4* sX = sXbuf;
 
-  // Persistent work-groups walk the output tiles t = blockIdx.x, + gridDim.x,
-  // ...  The weights are loaded once per work-group.  The next tile's halo is
+  // Persistent work-groups walk the output tiles t0, t0 + gridDim.x, ... (t0
+  // below).  The weights are loaded once per work-group.  The next tile's halo is
   // fetched while the current tile is computed: directly into the other LDS
   // buffer (DIRECT), else its first PU channel units (INMODE 0) or its FP32
   // input planes (INMODE 1) into registers, the rest after the tile.
@@ -406,7 +406,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
   };
 
-  int t = blockIdx.x;
+  // XCD-aware walk: work-groups are dispatched round-robin over the 8 XCDs,
+  // so work-group b runs on XCD b % 8.  The G tiles of one round of the walk
+  // (a contiguous range of the x-fastest tile order) are split into 8 runs of
+  // G / 8 consecutive tiles, run r going to the work-groups of XCD r: the
+  // tiles one XCD computes together are neighbours in x and y and share their
+  // halos in that XCD's L2 (with the round-robin order they were 8 columns
+  // apart).  When G / 8 tiles make whole slabs of TZ planes, a work-group's
+  // next tile is the one behind it in z, on the same XCD.  Any other grid
+  // keeps the plain order.
+  const int G = (int)gridDim.x;
+  int t = (G & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
   if (t >= ntile) return;
   int buf = 0;
   if (DIRECT) {
