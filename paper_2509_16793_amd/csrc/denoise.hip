@@ -741,10 +741,13 @@ struct W3 { float* p[3]; };
 // A thread takes an FY-row y strip of one x column of one component
 // (blockIdx.z) through FZ planes: the x- then y-filtered rows of the planes
 // z - 1 and z stay in registers, so that every input row is read once per
-// plane (plus the two halo rows).
+// plane (plus the two halo rows).  skip (device, nullable): when it points at
+// a non-zero flag every work-group returns at once (the fallback filter that
+// runs only when the network's current is rejected).
 constexpr int FY = 4, FZ = 8;
 
-__global__ __launch_bounds__(256) void k_filter(Box B, P3 in, W3 out) {
+__global__ __launch_bounds__(256) void k_filter(Box B, P3 in, W3 out, const int* skip) {
+  if (skip && *skip) return;
   const int ncol = B.X * (B.Y / FY);
   const int w = blockIdx.x * 256 + threadIdx.x;
   if (w >= ncol) return;
@@ -826,10 +829,19 @@ GP_DEV double block_sum_d(double v, double* sh) {
 // global atomics).
 // A work item is one (x, y) column through CZ planes: the values of plane
 // z - 1 that the curl and the divergences need are carried in registers.
+// F1 (one binomial pass): Jin is the raw current and the filtered values are
+// formed here, in k_filter's operation order (the same values bit for bit),
+// instead of being read back from a filtered copy: per plane, the x-then-y
+// filtered values of five streams (J_x at x and x - 1, J_y at y and y - 1,
+// J_z), carried over three planes for the zeta pass.  Otherwise Jin is Jf.
 constexpr int COMB_BLOCKS = 2048;
-constexpr int CZ = 8;
+template <bool F1> constexpr int comb_cz() { return F1 ? 32 : 8; }
 
-__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd, double* part) {
+struct Filt5 { float s0, s0x, s1, s1y, s2; };
+
+template <bool F1>
+__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jin, P3 A, W3 Jd, double* part) {
+  constexpr int CZ = comb_cz<F1>();
   __shared__ double sh[4];
   const Box& B = a.B;
   const int ncol = B.X * B.Y;
@@ -841,9 +853,37 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
     const int x = col % B.X, y = col / B.X;
     const int xm = wrapi(x - 1, B.X), ym = wrapi(y - 1, B.Y);
     const int cx = y * B.X + xm, cy = ym * B.X + x, cxy = ym * B.X + xm;
+    // F1: x-then-y filtered plane z of the five streams, zero outside the box
+    const int xm2 = wrapi(x - 2, B.X), xp = wrapi(x + 1, B.X);
+    const int ym2 = wrapi(y - 2, B.Y), yp = wrapi(y + 1, B.Y);
+    auto rx = [](const float* row, int l, int c, int r) { return 0.25f * row[l] + 0.5f * row[c] + 0.25f * row[r]; };
+    auto ry = [](float m, float c, float p) { return 0.25f * m + 0.5f * c + 0.25f * p; };
+    auto splane = [&](int z, bool only2) {
+      Filt5 o{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+      if (z < 0 || z >= B.Z) return o;
+      const int64_t zo = (int64_t)z * plane;
+      const float* q2 = Jin.p[2] + zo;
+      o.s2 = ry(rx(q2 + ym * B.X, xm, x, xp), rx(q2 + y * B.X, xm, x, xp), rx(q2 + yp * B.X, xm, x, xp));
+      if (only2) return o;
+      const float* q0 = Jin.p[0] + zo;
+      const float *r0m = q0 + ym * B.X, *r0c = q0 + y * B.X, *r0p = q0 + yp * B.X;
+      o.s0 = ry(rx(r0m, xm, x, xp), rx(r0c, xm, x, xp), rx(r0p, xm, x, xp));
+      o.s0x = ry(rx(r0m, xm2, xm, x), rx(r0c, xm2, xm, x), rx(r0p, xm2, xm, x));
+      const float* q1 = Jin.p[1] + zo;
+      const float c1m2 = rx(q1 + ym2 * B.X, xm, x, xp), c1m = rx(q1 + ym * B.X, xm, x, xp);
+      const float c1c = rx(q1 + y * B.X, xm, x, xp), c1p = rx(q1 + yp * B.X, xm, x, xp);
+      o.s1 = ry(c1m, c1c, c1p);
+      o.s1y = ry(c1m2, c1m, c1c);
+      return o;
+    };
+    Filt5 sm{}, sc{};
     // plane z0 - 1 (zero below the box): A_x at (y, x) and (y - 1, x),
     // A_y at (y, x) and (y, x - 1), z-component of the curl and Jf_z
     float pax = 0.0f, paxy = 0.0f, pay = 0.0f, payx = 0.0f, pc2 = 0.0f, pj2 = 0.0f;
+    if (F1) {
+      sm = splane(z0 - 1, false);
+      sc = splane(z0, false);
+    }
     if (z0 > 0) {
       const int64_t o = (z0 - 1) * plane;
       pax = A.p[0][o + col];
@@ -851,7 +891,8 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
       pay = A.p[1][o + col];
       payx = A.p[1][o + cx];
       pc2 = a.s * ((pay - payx) * a.ihx - (pax - paxy) * a.ihy);
-      pj2 = Jf.p[2][o + col];
+      if (F1) pj2 = ry(splane(z0 - 2, true).s2, sm.s2, sc.s2);
+      else pj2 = Jin.p[2][o + col];
     }
     const int zend = min(z0 + CZ, B.Z);
     for (int z = z0; z < zend; ++z) {
@@ -859,18 +900,33 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd,
       const float ax = A.p[0][o + col], ay = A.p[1][o + col], az = A.p[2][o + col];
       const float axy = A.p[0][o + cy], ayx = A.p[1][o + cx];
       const float azx = A.p[2][o + cx], azy = A.p[2][o + cy], azxy = A.p[2][o + cxy];
+      float j0, j1, j2, j0x, j1y;
+      if (F1) {
+        const Filt5 sp = splane(z + 1, false);
+        j0 = ry(sm.s0, sc.s0, sp.s0);
+        j1 = ry(sm.s1, sc.s1, sp.s1);
+        j2 = ry(sm.s2, sc.s2, sp.s2);
+        j0x = ry(sm.s0x, sc.s0x, sp.s0x);
+        j1y = ry(sm.s1y, sc.s1y, sp.s1y);
+        sm = sc;
+        sc = sp;
+      } else {
+        j0 = Jin.p[0][o + col];
+        j1 = Jin.p[1][o + col];
+        j2 = Jin.p[2][o + col];
+        j0x = Jin.p[0][o + cx];
+        j1y = Jin.p[1][o + cy];
+      }
       const float c0 = a.s * ((az - azy) * a.ihy - (ay - pay) * a.ih);
       const float c1 = a.s * ((ax - pax) * a.ih - (az - azx) * a.ihx);
       const float c2 = a.s * ((ay - ayx) * a.ihx - (ax - axy) * a.ihy);
       const float c0x = a.s * ((azx - azxy) * a.ihy - (ayx - payx) * a.ih);   // c0 at x - 1
       const float c1y = a.s * ((axy - paxy) * a.ih - (azy - azxy) * a.ihx);   // c1 at y - 1
-      const float j0 = Jf.p[0][o + col], j1 = Jf.p[1][o + col], j2 = Jf.p[2][o + col];
       Jd.p[0][o + col] = j0 + c0;
       Jd.p[1][o + col] = j1 + c1;
       Jd.p[2][o + col] = j2 + c2;
       const double dc = (double)(c0 - c0x) * a.ihx + (double)(c1 - c1y) * a.ihy + (double)(c2 - pc2) * a.ih;
-      const double df = (double)(j0 - Jf.p[0][o + cx]) * a.ihx + (double)(j1 - Jf.p[1][o + cy]) * a.ihy +
-                        (double)(j2 - pj2) * a.ih;
+      const double df = (double)(j0 - j0x) * a.ihx + (double)(j1 - j1y) * a.ihy + (double)(j2 - pj2) * a.ih;
       num += dc * dc;
       den += df * df;
       cc += (double)c0 * c0 + (double)c1 * c1 + (double)c2 * c2;
@@ -1068,6 +1124,7 @@ static int dn_fail(gempic_dn* d, int code, const std::string& m) {
 static int check_box(gempic_dn* d, int Z, int Y, int X) {
   if (Z < 1 || Y < TY || X < TX || Y % TY || X % TX)
     return dn_fail(d, GEMPIC_EINVAL, "box must have Z >= 1, Y a multiple of 8 and X a multiple of 16");
+  constexpr int CZ = comb_cz<false>();   // the shorter columns: the larger work count
   if ((int64_t)X * Y * ((Z + CZ - 1) / CZ) >= (int64_t(1) << 31) - (int64_t(COMB_BLOCKS) << 8))
     return dn_fail(d, GEMPIC_EINVAL, "box too large for the denoiser: X * Y * ceil(Z / 8) must stay below 2^31");
   return GEMPIC_OK;
@@ -1151,11 +1208,11 @@ static void filter(hipStream_t s, int Z, int Y, int X, const float* const in[3],
   }
   dim3 grid(nblk((int64_t)X * (Y / FY), 256), (unsigned)((Z + FZ - 1) / FZ), 3);
   if (passes == 1) {
-    k_filter<<<grid, 256, 0, s>>>(B, pi, W3{{out[0], out[1], out[2]}});
+    k_filter<<<grid, 256, 0, s>>>(B, pi, W3{{out[0], out[1], out[2]}}, nullptr);
     return;
   }
-  k_filter<<<grid, 256, 0, s>>>(B, pi, W3{{tmp[0], tmp[1], tmp[2]}});
-  k_filter<<<grid, 256, 0, s>>>(B, P3{{tmp[0], tmp[1], tmp[2]}}, W3{{out[0], out[1], out[2]}});
+  k_filter<<<grid, 256, 0, s>>>(B, pi, W3{{tmp[0], tmp[1], tmp[2]}}, nullptr);
+  k_filter<<<grid, 256, 0, s>>>(B, P3{{tmp[0], tmp[1], tmp[2]}}, W3{{out[0], out[1], out[2]}}, nullptr);
 }
 
 int dn_reserve(gempic_dn* d, int64_t nv) {
@@ -1223,15 +1280,27 @@ static int dn_step_ws(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const fl
                       int passes, double thr, int64_t* fallbacks, double* rel, const DnWork& w) {
   int64_t nv = (int64_t)Z * Y * X;
   if (!d->packed) repack(d, s);
-  filter(s, Z, Y, X, J, Jf, tmp, passes);
+  // one binomial pass is formed inside the combine (the filtered current is
+  // never stored); the fallback then filters the raw current into Jd
+  const bool f1 = passes == 1;
+  if (!f1) filter(s, Z, Y, X, J, Jf, tmp, passes);
   float* Ap[3] = {w.A, w.A + nv, w.A + 2 * nv};
   net_forward(d, s, Z, Y, X, J, (float)(1.0 / n_e), w.act, Ap);
   CurlArgs c = curl_args(Z, Y, X, n_e, hs);
-  k_combine<<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
-                                        W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
+  if (f1)
+    k_combine<true><<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{J[0], J[1], J[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                                W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
+  else
+    k_combine<false><<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                                 W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
   k_decide<<<1, 256, 0, s>>>(w.part, COMB_BLOCKS, thr, w.use_net, rel ? rel : w.rel,
                              fallbacks ? fallbacks : d->fallbacks);
-  k_select<<<SEL_BLOCKS, 256, 0, s>>>(c.B, w.use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
+  if (f1) {
+    dim3 grid(nblk((int64_t)X * (Y / FY), 256), (unsigned)((Z + FZ - 1) / FZ), 3);
+    k_filter<<<grid, 256, 0, s>>>(c.B, P3{{J[0], J[1], J[2]}}, W3{{Jd[0], Jd[1], Jd[2]}}, w.use_net);
+  } else {
+    k_select<<<SEL_BLOCKS, 256, 0, s>>>(c.B, w.use_net, P3{{Jf[0], Jf[1], Jf[2]}}, W3{{Jd[0], Jd[1], Jd[2]}});
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return dn_fail(d, GEMPIC_EDEVICE, std::string("denoiser launch: ") + hipGetErrorString(e));
   return GEMPIC_OK;

@@ -47,7 +47,9 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("shape", [(10, 16, 32), (4, 8, 16), (1, 8, 16)])
+# (37, 24, 80): a 32-plane column of the fused filter and combine and a
+# ragged second one, x wider than a wavefront
+@pytest.mark.parametrize("shape", [(10, 16, 32), (4, 8, 16), (1, 8, 16), (37, 24, 80)])
 def test_forward_matches_oracle(shape):
     # last layer scaled so that the correction stays below the filtered
     # current (the size criterion of the fallback test keeps it)
@@ -71,7 +73,7 @@ def test_forward_matches_oracle(shape):
 # shapes: one plane; planes and rows that fill the filter's 8-plane chunks and
 # 8-row strips exactly; a ragged last chunk with x wider than a wavefront
 @pytest.mark.parametrize("shape,passes", [((6, 8, 16), 2), ((1, 8, 16), 1), ((16, 16, 32), 1),
-                                          ((19, 24, 80), 2), ((19, 24, 80), 0)])
+                                          ((19, 24, 80), 2), ((19, 24, 80), 0), ((37, 24, 80), 1)])
 def test_fallback_returns_filtered_current(shape, passes):
     theta = workloads.denoiser_init(seed=12, last_scale=1.0, bias_scale=0.05)
     J = _current(shape, 2)
