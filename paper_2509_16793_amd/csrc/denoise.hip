@@ -829,19 +829,11 @@ GP_DEV double block_sum_d(double v, double* sh) {
 // global atomics).
 // A work item is one (x, y) column through CZ planes: the values of plane
 // z - 1 that the curl and the divergences need are carried in registers.
-// F1 (one binomial pass): Jin is the raw current and the filtered values are
-// formed here, in k_filter's operation order (the same values bit for bit),
-// instead of being read back from a filtered copy: per plane, the x-then-y
-// filtered values of five streams (J_x at x and x - 1, J_y at y and y - 1,
-// J_z), carried over three planes for the zeta pass.  Otherwise Jin is Jf.
+// (With one filter pass, k_combine_f1 below forms Jf itself.)
 constexpr int COMB_BLOCKS = 2048;
-template <bool F1> constexpr int comb_cz() { return F1 ? 32 : 8; }
+constexpr int CZ = 8;
 
-struct Filt5 { float s0, s0x, s1, s1y, s2; };
-
-template <bool F1>
-__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jin, P3 A, W3 Jd, double* part) {
-  constexpr int CZ = comb_cz<F1>();
+__global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jf, P3 A, W3 Jd, double* part) {
   __shared__ double sh[4];
   const Box& B = a.B;
   const int ncol = B.X * B.Y;
@@ -853,37 +845,9 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jin, P3 A, W3 Jd
     const int x = col % B.X, y = col / B.X;
     const int xm = wrapi(x - 1, B.X), ym = wrapi(y - 1, B.Y);
     const int cx = y * B.X + xm, cy = ym * B.X + x, cxy = ym * B.X + xm;
-    // F1: x-then-y filtered plane z of the five streams, zero outside the box
-    const int xm2 = wrapi(x - 2, B.X), xp = wrapi(x + 1, B.X);
-    const int ym2 = wrapi(y - 2, B.Y), yp = wrapi(y + 1, B.Y);
-    auto rx = [](const float* row, int l, int c, int r) { return 0.25f * row[l] + 0.5f * row[c] + 0.25f * row[r]; };
-    auto ry = [](float m, float c, float p) { return 0.25f * m + 0.5f * c + 0.25f * p; };
-    auto splane = [&](int z, bool only2) {
-      Filt5 o{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-      if (z < 0 || z >= B.Z) return o;
-      const int64_t zo = (int64_t)z * plane;
-      const float* q2 = Jin.p[2] + zo;
-      o.s2 = ry(rx(q2 + ym * B.X, xm, x, xp), rx(q2 + y * B.X, xm, x, xp), rx(q2 + yp * B.X, xm, x, xp));
-      if (only2) return o;
-      const float* q0 = Jin.p[0] + zo;
-      const float *r0m = q0 + ym * B.X, *r0c = q0 + y * B.X, *r0p = q0 + yp * B.X;
-      o.s0 = ry(rx(r0m, xm, x, xp), rx(r0c, xm, x, xp), rx(r0p, xm, x, xp));
-      o.s0x = ry(rx(r0m, xm2, xm, x), rx(r0c, xm2, xm, x), rx(r0p, xm2, xm, x));
-      const float* q1 = Jin.p[1] + zo;
-      const float c1m2 = rx(q1 + ym2 * B.X, xm, x, xp), c1m = rx(q1 + ym * B.X, xm, x, xp);
-      const float c1c = rx(q1 + y * B.X, xm, x, xp), c1p = rx(q1 + yp * B.X, xm, x, xp);
-      o.s1 = ry(c1m, c1c, c1p);
-      o.s1y = ry(c1m2, c1m, c1c);
-      return o;
-    };
-    Filt5 sm{}, sc{};
     // plane z0 - 1 (zero below the box): A_x at (y, x) and (y - 1, x),
     // A_y at (y, x) and (y, x - 1), z-component of the curl and Jf_z
     float pax = 0.0f, paxy = 0.0f, pay = 0.0f, payx = 0.0f, pc2 = 0.0f, pj2 = 0.0f;
-    if (F1) {
-      sm = splane(z0 - 1, false);
-      sc = splane(z0, false);
-    }
     if (z0 > 0) {
       const int64_t o = (z0 - 1) * plane;
       pax = A.p[0][o + col];
@@ -891,8 +855,7 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jin, P3 A, W3 Jd
       pay = A.p[1][o + col];
       payx = A.p[1][o + cx];
       pc2 = a.s * ((pay - payx) * a.ihx - (pax - paxy) * a.ihy);
-      if (F1) pj2 = ry(splane(z0 - 2, true).s2, sm.s2, sc.s2);
-      else pj2 = Jin.p[2][o + col];
+      pj2 = Jf.p[2][o + col];
     }
     const int zend = min(z0 + CZ, B.Z);
     for (int z = z0; z < zend; ++z) {
@@ -900,33 +863,18 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jin, P3 A, W3 Jd
       const float ax = A.p[0][o + col], ay = A.p[1][o + col], az = A.p[2][o + col];
       const float axy = A.p[0][o + cy], ayx = A.p[1][o + cx];
       const float azx = A.p[2][o + cx], azy = A.p[2][o + cy], azxy = A.p[2][o + cxy];
-      float j0, j1, j2, j0x, j1y;
-      if (F1) {
-        const Filt5 sp = splane(z + 1, false);
-        j0 = ry(sm.s0, sc.s0, sp.s0);
-        j1 = ry(sm.s1, sc.s1, sp.s1);
-        j2 = ry(sm.s2, sc.s2, sp.s2);
-        j0x = ry(sm.s0x, sc.s0x, sp.s0x);
-        j1y = ry(sm.s1y, sc.s1y, sp.s1y);
-        sm = sc;
-        sc = sp;
-      } else {
-        j0 = Jin.p[0][o + col];
-        j1 = Jin.p[1][o + col];
-        j2 = Jin.p[2][o + col];
-        j0x = Jin.p[0][o + cx];
-        j1y = Jin.p[1][o + cy];
-      }
       const float c0 = a.s * ((az - azy) * a.ihy - (ay - pay) * a.ih);
       const float c1 = a.s * ((ax - pax) * a.ih - (az - azx) * a.ihx);
       const float c2 = a.s * ((ay - ayx) * a.ihx - (ax - axy) * a.ihy);
       const float c0x = a.s * ((azx - azxy) * a.ihy - (ayx - payx) * a.ih);   // c0 at x - 1
       const float c1y = a.s * ((axy - paxy) * a.ih - (azy - azxy) * a.ihx);   // c1 at y - 1
+      const float j0 = Jf.p[0][o + col], j1 = Jf.p[1][o + col], j2 = Jf.p[2][o + col];
       Jd.p[0][o + col] = j0 + c0;
       Jd.p[1][o + col] = j1 + c1;
       Jd.p[2][o + col] = j2 + c2;
       const double dc = (double)(c0 - c0x) * a.ihx + (double)(c1 - c1y) * a.ihy + (double)(c2 - pc2) * a.ih;
-      const double df = (double)(j0 - j0x) * a.ihx + (double)(j1 - j1y) * a.ihy + (double)(j2 - pj2) * a.ih;
+      const double df = (double)(j0 - Jf.p[0][o + cx]) * a.ihx + (double)(j1 - Jf.p[1][o + cy]) * a.ihy +
+                        (double)(j2 - pj2) * a.ih;
       num += dc * dc;
       den += df * df;
       cc += (double)c0 * c0 + (double)c1 * c1 + (double)c2 * c2;
@@ -937,6 +885,155 @@ __global__ __launch_bounds__(256) void k_combine(CurlArgs a, P3 Jin, P3 A, W3 Jd
       payx = ayx;
       pc2 = c2;
       pj2 = j2;
+    }
+  }
+  double tn = block_sum_d(num, sh);
+  __syncthreads();
+  double td = block_sum_d(den, sh);
+  __syncthreads();
+  double tc = block_sum_d(cc, sh);
+  __syncthreads();
+  double tj = block_sum_d(jj, sh);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x] = tn;
+    part[4 * blockIdx.x + 1] = td;
+    part[4 * blockIdx.x + 2] = tc;
+    part[4 * blockIdx.x + 3] = tj;
+  }
+}
+
+// k_combine with one binomial pass formed inside: the filtered current is
+// computed from the raw one in k_filter's operation order (the same values
+// bit for bit) and never stored.  A work item is a strip of FYS rows
+// (y0 .. y0 + FYS - 1) of one x column through FCZ planes.  Per plane it
+// filters, along x then y, five streams (J_x at x and x - 1, J_y at the rows
+// and the row above, J_z), carried over three planes for the zeta pass; the
+// x-filtered rows of the raw current and A's values at y - 1 are shared by
+// the rows of the strip.  The partial sums are those of k_combine, added in
+// another order.
+constexpr int FCZ = 32;
+template <int FYS>
+__global__ __launch_bounds__(256) void k_combine_f1(CurlArgs a, P3 J, P3 A, W3 Jd, double* part) {
+  __shared__ double sh[4];
+  const Box& B = a.B;
+  const int nstrip = B.X * (B.Y / FYS);
+  const int nwork = nstrip * ((B.Z + FCZ - 1) / FCZ);
+  const int64_t plane = (int64_t)B.Y * B.X;
+  double num = 0.0, den = 0.0, cc = 0.0, jj = 0.0;
+  auto rx = [](const float* row, int l, int c, int r) { return 0.25f * row[l] + 0.5f * row[c] + 0.25f * row[r]; };
+  auto ry = [](float m, float c, float p) { return 0.25f * m + 0.5f * c + 0.25f * p; };
+  // x-then-y filtered plane z: J_x at (y, x) and (y, x - 1), J_y at y - 1 ..
+  // y0 + FYS - 1 (s1[i] at row y0 + i - 1), J_z; zero outside the box
+  struct S {
+    float s0[FYS], s0x[FYS], s1[FYS + 1], s2[FYS];
+  };
+  for (int w = blockIdx.x * 256 + threadIdx.x; w < nwork; w += gridDim.x * 256) {
+    const int st = w % nstrip, z0 = (w / nstrip) * FCZ;
+    const int x = st % B.X, y0 = (st / B.X) * FYS;
+    const int xm = wrapi(x - 1, B.X), xm2 = wrapi(x - 2, B.X), xp = wrapi(x + 1, B.X);
+    int rows[FYS + 3];                      // row offsets of y0 - 2 .. y0 + FYS
+#pragma unroll
+    for (int r = 0; r < FYS + 3; ++r) rows[r] = wrapi(y0 - 2 + r, B.Y) * B.X;
+    auto splane = [&](int z, bool only2) {
+      S o;
+#pragma unroll
+      for (int i = 0; i < FYS; ++i) o.s0[i] = o.s0x[i] = o.s2[i] = 0.0f;
+#pragma unroll
+      for (int i = 0; i <= FYS; ++i) o.s1[i] = 0.0f;
+      if (z < 0 || z >= B.Z) return o;
+      const int64_t zo = (int64_t)z * plane;
+      float r2[FYS + 2];
+#pragma unroll
+      for (int r = 0; r < FYS + 2; ++r) r2[r] = rx(J.p[2] + zo + rows[r + 1], xm, x, xp);
+#pragma unroll
+      for (int i = 0; i < FYS; ++i) o.s2[i] = ry(r2[i], r2[i + 1], r2[i + 2]);
+      if (only2) return o;
+      float r0[FYS + 2], r0x[FYS + 2], r1[FYS + 3];
+#pragma unroll
+      for (int r = 0; r < FYS + 2; ++r) {
+        const float* row = J.p[0] + zo + rows[r + 1];
+        r0[r] = rx(row, xm, x, xp);
+        r0x[r] = rx(row, xm2, xm, x);
+      }
+#pragma unroll
+      for (int r = 0; r < FYS + 3; ++r) r1[r] = rx(J.p[1] + zo + rows[r], xm, x, xp);
+#pragma unroll
+      for (int i = 0; i < FYS; ++i) {
+        o.s0[i] = ry(r0[i], r0[i + 1], r0[i + 2]);
+        o.s0x[i] = ry(r0x[i], r0x[i + 1], r0x[i + 2]);
+      }
+#pragma unroll
+      for (int i = 0; i <= FYS; ++i) o.s1[i] = ry(r1[i], r1[i + 1], r1[i + 2]);
+      return o;
+    };
+    S sm = splane(z0 - 1, false), sc = splane(z0, false);
+    // plane z0 - 1 (zero below the box), per row: A_x at y and y - 1, A_y at
+    // x and x - 1, the z-component of the curl and the filtered J_z
+    float pax[FYS], paxy[FYS], pay[FYS], payx[FYS], pc2[FYS], pj2[FYS];
+#pragma unroll
+    for (int i = 0; i < FYS; ++i) pax[i] = paxy[i] = pay[i] = payx[i] = pc2[i] = pj2[i] = 0.0f;
+    if (z0 > 0) {
+      const int64_t o = (int64_t)(z0 - 1) * plane;
+      const S smm = splane(z0 - 2, true);
+#pragma unroll
+      for (int i = 0; i < FYS; ++i) {
+        const int64_t c = o + rows[i + 2] + x;
+        pax[i] = A.p[0][c];
+        paxy[i] = i ? pax[i - 1] : A.p[0][o + rows[1] + x];
+        pay[i] = A.p[1][c];
+        payx[i] = A.p[1][o + rows[i + 2] + xm];
+        pc2[i] = a.s * ((pay[i] - payx[i]) * a.ihx - (pax[i] - paxy[i]) * a.ihy);
+        pj2[i] = ry(smm.s2[i], sm.s2[i], sc.s2[i]);
+      }
+    }
+    const int zend = min(z0 + FCZ, B.Z);
+    for (int z = z0; z < zend; ++z) {
+      const int64_t o = (int64_t)z * plane;
+      const S sp = splane(z + 1, false);
+      // A at row y0 - 1 (x and x - 1), then row by row
+      float axy = A.p[0][o + rows[1] + x], azy = A.p[2][o + rows[1] + x], azxy = A.p[2][o + rows[1] + xm];
+      float j1y = ry(sm.s1[0], sc.s1[0], sp.s1[0]);
+      float c1y_prev = 0.0f;
+#pragma unroll
+      for (int i = 0; i < FYS; ++i) {
+        const int64_t c = o + rows[i + 2] + x;
+        const float ax = A.p[0][c], ay = A.p[1][c], az = A.p[2][c];
+        const float ayx = A.p[1][c - x + xm], azx = A.p[2][c - x + xm];
+        const float j0 = ry(sm.s0[i], sc.s0[i], sp.s0[i]);
+        const float j1 = ry(sm.s1[i + 1], sc.s1[i + 1], sp.s1[i + 1]);
+        const float j2 = ry(sm.s2[i], sc.s2[i], sp.s2[i]);
+        const float j0x = ry(sm.s0x[i], sc.s0x[i], sp.s0x[i]);
+        const float c0 = a.s * ((az - azy) * a.ihy - (ay - pay[i]) * a.ih);
+        const float c1 = a.s * ((ax - pax[i]) * a.ih - (az - azx) * a.ihx);
+        const float c2 = a.s * ((ay - ayx) * a.ihx - (ax - axy) * a.ihy);
+        const float c0x = a.s * ((azx - azxy) * a.ihy - (ayx - payx[i]) * a.ih);   // c0 at x - 1
+        // c1 at y - 1: the row above's c1, or (first row) from row y0 - 1
+        const float c1y = i ? c1y_prev : a.s * ((axy - paxy[i]) * a.ih - (azy - azxy) * a.ihx);
+        Jd.p[0][c] = j0 + c0;
+        Jd.p[1][c] = j1 + c1;
+        Jd.p[2][c] = j2 + c2;
+        const double dc = (double)(c0 - c0x) * a.ihx + (double)(c1 - c1y) * a.ihy + (double)(c2 - pc2[i]) * a.ih;
+        const double df = (double)(j0 - j0x) * a.ihx + (double)(j1 - j1y) * a.ihy + (double)(j2 - pj2[i]) * a.ih;
+        num += dc * dc;
+        den += df * df;
+        cc += (double)c0 * c0 + (double)c1 * c1 + (double)c2 * c2;
+        jj += (double)j0 * j0 + (double)j1 * j1 + (double)j2 * j2;
+        // carried to the next plane (z; axy still holds A_x of the row
+        // above) and to the next row (y)
+        paxy[i] = axy;
+        pax[i] = ax;
+        pay[i] = ay;
+        payx[i] = ayx;
+        pc2[i] = c2;
+        pj2[i] = j2;
+        axy = ax;
+        azy = az;
+        azxy = azx;
+        j1y = j1;
+        c1y_prev = c1;
+      }
+      sm = sc;
+      sc = sp;
     }
   }
   double tn = block_sum_d(num, sh);
@@ -1124,7 +1221,6 @@ static int dn_fail(gempic_dn* d, int code, const std::string& m) {
 static int check_box(gempic_dn* d, int Z, int Y, int X) {
   if (Z < 1 || Y < TY || X < TX || Y % TY || X % TX)
     return dn_fail(d, GEMPIC_EINVAL, "box must have Z >= 1, Y a multiple of 8 and X a multiple of 16");
-  constexpr int CZ = comb_cz<false>();   // the shorter columns: the larger work count
   if ((int64_t)X * Y * ((Z + CZ - 1) / CZ) >= (int64_t(1) << 31) - (int64_t(COMB_BLOCKS) << 8))
     return dn_fail(d, GEMPIC_EINVAL, "box too large for the denoiser: X * Y * ceil(Z / 8) must stay below 2^31");
   return GEMPIC_OK;
@@ -1288,11 +1384,11 @@ static int dn_step_ws(gempic_dn* d, hipStream_t s, int Z, int Y, int X, const fl
   net_forward(d, s, Z, Y, X, J, (float)(1.0 / n_e), w.act, Ap);
   CurlArgs c = curl_args(Z, Y, X, n_e, hs);
   if (f1)
-    k_combine<true><<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{J[0], J[1], J[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+    k_combine_f1<2><<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{J[0], J[1], J[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
                                                 W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
   else
-    k_combine<false><<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
-                                                 W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
+    k_combine<<<COMB_BLOCKS, 256, 0, s>>>(c, P3{{Jf[0], Jf[1], Jf[2]}}, P3{{Ap[0], Ap[1], Ap[2]}},
+                                          W3{{Jd[0], Jd[1], Jd[2]}}, w.part);
   k_decide<<<1, 256, 0, s>>>(w.part, COMB_BLOCKS, thr, w.use_net, rel ? rel : w.rel,
                              fallbacks ? fallbacks : d->fallbacks);
   if (f1) {
