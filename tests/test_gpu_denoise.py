@@ -48,8 +48,11 @@ def _dev(a):
 
 
 # (37, 24, 80): a 32-plane column of the fused filter and combine and a
-# ragged second one, x wider than a wavefront
-@pytest.mark.parametrize("shape", [(10, 16, 32), (4, 8, 16), (1, 8, 16), (37, 24, 80)])
+# ragged second one, x wider than a wavefront.  (80, 64, 64): 640 tiles of
+# 4 x 8 x 16, at least one whole grid of persistent work-groups (a multiple
+# of 8 on this chip), so the convolutions take the XCD-aware tile walk, with
+# a ragged second round where the grid holds fewer than 640 work-groups
+@pytest.mark.parametrize("shape", [(10, 16, 32), (4, 8, 16), (1, 8, 16), (37, 24, 80), (80, 64, 64)])
 def test_forward_matches_oracle(shape):
     # last layer scaled so that the correction stays below the filtered
     # current (the size criterion of the fallback test keeps it)
