@@ -256,8 +256,9 @@ def bench_march(stream, steps=5, cpu=True):
     return out, med
 
 
-def bench_denoise(stream, steps=8):
-    """1 ppc + the committed network against 16 ppc on the LWFA physics."""
+def bench_denoise(stream, steps=16):
+    """1 ppc + the committed network against 16 ppc on the LWFA physics: median
+    whole-step times over `steps` steps after 3 warm-up steps."""
     import numpy as np
     import workloads
     from paper_2509_16793_amd.gempic import Denoiser, Sim
