@@ -46,7 +46,7 @@ METRIC = "particle updates/s (gather+push+deposit), % HBM roofline; 1ppc+CNN vs 
 # HBM bytes per k_push_deposit launch from rocprofv3 FETCH_SIZE / WRITE_SIZE on this
 # workload, scaled by a plain-copy calibration (profiles/k_push_deposit_lwfa3d_*.md);
 # valid only for the kernel source it was measured on.
-MEASURED_TRAFFIC = {"push_h_sha256_prefix": "383780be9f5cf20b", "bytes_per_launch": 5.753e+09}
+MEASURED_TRAFFIC = {"push_h_sha256_prefix": "632fbbfc27b15b7e", "bytes_per_launch": 5.740e+09}
 HBM_PEAK_GBS = 8000.0
 WORKLOAD_TEXT = {
     "lwfa": "lwfa3d_fp32: 3-D LWFA 256x256x512, dx=dy=0.4, dzeta=0.05 (lambda_L), n_e=0.001 n_c, "

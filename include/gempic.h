@@ -270,6 +270,21 @@ int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes);
 int gempic_timing(gempic_t* g, int32_t enable);
 int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps);
 
+/* Deterministic deposit (tau scheme, FP32 modes, no driver beam; for tests
+ * and reproducible runs).  The charge-conserving current of Sec. 5.1 is
+ * summed per tile in 64-bit fixed point in either mode; by default each tile
+ * then adds its FP32 values to the global current with floating-point
+ * atomics, so a node that up to four tiles reach depends on their order in
+ * its last bits.  With on = 1 the tiles add their fixed-point sums to 64-bit
+ * integer arrays (3 x 8 bytes per node, allocated at the first call and held
+ * until gempic_destroy) and one pass converts them: the current, and so every
+ * later field and particle, is then the same bit for bit from run to run.
+ * It costs integer atomics and a conversion pass per step.  on = 0 returns to
+ * the default.  The charge arrays of deposit_rho keep FP32 atomics.
+ * GEMPIC_EINVAL for the zeta march, FP64, or a driver beam; GEMPIC_ENOMEM
+ * when the arrays cannot be allocated. */
+int gempic_set_deterministic(gempic_t* g, int32_t on);
+
 /* Witness-bunch diagnostics in the style of Table 1 (Sec. 6): over the
  * macro-particles with gamma >= gamma_min, weighted by their electrons w,
  * the charge q sum w, the mean and rms of gamma (energy gamma m c^2), the

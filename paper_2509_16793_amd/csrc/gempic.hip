@@ -99,6 +99,9 @@ struct gempic {
   void* Jt[3];
   int64_t* dn_fallbacks;
   double* dn_rel;
+  // deterministic deposit (FP32, tau scheme): 64-bit fixed-point current sums
+  bool det;
+  void* Jfix[3];
   // zeta march (scheme 1 = GT1, 2 = GT2)
   int scheme;
   double Delta;                 // slow step of the next step (normalised)
@@ -457,6 +460,7 @@ struct Impl {
     a.g = G;
     a.F6 = (const T*)g->F6;
     for (int q = 0; q < 3; ++q) a.J[q] = (T*)g->J[q];
+    for (int q = 0; q < 3; ++q) a.Jfix[q] = (unsigned long long*)g->Jfix[q];
     a.rho0 = g->cfg.deposit_rho ? (T*)g->rho[0] : nullptr;
     a.rho1 = g->cfg.deposit_rho ? (T*)g->rho[1] : nullptr;
     double q = -1.0;
@@ -536,6 +540,19 @@ struct Impl {
   static void push_tile(gempic* g, const PushArgs<T>& a, PartPtrs<T> P, bool rho) {
     unsigned nb = push_blocks(a);
     constexpr int NTHR = TZ == 8 ? 512 : 256;
+    if constexpr (std::is_same<T, float>::value) {
+      if (g->det) {   // no driver beam (rejected when the mode is set)
+        constexpr bool A3 = DIM == 3;   // absolute positions: 3-D only
+        if (A3 && g->g.abs_pos) {
+          if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, false, A3, true><<<nb, NTHR, 0, g->s>>>(a, P);
+          else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, false, A3, true><<<nb, NTHR, 0, g->s>>>(a, P);
+        } else {
+          if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, false, false, true><<<nb, NTHR, 0, g->s>>>(a, P);
+          else k_push_deposit<T, DIM, false, TX, TY, TZ, NTHR, false, false, true><<<nb, NTHR, 0, g->s>>>(a, P);
+        }
+        return;
+      }
+    }
     if constexpr (DIM == 3) {
       if (g->cfg.beam_np > 0) {
         if (rho) k_push_deposit<T, DIM, true, TX, TY, TZ, NTHR, true, false><<<nb, NTHR, 0, g->s>>>(a, P);
@@ -587,11 +604,25 @@ struct Impl {
     int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
     int rc = mark(g, 0);
     if (rc) return rc;
-    for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
+    if (g->det) {
+      // the conversion below writes every node of J
+      for (int q = 0; q < 3; ++q)
+        k_fill<int64_t><<<nblk(nJ, 256), 256, 0, g->s>>>((int64_t*)g->Jfix[q], nJ, 0);
+    } else {
+      for (int q = 0; q < 3; ++q) fill(g, g->J[q], nJ);
+    }
     if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
     if ((rc = launch_check(g, "clearing the current"))) return rc;
     if ((rc = mark(g, 1))) return rc;
     launch_push(g);
+    if constexpr (std::is_same<T, float>::value) {
+      if (g->det) {
+        const PushArgs<T> a = push_args(g);
+        for (int q = 0; q < 3; ++q)
+          k_fix_to_float<<<nblk(nJ, 256), 256, 0, g->s>>>((const unsigned long long*)g->Jfix[q], (float*)g->J[q],
+                                                          nJ, a.finv);
+      }
+    }
     if ((rc = launch_check(g, "push and deposit"))) return rc;
     if ((rc = mark(g, 2))) return rc;
     (void)hipMemcpyAsync(g->pushed, g->total, 8, hipMemcpyDeviceToDevice, g->s);
@@ -1837,6 +1868,28 @@ int gempic_set_fields(gempic_t* g, const void* fields, size_t bytes) {
       k_interleave<float><<<nblk(nf, 256), 256, 0, g->s>>>((float*)g->F6, (const float*)g->outs[0], q, nf);
   }
   HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
+int gempic_set_deterministic(gempic_t* g, int32_t on) {
+  if (!g) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  if (!on) { g->det = false; return GEMPIC_OK; }
+  if (g->scheme) return fail(g, GEMPIC_EINVAL, "the deterministic deposit serves the tau scheme");
+  if (g->prec != 1)
+    return fail(g, GEMPIC_EINVAL, "the deterministic deposit needs an FP32 mode (FP64 tiles sum in FP64 atomics)");
+  if (g->cfg.beam_np > 0) return fail(g, GEMPIC_EINVAL, "the deterministic deposit does not take a driver beam");
+  const Geom& G = g->g;
+  int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
+  if (!g->Jfix[0]) {
+    bool ok = true;
+    for (int q = 0; q < 3; ++q) {
+      g->Jfix[q] = g->dev.alloc(nJ * 8);
+      ok = ok && g->Jfix[q];
+    }
+    if (!ok) return fail(g, GEMPIC_ENOMEM, "deterministic current buffers");
+  }
+  g->det = true;
   return GEMPIC_OK;
 }
 

@@ -49,6 +49,7 @@ struct PushArgs {
   const int64_t* tile_base;   // [NT] first particle of each tile
   const int64_t* tile_count;  // [NT] particles of each tile
   const int64_t* total;       // particles in the buffer (0 after a capacity overflow)
+  unsigned long long* Jfix[3]; // deterministic FP32 flush: 64-bit fixed-point current sums
   int seg_len;                // zeta tiles per work-group segment
   int nseg;                   // segments per column
   int* err;
@@ -79,6 +80,13 @@ template <> struct Fix<float> {
     return hi * 4294967296.0f + lo;
   }
 };
+// deterministic deposit: the 64-bit fixed-point node sums of one current
+// component to FP32, converted as the ordinary flush converts a tile's sums
+__global__ void k_fix_to_float(const unsigned long long* fix, float* J, int64_t n, float finv) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    J[i] = Fix<float>::value(fix[i]) * finv;
+}
+
 template <> struct Fix<double> {
   // FP64 (the parity mode): native FP64 LDS atomics, no range limit
   using t = double;
@@ -168,8 +176,13 @@ GP_DEV PLoad<T> load_row(const PartPtrs<T>& P, int base, int n, unsigned lane) {
 // ABS: particles hold absolute FP32 positions; cells and offsets are decoded
 // from them (abs_cell), the move adds v dtau to the position in FP32 (periodic
 // wrap transversally) and the new cell and offset are decoded again.
-template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR, bool SPEC, bool ABS>
+// DET (FP32 only): the flush adds the tile's exact fixed-point sums to the
+// 64-bit integer arrays Jfix with integer atomics instead of adding their
+// FP32 values to J, so that no summation order reaches the current; a later
+// pass converts Jfix to J.
+template <typename T, int DIM, bool RHO, int TX, int TY, int TZ, int NTHR, bool SPEC, bool ABS, bool DET = false>
 __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T> P) {
+  static_assert(!DET || std::is_same<T, float>::value, "the deterministic flush needs the fixed-point tile");
   constexpr int FX = TX + 1, FY = DIM == 3 ? TY + 1 : 1, FZ = TZ + 1;
   constexpr int FN = FX * FY * FZ;
   // current tile: J_x and J_y on planes 1 .. JZ-1, J_z on planes 0 .. JZ-1
@@ -663,8 +676,12 @@ __global__ __launch_bounds__(NTHR) void k_push_deposit(PushArgs<T> a, PartPtrs<T
         auto put = [&](A iv, int jz) {
           const int plane = z0 + jz;
           if (iv != (A)0 && plane < g.NPJ) {
-            char* base = reinterpret_cast<char*>(dq + (int64_t)plane * plane_stride);
-            atomicAdd(reinterpret_cast<T*>(base + boff), Fix<T>::value(iv) * a.finv);
+            if constexpr (DET) {
+              atomicAdd(a.Jfix[q] + (int64_t)plane * plane_stride + boff / (unsigned)sizeof(T), iv);
+            } else {
+              char* base = reinterpret_cast<char*>(dq + (int64_t)plane * plane_stride);
+              atomicAdd(reinterpret_cast<T*>(base + boff), Fix<T>::value(iv) * a.finv);
+            }
           }
         };
         // a slab's planes below TZ + first are final: the next tile's deposits

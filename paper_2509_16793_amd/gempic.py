@@ -89,6 +89,7 @@ _SIGS = {
     "gempic_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
     "gempic_set_slow_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "gempic_set_deterministic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "gempic_bunch_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(gempic_bunch)]),
     "gempic_march_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -360,6 +361,12 @@ class Sim:
     def set_slow_step(self, delta):
         """Zeta march: slow step of the following steps (config units)."""
         _check(lib().gempic_set_slow_step(self.h, float(delta)), self.h)
+
+    def set_deterministic(self, on=True):
+        """Deterministic deposit (tau scheme, FP32, no driver beam): the current
+        summed in 64-bit fixed point across tiles, the same bit for bit from
+        run to run."""
+        _check(lib().gempic_set_deterministic(self.h, 1 if on else 0), self.h)
 
     def set_denoiser(self, dn, threshold=1e-3):
         """Attach a Denoiser (None detaches); the Denoiser must outlive it."""

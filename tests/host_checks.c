@@ -105,6 +105,7 @@ int main(void) {
   expect(gempic_step(NULL, 1, NULL) == GEMPIC_EINVAL, "step without handle");
   expect(gempic_fields_bytes(NULL, ~0u) == 0, "fields_bytes without handle");
   expect(gempic_timing(NULL, 1) == GEMPIC_EINVAL, "timing without handle");
+  expect(gempic_set_deterministic(NULL, 1) == GEMPIC_EINVAL, "deterministic deposit without handle");
   {
     double ms[5];
     expect(gempic_get_timing(NULL, ms, NULL) == GEMPIC_EINVAL, "get_timing without handle");
