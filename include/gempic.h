@@ -270,6 +270,13 @@ int gempic_get_spectral(gempic_t* g, void* spectral, size_t spectral_bytes);
 int gempic_timing(gempic_t* g, int32_t enable);
 int gempic_get_timing(gempic_t* g, double* ms, int64_t* steps);
 
+/* On-axis field (FP64 diagnostics; the wake's E_z is the quantity that Sec. 6
+ * and the denoiser's accuracy measure): component (0 .. 5 = Ex, Ey, Ez, Bx,
+ * By, Bz) at the node column (Nx/2, Ny/2) (2-D: Nx/2), for the zeta planes
+ * 0 .. Nz - 1, converted to FP64 into the caller's host buffer dst[n].
+ * GEMPIC_EINVAL for another component or n < Nz.  Synchronises the stream. */
+int gempic_axis_field(gempic_t* g, int32_t component, double* dst, size_t n);
+
 /* Deterministic deposit (tau scheme, FP32 modes, no driver beam; for tests
  * and reproducible runs).  The charge-conserving current of Sec. 5.1 is
  * summed per tile in 64-bit fixed point in either mode; by default each tile

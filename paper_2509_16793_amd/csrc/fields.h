@@ -442,6 +442,13 @@ __global__ void k_deinterleave(const T* rec, T* out, int q, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = rec[6 * i + q];
 }
+// Component q of the node records along the column (iy, ix), every zeta
+// plane, in FP64.
+template <typename T>
+__global__ void k_axis(const T* rec, double* out, int q, int Nz, int64_t plane, int64_t col) {
+  int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < Nz) out[z] = (double)rec[6 * (z * plane + col) + q];
+}
 template <typename T>
 __global__ void k_interleave(T* rec, const T* in, int q, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

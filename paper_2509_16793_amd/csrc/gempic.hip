@@ -1645,6 +1645,25 @@ int gempic_fields(gempic_t* g, uint32_t mask, int32_t on_device, void* dst, size
   return GEMPIC_OK;
 }
 
+int gempic_axis_field(gempic_t* g, int32_t component, double* dst, size_t n) {
+  if (!g || !dst) return GEMPIC_EINVAL;
+  if (g->failed) return fail(g, GEMPIC_ESTATE, "handle failed earlier: " + g->err);
+  if (component < 0 || component > 5) return fail(g, GEMPIC_EINVAL, "component must be 0 .. 5 (Ex .. Bz)");
+  const Geom& G = g->g;
+  if (n < (size_t)G.Nz) return fail(g, GEMPIC_EINVAL, "n smaller than the zeta planes");
+  // outs[0] (Nz Ny Nx elements of the mode's precision) holds the Nz doubles
+  const int64_t plane = (int64_t)G.Ny * G.Nx, col = (int64_t)(G.Ny / 2) * G.Nx + G.Nx / 2;
+  double* tmp = (double*)g->outs[0];
+  if (g->prec == 0)
+    k_axis<double><<<nblk(G.Nz, 256), 256, 0, g->s>>>((const double*)g->F6, tmp, component, G.Nz, plane, col);
+  else
+    k_axis<float><<<nblk(G.Nz, 256), 256, 0, g->s>>>((const float*)g->F6, tmp, component, G.Nz, plane, col);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipMemcpyAsync(dst, tmp, (size_t)G.Nz * 8, hipMemcpyDeviceToHost, g->s));
+  HIPCHK(g, hipStreamSynchronize(g->s));
+  return GEMPIC_OK;
+}
+
 static int march_particles(gempic_t* g, int32_t on_device, int32_t* cell, void* off, void* u, int64_t* id,
                            void* w, void* b, size_t capacity, size_t* count) {
   int n = 0;

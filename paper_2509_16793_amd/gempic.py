@@ -90,6 +90,8 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_int64)]),
     "gempic_set_slow_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "gempic_set_deterministic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "gempic_axis_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_size_t]),
     "gempic_bunch_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(gempic_bunch)]),
     "gempic_march_particles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -361,6 +363,15 @@ class Sim:
     def set_slow_step(self, delta):
         """Zeta march: slow step of the following steps (config units)."""
         _check(lib().gempic_set_slow_step(self.h, float(delta)), self.h)
+
+    def axis_field(self, name="Ez"):
+        """FP64 copy of one E or B component along the axis node column
+        (Nx/2, Ny/2), one value per zeta plane."""
+        import numpy as np
+        out = np.empty(self.Nz, np.float64)
+        _check(lib().gempic_axis_field(self.h, FIELD_NAMES.index(name), out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), out.size), self.h)
+        return out
 
     def set_deterministic(self, on=True):
         """Deterministic deposit (tau scheme, FP32, no driver beam): the current

@@ -107,6 +107,10 @@ int main(void) {
   expect(gempic_timing(NULL, 1) == GEMPIC_EINVAL, "timing without handle");
   expect(gempic_set_deterministic(NULL, 1) == GEMPIC_EINVAL, "deterministic deposit without handle");
   {
+    double axis[4];
+    expect(gempic_axis_field(NULL, 2, axis, 4) == GEMPIC_EINVAL, "axis field without handle");
+  }
+  {
     double ms[5];
     expect(gempic_get_timing(NULL, ms, NULL) == GEMPIC_EINVAL, "get_timing without handle");
   }
