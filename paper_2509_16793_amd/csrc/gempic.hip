@@ -1,4 +1,5 @@
 // Host driver and C ABI of the gfx950 Galilean PIC library (see include/gempic.h).
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +21,40 @@
 namespace {
 
 thread_local std::string g_create_error;
+
+// roctx ranges around the phases of a step, so that rocprofv3 (--marker-trace,
+// or --kernel-rename to name each kernel after its phase) attributes the
+// kernels.  The roctx library is opened at run time; without it a range does
+// nothing.  Ranges are host-side: they bracket the enqueueing of a phase.
+struct RoctxLib {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+  RoctxLib() {
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr;
+  }
+};
+const RoctxLib& roctx() {
+  static const RoctxLib lib;
+  return lib;
+}
+struct Range {
+  const bool on;
+  explicit Range(const char* name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name);
+  }
+  void next(const char* name) {
+    if (!on) return;
+    roctx().pop();
+    roctx().push(name);
+  }
+  ~Range() {
+    if (on) roctx().pop();
+  }
+};
 
 struct Dev {
   std::vector<void*> ptrs;
@@ -604,6 +639,7 @@ struct Impl {
     int64_t nJ = (int64_t)G.NPJ * G.Ny * G.Nx;
     int rc = mark(g, 0);
     if (rc) return rc;
+    Range range("gempic.clear");
     if (g->det) {
       // the conversion below writes every node of J
       for (int q = 0; q < 3; ++q)
@@ -614,6 +650,7 @@ struct Impl {
     if (g->cfg.deposit_rho) { fill(g, g->rho[0], nJ); fill(g, g->rho[1], nJ); }
     if ((rc = launch_check(g, "clearing the current"))) return rc;
     if ((rc = mark(g, 1))) return rc;
+    range.next("gempic.push_deposit");
     launch_push(g);
     if constexpr (std::is_same<T, float>::value) {
       if (g->det) {
@@ -625,12 +662,14 @@ struct Impl {
     }
     if ((rc = launch_check(g, "push and deposit"))) return rc;
     if ((rc = mark(g, 2))) return rc;
+    range.next("gempic.sort_window");
     (void)hipMemcpyAsync(g->pushed, g->total, 8, hipMemcpyDeviceToDevice, g->s);
     rc = sort_and_inject(g, g->step + 1);
     if (rc) return rc;
     if ((rc = launch_check(g, "sort and window"))) return rc;
     if ((rc = mark(g, 3))) return rc;
     if (g->dn) {
+      range.next("gempic.denoise");
       if (sizeof(T) != 4) return fail(g, GEMPIC_EINVAL, "denoiser needs FP32");
       const double hs[3] = {G.hx, G.hy, G.h};
       const float* J[3] = {(const float*)g->J[0], (const float*)g->J[1], (const float*)g->J[2]};
@@ -641,6 +680,7 @@ struct Impl {
                    g->dn_fallbacks, g->dn_rel);
       if (rc) return fail(g, rc, std::string("denoiser: ") + dn_error(g->dn));
     }
+    range.next("gempic.fields");
     field_update(g, true, (T)G.dtau);
     if ((rc = launch_check(g, "field update"))) return rc;
     if ((rc = mark(g, 4))) return rc;
@@ -961,6 +1001,7 @@ struct Impl {
   // of zero slow step, one fresh batch pushed through and discarded, nothing
   // advanced
   static int mz_step(gempic* g, bool startup = false) {
+    Range range(startup ? "gempic.zeta_march_startup" : "gempic.zeta_march_step");
     const Geom& G = g->g;
     const int Nz = G.Nz;
     const int64_t M = (int64_t)G.Ny * G.Nxh;
