@@ -17,7 +17,8 @@ algorithmic bytes (2 x 28 B particle state, 24 B of fields and 12 B of current
 per cell) per launch over its median duration, against 8 TB/s.
 cpu_baseline = the FP64 CPU oracle's gather + push + deposit on bounded
 transverse crops of the same workload, on every host core (one crop per
-process) and on one core.
+process) and on one core; and, as lwfa2d_full_step, the small 2-D FP64 case
+run in full (100 whole steps) on the GPU and by the oracle on one core.
 
 Extra objects on the same line:
   march   -- the paper's own slow step (the zeta march, GT1) on the same
@@ -138,6 +139,36 @@ def cpu_baseline(workload="lwfa"):
                       f"core (slowest process's compute time); wall {wall:.1f} s with start-up",
             "single_thread": {"value": one_done / one_s, "cores": 1, "seconds": one_s},
             "host_cpu": model, "os_cpu_count": os.cpu_count()}
+
+
+def full_step_2d(stream, steps=100, warmup=5):
+    """The small 2-D (x, zeta) LWFA case in full (64 x 256 cells, 2 ppc, FP64,
+    100 steps): wall time per whole step (gather, push, deposit, sort,
+    window, field update) on the GPU and of the FP64 oracle on one host core,
+    on the same configuration."""
+    import torch
+    import workloads
+    from oracle.sim import Simulation
+    from paper_2509_16793_amd.gempic import Sim
+    cfg = workloads.lwfa2d_fp64()
+    g = Sim(cfg, stream=stream)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    n = g._count()
+    g.close()
+    o = Simulation(cfg)
+    o.run(warmup)
+    t0 = time.perf_counter()
+    o.run(steps)
+    cpu_s = time.perf_counter() - t0
+    return {"workload": "lwfa2d_fp64: 2-D LWFA 64x256, dx=0.25, dzeta=0.05, n_e=0.01 n_c, 2 ppc, a0=1, "
+                        "FP64, whole step", "steps": steps, "particles": n,
+            "gpu_ms_per_step": 1e3 * gpu_s / steps, "oracle_ms_per_step": 1e3 * cpu_s / steps,
+            "oracle_cores": 1}
 
 
 def _oracle_march_crop(args):
@@ -405,6 +436,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on crops", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
+        if args.workload == "lwfa":
+            print("[bench] the 2-D case in full, GPU and oracle", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["lwfa2d_full_step"] = full_step_2d(stream)
     print(json.dumps(out), flush=True)
 
 
