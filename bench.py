@@ -14,7 +14,10 @@ gather + push + deposit kernel: particles over the median of its per-step
 durations (HIP events on the stream the library runs on); ms_per_step = wall
 time per whole step over the timed region.  roofline = that kernel's
 algorithmic bytes (2 x 28 B particle state, 24 B of fields and 12 B of current
-per cell) per launch over its median duration, against 8 TB/s.
+per cell) per launch over its median duration, against 8 TB/s; traffic = the
+HBM bytes per launch that rocprofv3 counted on this kernel source (null for
+another source), and traffic_achieved / traffic_frac = those over the same
+median duration.
 cpu_baseline = the FP64 CPU oracle's gather + push + deposit on bounded
 transverse crops of the same workload, on every host core (one crop per
 process) and on one core; and, as lwfa2d_full_step, the small 2-D FP64 case
@@ -416,6 +419,8 @@ def main():
                    "grid": cfg["n"], "ppc": ppc, "particles": int(n_avg)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_achieved": traffic / launch_s / 1e9 if traffic else None,
+                     "traffic_frac": traffic / launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
                      "kernel": "k_push_deposit", "bytes_per_update": bpu,
                      "median_launch_ms": launch_s * 1e3,
                      "mean_launch_ms": statistics.fmean(r["push_deposit"] for r in rows)},
