@@ -8,7 +8,7 @@ order; the deterministic mode adds the integer sums instead and converts once.
 Checked on the small 3-D LWFA case (32 x 32 x 64 cells, a laser that moves
 particles across cells):
   * two runs agree bit for bit after 8 steps (current, fields, particles), in
-    both FP32 modes;
+    both FP32 modes, and at the benchmark size after 5 steps (current, E_z);
   * the deterministic fields agree with the atomic ones within the FP32 field
     bar, and its current is no farther from the FP64 oracle than the atomic
     one (the exact integer sums round once, the atomic path once per tile);
@@ -47,6 +47,20 @@ def test_two_runs_agree_bit_for_bit(prec):
         assert np.array_equal(F1[k].view(np.uint32), F2[k].view(np.uint32)), k
     for k in P1:
         assert np.array_equal(P1[k], P2[k]), k
+
+
+def test_full_size_runs_repeat_bit_for_bit():
+    """The benchmark workload (256 x 256 x 512 cells, 2 ppc, 131,072 tiles):
+    two runs of 5 steps give the same current and E_z bit for bit."""
+    out = []
+    for _ in range(2):
+        g = Sim(workloads.lwfa3d_fp32())
+        g.set_deterministic(True)
+        g.step(5)
+        out.append(g.fields(("Jx", "Jy", "Jz", "Ez")))
+        g.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k].view(np.uint32), out[1][k].view(np.uint32)), k
 
 
 def test_deterministic_and_atomic_agree_to_roundoff():
