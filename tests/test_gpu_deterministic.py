@@ -63,6 +63,26 @@ def test_full_size_runs_repeat_bit_for_bit():
         assert np.array_equal(out[0][k].view(np.uint32), out[1][k].view(np.uint32)), k
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32abs"])
+def test_with_the_charge_deposit(prec):
+    """deposit_rho = 1 (the instantiation that also deposits the charge, which
+    keeps FP32 atomics): the current still repeats bit for bit, and the
+    discrete continuity residual of the step stays at the atomic mode's level
+    (FP32 roundoff; below 1e-4 as the absolute-position test requires)."""
+    cont, J = {}, []
+    for det in (True, True, False):
+        g = Sim(workloads.small3d(prec), deposit_rho=True)
+        g.set_deterministic(det)
+        dg = g.step(4, diag=True)
+        cont[det] = dg["continuity_rel"]
+        if det:
+            J.append(g.fields(("Jx", "Jy", "Jz")))
+        g.close()
+    for k in J[0]:
+        assert np.array_equal(J[0][k].view(np.uint32), J[1][k].view(np.uint32)), k
+    assert cont[True] < 1e-4 and cont[True] <= 2.0 * cont[False] + 1e-7, cont
+
+
 def test_deterministic_and_atomic_agree_to_roundoff():
     """The two modes' fields agree within the FP32 field bar, and each current
     component of the deterministic run is no farther from the FP64 oracle than
