@@ -8,7 +8,8 @@ order; the deterministic mode adds the integer sums instead and converts once.
 Checked on the small 3-D LWFA case (32 x 32 x 64 cells, a laser that moves
 particles across cells):
   * two runs agree bit for bit after 8 steps (current, fields, particles), in
-    both FP32 modes, and at the benchmark size after 5 steps (current, E_z);
+    both FP32 modes, in 2-D, and at the benchmark size after 5 steps
+    (current, E_z);
   * the deterministic fields agree with the atomic ones within the FP32 field
     bar, and its current is no farther from the FP64 oracle than the atomic
     one (the exact integer sums round once, the atomic path once per tile);
@@ -29,7 +30,8 @@ NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz")
 
 
 def _run(prec, det, steps=8):
-    g = Sim(workloads.small3d(prec), track_ids=True)
+    cfg = dict(workloads.lwfa2d_fp64(), precision="fp32") if prec == "2d-fp32" else workloads.small3d(prec)
+    g = Sim(cfg, track_ids=True)
     if det:
         g.set_deterministic(True)
     g.step(steps)
@@ -39,7 +41,7 @@ def _run(prec, det, steps=8):
     return F, P
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp32abs"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32abs", "2d-fp32"])
 def test_two_runs_agree_bit_for_bit(prec):
     F1, P1 = _run(prec, True)
     F2, P2 = _run(prec, True)
