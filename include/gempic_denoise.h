@@ -21,7 +21,7 @@
  * falls back to F(J_raw) when rel exceeds a threshold or is not finite.
  * D.curl vanishes identically, so for a finite network output rel is FP32
  * rounding: this test is a finiteness guard.  The filtered current also
- * judges the network's size: the step falls back as well when
+ * bounds the network's correction: the step falls back as well when
  * ||s curl(A)|| > ||F(J_raw)||, a correction larger than the current it
  * corrects, which catches a finite but wrong output.
  * F is one (or two) 1-2-1 passes along x, y (periodic) and zeta (zero

@@ -1056,8 +1056,8 @@ __global__ __launch_bounds__(256) void k_combine_f1(CurlArgs a, P3 J, P3 A, W3 J
 //  - continuity: ||D.(s curl A)|| / ||D.Jf|| <= thr.  D.curl vanishes
 //    identically, so for a finite A this ratio is FP32 rounding; it rejects a
 //    non-finite output (a finiteness guard), not a wrong one;
-//  - size: ||s curl A|| <= DN_CORR_MAX ||Jf||.  The filtered current judges
-//    the network: a correction larger than the current it corrects is taken
+//  - size: ||s curl A|| <= DN_CORR_MAX ||Jf||.  The filtered current is the
+//    yardstick: a correction larger than the current it corrects is taken
 //    as the network's failure (a finite but wrong output).
 constexpr double DN_CORR_MAX = 1.0;
 __global__ __launch_bounds__(256) void k_decide(const double* part, int nparts, double thr, int* use_net,
