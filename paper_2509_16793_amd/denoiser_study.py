@@ -124,10 +124,8 @@ def plain_loss(X, T, n_e, h, n=64, rng=None):
 
 
 def on_axis_ez(sim):
-    torch = _ctx()
-    ez = torch.empty((1, sim.Nz, sim.Ny, sim.Nx), dtype=torch.float32, device="cuda")
-    sim.fields_device(("Ez",), ez)
-    return ez[0, :, sim.Ny // 2, sim.Nx // 2].double().cpu().numpy()
+    """E_z along the axis node column (Nx/2, Ny/2), FP64, one value per plane."""
+    return sim.axis_field("Ez")
 
 
 def run_timed(sim, nsteps):
